@@ -1,0 +1,239 @@
+"""FP64 CPU oracle of the local spline simulator (arXiv 2301.05127).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py``; never by the product package.  It shares no code
+with the HIP library.  The arithmetic lives in ``loss_oracle.c`` (plain C, double
+precision); this module only marshals numpy arrays through ctypes.
+
+Grids are plain dicts: ``{"ndim": 2|3, "n": (nx, ny, nz) intervals, "h": (hx, hy, hz),
+"M": (Mx, My, Mz) patch intervals, "halo": n_nb, "end_mode": 0|1|2}``; for a 2-D grid
+``n[1] == 0``.  Fields are numpy arrays of shape ``(nz+1, ny+1, nx+1)`` (3-D) or
+``(nz+1, nx+1)`` (2-D), x fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "loss_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liblossoracle.so")
+
+END_NATURAL, END_PAPER_STENCIL, END_PERIODIC = 0, 1, 2
+ACOUSTIC, ELASTIC = 0, 1
+SRC_PRESSURE, SRC_EXPLOSIVE, SRC_FORCE_X, SRC_FORCE_Y, SRC_FORCE_Z = 0, 1, 2, 3, 4
+A_SIGMA, A_V1, A_V3 = 0, 1, 2
+E_V1, E_V2, E_V3, E_S11, E_S22, E_S33, E_S12, E_S13, E_S23 = range(9)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc into an in-tree shared library."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "loss_oracle.h"))
+    ):
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double * 3),
+                ("M", ctypes.c_int * 3), ("halo", ctypes.c_int), ("end_mode", ctypes.c_int)]
+
+
+class _Source(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("pos", ctypes.c_double * 3), ("spread", ctypes.c_double),
+                ("wavelet", ctypes.POINTER(ctypes.c_double)), ("nt", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        D = ctypes.POINTER(ctypes.c_double)
+        I = ctypes.POINTER(ctypes.c_int)
+        G = ctypes.POINTER(_Grid)
+        S = ctypes.POINTER(_Source)
+        c_int, c_double = ctypes.c_int, ctypes.c_double
+        sig = {
+            "or_global_spline": (None, [c_int, c_double, D, D]),
+            "or_global_inverse_column": (None, [c_int, c_double, c_int, D]),
+            "or_patch_lu": (None, [c_int, D, D]),
+            "or_pmbc_row": (c_int, [c_int, c_double, c_int, c_int, c_int, c_int, D, I]),
+            "or_line_deriv": (None, [c_int, c_double, c_int, c_int, c_int, D, D, D]),
+            "or_line_deriv_matrix": (None, [c_int, c_double, c_int, c_int, c_int, D]),
+            "or_field_deriv": (None, [G, c_int, c_int, D, D]),
+            "or_source_weights": (None, [G, D, c_double, D]),
+            "or_run_from": (c_int, [G, c_int, c_double, c_int, c_int, D, D, D, c_int, S, c_int, I,
+                                    c_int, D, D, D]),
+            "or_acoustic_adjoint": (c_int, [G, c_double, c_int, D, D, c_int, S, c_int, I, D, D]),
+            "or_num_fields": (c_int, [c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _grid(g) -> _Grid:
+    s = _Grid()
+    s.ndim = int(g["ndim"])
+    for a in range(3):
+        s.n[a] = int(g["n"][a])
+        s.h[a] = float(g["h"][a])
+        s.M[a] = int(g["M"][a])
+    s.halo = int(g["halo"])
+    s.end_mode = int(g.get("end_mode", END_NATURAL))
+    return s
+
+
+def field_shape(g):
+    n = g["n"]
+    if g["ndim"] == 2:
+        return (n[2] + 1, n[0] + 1)
+    return (n[2] + 1, n[1] + 1, n[0] + 1)
+
+
+# ---- 1-D ------------------------------------------------------------------
+
+def global_spline(N, h, v):
+    v = _f64(v)
+    out = np.zeros(N + 3)
+    lib().or_global_spline(N, h, _dp(v), _dp(out))
+    return out
+
+
+def global_inverse_column(N, h, k):
+    out = np.zeros(N + 3)
+    lib().or_global_inverse_column(N, h, k, _dp(out))
+    return out
+
+
+def patch_lu(M):
+    d = np.zeros(M + 3)
+    l = np.zeros(M + 2)
+    lib().or_patch_lu(M, _dp(d), _dp(l))
+    return d, l
+
+
+def pmbc_row(N, h, M, halo, end_mode, J):
+    c = np.zeros(2 * halo + 1)
+    idx = np.zeros(2 * halo + 1, dtype=np.int32)
+    has = lib().or_pmbc_row(N, h, M, halo, end_mode, J, _dp(c), _ip(idx))
+    return bool(has), c, idx
+
+
+def line_deriv(N, h, M, halo, end_mode, u):
+    u = _f64(u)
+    d1 = np.zeros(N + 1)
+    d2 = np.zeros(N + 1)
+    lib().or_line_deriv(N, h, M, halo, end_mode, _dp(u), _dp(d1), _dp(d2))
+    return d1, d2
+
+
+def line_deriv_matrix(N, h, M, halo, end_mode):
+    D = np.zeros((N + 1, N + 1))
+    lib().or_line_deriv_matrix(N, h, M, halo, end_mode, _dp(D))
+    return D
+
+
+# ---- fields ---------------------------------------------------------------
+
+def field_deriv(g, axis, order, field):
+    f = _f64(field)
+    out = np.zeros_like(f)
+    gs = _grid(g)
+    lib().or_field_deriv(ctypes.byref(gs), axis, order, _dp(f), _dp(out))
+    return out
+
+
+def source_weights(g, pos, spread):
+    out = np.zeros(field_shape(g))
+    gs = _grid(g)
+    p = _f64(list(pos) + [0.0] * (3 - len(pos)))
+    lib().or_source_weights(ctypes.byref(gs), _dp(p), float(spread), _dp(out))
+    return out
+
+
+def _sources(sources):
+    """sources: list of dicts {kind, pos (3), spread, wavelet (1-D array)}."""
+    keep = []
+    arr = (_Source * max(1, len(sources)))()
+    for i, s in enumerate(sources):
+        w = _f64(s["wavelet"])
+        keep.append(w)
+        arr[i].kind = int(s["kind"])
+        for a in range(3):
+            arr[i].pos[a] = float(s["pos"][a])
+        arr[i].spread = float(s.get("spread", 0.0))
+        arr[i].wavelet = _dp(w)
+        arr[i].nt = int(w.size)
+    return arr, keep
+
+
+def run(g, physics, dt, nsteps, vp, rho, vs=None, sources=(), receivers=None, rec_comp=0,
+        fields_in=None, step0=0):
+    """Run one shot; returns (fields (nfields, *shape), traces (nrec, nsteps))."""
+    shape = field_shape(g)
+    nf = 3 if physics == ACOUSTIC else 9
+    vp = _f64(vp)
+    rho = _f64(rho)
+    vs = _f64(vs) if vs is not None else None
+    src, keep = _sources(list(sources))
+    rec = np.zeros((0, 3), dtype=np.int32) if receivers is None else np.ascontiguousarray(receivers, dtype=np.int32)
+    nrec = rec.shape[0]
+    fields = np.zeros((nf,) + shape)
+    traces = np.zeros((nrec, nsteps))
+    fin = _f64(fields_in) if fields_in is not None else None
+    gs = _grid(g)
+    rc = lib().or_run_from(ctypes.byref(gs), physics, float(dt), int(step0), int(nsteps), _dp(vp),
+                           _dp(vs), _dp(rho), len(keep), src, nrec, _ip(rec), int(rec_comp),
+                           _dp(fin), _dp(fields), _dp(traces))
+    if rc != 0:
+        raise ValueError("oracle or_run_from rejected its arguments (rc=%d)" % rc)
+    return fields, traces
+
+
+def acoustic_adjoint(g, dt, nsteps, vp, rho, sources, receivers, residual):
+    """Gradient dJ/dK (K = rho c^2) at every node for J = 1/2 sum residual^2."""
+    shape = field_shape(g)
+    vp = _f64(vp)
+    rho = _f64(rho)
+    src, keep = _sources(list(sources))
+    rec = np.ascontiguousarray(receivers, dtype=np.int32)
+    res = _f64(residual)
+    grad = np.zeros(shape)
+    gs = _grid(g)
+    rc = lib().or_acoustic_adjoint(ctypes.byref(gs), float(dt), int(nsteps), _dp(vp), _dp(rho),
+                                   len(keep), src, rec.shape[0], _ip(rec), _dp(res), _dp(grad))
+    if rc != 0:
+        raise ValueError("oracle or_acoustic_adjoint rejected its arguments (rc=%d)" % rc)
+    return grad
+
+
+def rel_l2(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.linalg.norm(ref)
+    return float(np.linalg.norm(x - ref) / den) if den > 0 else float(np.linalg.norm(x - ref))

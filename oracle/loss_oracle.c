@@ -1,0 +1,723 @@
+/*
+ * loss_oracle.c -- plain FP64 CPU oracle of the local spline simulator (LOSS),
+ * arXiv 2301.05127.  TEST INFRASTRUCTURE ONLY (see loss_oracle.h).
+ *
+ * Parity unpinned: none of the routines below lacks a pin; the pins live in
+ * tests/test_oracle_pins.py (dense brute force, closed forms, invariants,
+ * analytic plane-wave dispersion, finite differences of the adjoint).
+ *
+ * Method, in the paper's order (Sec. 3):
+ *   1. cubic B-spline coefficients v~_{-1..N+1} of a line from the collocation rows
+ *      (v~_{i-1} + 4 v~_i + v~_{i+1})/6 = v_i and two end rows  (Sec. 3.1);
+ *   2. the line is cut into patches of M intervals sharing their junction nodes;
+ *      each patch solves its own bordered system with Hermite end rows
+ *      (v~_1 - v~_{-1})/(2h) = phi  (eq. spline_cofficient_eq_piece);
+ *   3. the junction slope phi is the truncated row of the global inverse b = A^{-1}
+ *      (eq. truncated_solution, truncation, PMBC, PMBC_coeffcients);
+ *   4. the derivative is the centred difference of the coefficients
+ *      (eq. derivative_approximation); the second derivative is the second
+ *      difference of the coefficients divided by h^2 (second derivative of B_i);
+ *   5. time: Strang splitting, half step of the velocity sub-flow, full step of the
+ *      stress sub-flow, half step of the velocity sub-flow (Sec. 3.3, no PML).
+ */
+#include "loss_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Bordered spline system.                                                   */
+/* Unknowns x_{-1..K+1} stored as xs[0..K+2].  Rows:                         */
+/*   L[0] x_{-1} + L[1] x_0 + L[2] x_1 = rl                                  */
+/*   (x_{i-1} + 4 x_i + x_{i+1}) / 6   = r_i        i = 0..K                 */
+/*   R[0] x_{K-1} + R[1] x_K + R[2] x_{K+1} = rr                             */
+/* Solved by substituting the two ghost unknowns from the border rows into   */
+/* rows 0 and K, Gaussian elimination of the remaining (K+1) tridiagonal     */
+/* system (diagonally dominant: no pivoting), and back-substitution.         */
+/* ------------------------------------------------------------------------ */
+static void bordered_solve(int K, const double L[3], double rl, const double *r,
+                           const double R[3], double rr, double *xs)
+{
+    int n = K + 1, i;
+    double *a = (double *)malloc(sizeof(double) * 4 * n);
+    double *b = a + n, *c = b + n, *d = c + n;
+    for (i = 0; i < n; ++i) { a[i] = 1.0; b[i] = 4.0; c[i] = 1.0; d[i] = 6.0 * r[i]; }
+    a[0] = 0.0;
+    c[n - 1] = 0.0;
+    /* row 0 with x_{-1} = (rl - L1 x_0 - L2 x_1) / L0 */
+    b[0] -= L[1] / L[0];
+    c[0] = (n > 1 ? 1.0 : 0.0) - L[2] / L[0];
+    d[0] -= rl / L[0];
+    /* row K with x_{K+1} = (rr - R0 x_{K-1} - R1 x_K) / R2 */
+    if (n > 1) a[n - 1] = 1.0 - R[0] / R[2];
+    b[n - 1] -= R[1] / R[2];
+    d[n - 1] -= rr / R[2];
+    /* forward elimination */
+    for (i = 1; i < n; ++i) {
+        double m = a[i] / b[i - 1];
+        b[i] -= m * c[i - 1];
+        d[i] -= m * d[i - 1];
+    }
+    /* back substitution into xs[1..K+1] = x_0..x_K */
+    xs[n] = d[n - 1] / b[n - 1];
+    for (i = n - 2; i >= 0; --i) xs[i + 1] = (d[i] - c[i] * xs[i + 2]) / b[i];
+    /* ghosts */
+    xs[0] = (rl - L[1] * xs[1] - L[2] * xs[2]) / L[0];
+    xs[K + 2] = (rr - R[0] * xs[K] - R[1] * xs[K + 1]) / R[2];
+    free(a);
+}
+
+static void natural_row(double h, double row[3])
+{
+    row[0] = 1.0 / (h * h); row[1] = -2.0 / (h * h); row[2] = 1.0 / (h * h);
+}
+
+static void hermite_row(double h, double row[3])
+{
+    row[0] = -1.0 / (2.0 * h); row[1] = 0.0; row[2] = 1.0 / (2.0 * h);
+}
+
+void or_global_spline(int N, double h, const double *v, double *vt)
+{
+    double L[3], R[3];
+    natural_row(h, L);
+    natural_row(h, R);
+    bordered_solve(N, L, 0.0, v, R, 0.0, vt);
+}
+
+void or_global_inverse_column(int N, double h, int k, double *out)
+{
+    double *e = (double *)calloc((size_t)N + 1, sizeof(double));
+    e[k] = 1.0;
+    or_global_spline(N, h, e, out);
+    free(e);
+}
+
+void or_patch_lu(int M, double *d, double *l)
+{
+    int i;
+    d[1] = 4.0;
+    l[1] = 0.25;
+    d[2] = 4.0 - 2.0 * l[1];
+    for (i = 2; i <= M; ++i) {
+        l[i] = 1.0 / d[i];
+        d[i + 1] = 4.0 - l[i];
+    }
+    l[M + 1] = 1.0 / (d[M] * d[M + 1]);
+    d[M + 2] = 1.0 - l[M + 1];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Periodic line: circulant collocation system on N distinct nodes           */
+/* (node N is node 0).  First column g of its inverse, by dense Gaussian      */
+/* elimination with partial pivoting (obviously correct, O(N^3), small N).    */
+/* ------------------------------------------------------------------------ */
+static int periodic_inverse_column0(int N, double *g)
+{
+    double *A = (double *)calloc((size_t)N * N, sizeof(double));
+    int i, j, k;
+    if (!A) return -1;
+    for (i = 0; i < N; ++i) {
+        A[(size_t)i * N + i] += 4.0 / 6.0;
+        A[(size_t)i * N + (i + 1) % N] += 1.0 / 6.0;
+        A[(size_t)i * N + (i + N - 1) % N] += 1.0 / 6.0;
+        g[i] = (i == 0) ? 1.0 : 0.0;
+    }
+    for (k = 0; k < N; ++k) {
+        int p = k;
+        for (i = k + 1; i < N; ++i)
+            if (fabs(A[(size_t)i * N + k]) > fabs(A[(size_t)p * N + k])) p = i;
+        if (p != k) {
+            for (j = 0; j < N; ++j) {
+                double t = A[(size_t)k * N + j];
+                A[(size_t)k * N + j] = A[(size_t)p * N + j];
+                A[(size_t)p * N + j] = t;
+            }
+            { double t = g[k]; g[k] = g[p]; g[p] = t; }
+        }
+        for (i = k + 1; i < N; ++i) {
+            double m = A[(size_t)i * N + k] / A[(size_t)k * N + k];
+            if (m == 0.0) continue;
+            for (j = k; j < N; ++j) A[(size_t)i * N + j] -= m * A[(size_t)k * N + j];
+            g[i] -= m * g[k];
+        }
+    }
+    for (i = N - 1; i >= 0; --i) {
+        double s = g[i];
+        for (j = i + 1; j < N; ++j) s -= A[(size_t)i * N + j] * g[j];
+        g[i] = s / A[(size_t)i * N + i];
+    }
+    free(A);
+    return 0;
+}
+
+static int num_patches(int N, int M) { return (N + M - 1) / M; }
+
+static int node_has_row(int N, int M, int end_mode, int J)
+{
+    if (J < 0 || J > N) return 0;
+    if (J == 0 || J == N) return end_mode != OR_END_NATURAL;
+    return (J % M) == 0;
+}
+
+int or_pmbc_row(int N, double h, int M, int halo, int end_mode, int J, double *c, int *idx)
+{
+    int n = halo, t;
+    for (t = 0; t <= 2 * n; ++t) { c[t] = 0.0; idx[t] = -1; }
+    if (!node_has_row(N, M, end_mode, J)) return 0;
+    if (end_mode == OR_END_PERIODIC) {
+        /* b_{i,k} = g[(i - k) mod N] for the circulant system */
+        double *g = (double *)malloc(sizeof(double) * N);
+        periodic_inverse_column0(N, g);
+        for (t = 0; t <= 2 * n; ++t) {
+            int k = (((J - n + t) % N) + N) % N;
+            int ip = (((J + 1 - k) % N) + N) % N, im = (((J - 1 - k) % N) + N) % N;
+            c[t] = (g[ip] - g[im]) / (2.0 * h);
+            idx[t] = k;
+        }
+        free(g);
+        return 1;
+    }
+    {
+        /* phi_J = sum_k (b_{J+1,k} - b_{J-1,k}) / (2h) v_k over |k - J| <= n, k in [0,N]
+         * (eq. PMBC with the coefficients of eq. PMBC_coeffcients; at J = 0 and J = N
+         * the same window clipped to the line is the paper's one-sided end stencil). */
+        double *col = (double *)malloc(sizeof(double) * ((size_t)N + 3));
+        for (t = 0; t <= 2 * n; ++t) {
+            int k = J - n + t;
+            if (k < 0 || k > N) continue;
+            or_global_inverse_column(N, h, k, col);
+            /* col[i+1] = b_{i,k} */
+            c[t] = (col[J + 2] - col[J]) / (2.0 * h);
+            idx[t] = k;
+        }
+        free(col);
+        return 1;
+    }
+}
+
+/* Per-axis table: the PMBC row of every node that carries one. */
+typedef struct {
+    int N, M, n, mode;
+    double h;
+    unsigned char *has;
+    double *c;
+    int *idx;
+} axis_tab;
+
+static void axis_tab_build(axis_tab *T, int N, double h, int M, int halo, int mode)
+{
+    int J, w = 2 * halo + 1;
+    T->N = N; T->M = M; T->n = halo; T->mode = mode; T->h = h;
+    T->has = (unsigned char *)calloc((size_t)N + 1, 1);
+    T->c = (double *)calloc((size_t)(N + 1) * w, sizeof(double));
+    T->idx = (int *)calloc((size_t)(N + 1) * w, sizeof(int));
+    for (J = 0; J <= N; ++J)
+        T->has[J] = (unsigned char)or_pmbc_row(N, h, M, halo, mode, J, T->c + (size_t)J * w,
+                                               T->idx + (size_t)J * w);
+}
+
+static void axis_tab_free(axis_tab *T)
+{
+    free(T->has); free(T->c); free(T->idx);
+}
+
+static double axis_phi(const axis_tab *T, int J, const double *u)
+{
+    int w = 2 * T->n + 1, t;
+    double s = 0.0;
+    for (t = 0; t < w; ++t) {
+        int k = T->idx[(size_t)J * w + t];
+        if (k >= 0) s += T->c[(size_t)J * w + t] * u[k];
+    }
+    return s;
+}
+
+/* Derivative of one line with a prebuilt table; xs is scratch of M+3 doubles. */
+static void line_deriv_tab(const axis_tab *T, const double *u, double *d1, double *d2, double *xs)
+{
+    int N = T->N, M = T->M, p = num_patches(N, M), l, i;
+    double h = T->h;
+    for (l = 0; l < p; ++l) {
+        int s = l * M, e = s + M < N ? s + M : N, K = e - s;
+        double L[3], R[3], rl = 0.0, rr = 0.0;
+        if (s == 0 && T->mode == OR_END_NATURAL) natural_row(h, L);
+        else { hermite_row(h, L); rl = axis_phi(T, s, u); }
+        if (e == N && T->mode == OR_END_NATURAL) natural_row(h, R);
+        else { hermite_row(h, R); rr = axis_phi(T, e, u); }
+        bordered_solve(K, L, rl, u + s, R, rr, xs);
+        for (i = 0; i <= K; ++i) {
+            if (i == K && e != N) break;  /* junction node e is owned by patch l+1 */
+            if (d1) d1[s + i] = (xs[i + 2] - xs[i]) / (2.0 * h);
+            if (d2) d2[s + i] = (xs[i] - 2.0 * xs[i + 1] + xs[i + 2]) / (h * h);
+        }
+    }
+}
+
+void or_line_deriv(int N, double h, int M, int halo, int end_mode, const double *u, double *d1,
+                   double *d2)
+{
+    axis_tab T;
+    double *xs = (double *)malloc(sizeof(double) * ((size_t)M + 3));
+    axis_tab_build(&T, N, h, M, halo, end_mode);
+    line_deriv_tab(&T, u, d1, d2, xs);
+    axis_tab_free(&T);
+    free(xs);
+}
+
+void or_line_deriv_matrix(int N, double h, int M, int halo, int end_mode, double *D)
+{
+    axis_tab T;
+    int j, i;
+    double *e = (double *)calloc((size_t)N + 1, sizeof(double));
+    double *col = (double *)malloc(sizeof(double) * ((size_t)N + 1));
+    double *xs = (double *)malloc(sizeof(double) * ((size_t)M + 3));
+    axis_tab_build(&T, N, h, M, halo, end_mode);
+    for (j = 0; j <= N; ++j) {
+        e[j] = 1.0;
+        line_deriv_tab(&T, e, col, NULL, xs);
+        for (i = 0; i <= N; ++i) D[(size_t)i * (N + 1) + j] = col[i];
+        e[j] = 0.0;
+    }
+    axis_tab_free(&T);
+    free(e); free(col); free(xs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fields                                                                    */
+/* ------------------------------------------------------------------------ */
+static void grid_nodes(const or_grid *g, long nn[3])
+{
+    nn[0] = g->n[0] + 1;
+    nn[1] = g->ndim == 3 ? g->n[1] + 1 : 1;
+    nn[2] = g->n[2] + 1;
+}
+
+static long grid_total(const or_grid *g)
+{
+    long nn[3];
+    grid_nodes(g, nn);
+    return nn[0] * nn[1] * nn[2];
+}
+
+/* Apply a line operator along `axis` to every line.  op(ctx, in_line, out_line). */
+typedef void (*line_op)(const void *ctx, const double *in, double *out, double *scratch);
+
+static void apply_lines(const or_grid *g, int axis, const double *in, double *out, line_op op,
+                        const void *ctx, int scratch_len)
+{
+    long nn[3], stride[3], nlines, L;
+    int len;
+    grid_nodes(g, nn);
+    stride[0] = 1; stride[1] = nn[0]; stride[2] = nn[0] * nn[1];
+    len = (int)nn[axis];
+    nlines = grid_total(g) / len;
+#pragma omp parallel
+    {
+        double *a = (double *)malloc(sizeof(double) * (size_t)(2 * len + scratch_len));
+        double *b = a + len, *s = b + len;
+#pragma omp for schedule(static)
+        for (L = 0; L < nlines; ++L) {
+            /* decompose the line index into the two other coordinates */
+            long base, o0, o1;
+            int ax0 = axis == 0 ? 1 : 0, ax1 = axis == 2 ? 1 : 2, i;
+            o0 = L % nn[ax0];
+            o1 = L / nn[ax0];
+            base = o0 * stride[ax0] + o1 * stride[ax1];
+            for (i = 0; i < len; ++i) a[i] = in[base + i * stride[axis]];
+            op(ctx, a, b, s);
+            for (i = 0; i < len; ++i) out[base + i * stride[axis]] = b[i];
+        }
+        free(a);
+    }
+}
+
+typedef struct { const axis_tab *T; int order; } deriv_ctx;
+
+static void deriv_op(const void *ctx, const double *in, double *out, double *scratch)
+{
+    const deriv_ctx *c = (const deriv_ctx *)ctx;
+    if (c->order == 2) line_deriv_tab(c->T, in, NULL, out, scratch);
+    else line_deriv_tab(c->T, in, out, NULL, scratch);
+}
+
+typedef struct { const double *D; int n; int transpose; } dense_ctx;
+
+static void dense_op(const void *ctx, const double *in, double *out, double *scratch)
+{
+    const dense_ctx *c = (const dense_ctx *)ctx;
+    int i, j, n = c->n;
+    (void)scratch;
+    for (i = 0; i < n; ++i) {
+        double s = 0.0;
+        if (c->transpose)
+            for (j = 0; j < n; ++j) s += c->D[(size_t)j * n + i] * in[j];
+        else
+            for (j = 0; j < n; ++j) s += c->D[(size_t)i * n + j] * in[j];
+        out[i] = s;
+    }
+}
+
+static void tab_for_axis(const or_grid *g, int axis, axis_tab *T)
+{
+    axis_tab_build(T, g->n[axis], g->h[axis], g->M[axis], g->halo, g->end_mode);
+}
+
+void or_field_deriv(const or_grid *g, int axis, int order, const double *in, double *out)
+{
+    axis_tab T;
+    deriv_ctx c;
+    tab_for_axis(g, axis, &T);
+    c.T = &T; c.order = order;
+    apply_lines(g, axis, in, out, deriv_op, &c, g->M[axis] + 3);
+    axis_tab_free(&T);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sources                                                                   */
+/* ------------------------------------------------------------------------ */
+void or_source_weights(const or_grid *g, const double pos[3], double spread, double *w)
+{
+    long nn[3], tot = grid_total(g), i;
+    int a, ax[3], lo[3], hi[3], cnode[3], x, y, z, nax = g->ndim == 3 ? 3 : 2;
+    double hd = 1.0, sum = 0.0;
+    grid_nodes(g, nn);
+    ax[0] = 0; ax[1] = g->ndim == 3 ? 1 : 2; ax[2] = 2;
+    for (i = 0; i < tot; ++i) w[i] = 0.0;
+    for (a = 0; a < 3; ++a) {
+        lo[a] = hi[a] = cnode[a] = 0;
+    }
+    for (a = 0; a < nax; ++a) {
+        int d = ax[a];
+        hd *= g->h[d];
+        cnode[d] = (int)floor(pos[d] / g->h[d] + 0.5);
+        if (cnode[d] < 0) cnode[d] = 0;
+        if (cnode[d] > g->n[d]) cnode[d] = g->n[d];
+        if (spread > 0.0) {
+            int r = (int)ceil(4.0 * spread / g->h[d]);
+            lo[d] = cnode[d] - r < 0 ? 0 : cnode[d] - r;
+            hi[d] = cnode[d] + r > g->n[d] ? g->n[d] : cnode[d] + r;
+        } else {
+            lo[d] = hi[d] = cnode[d];
+        }
+    }
+    for (z = lo[2]; z <= hi[2]; ++z)
+        for (y = lo[1]; y <= hi[1]; ++y)
+            for (x = lo[0]; x <= hi[0]; ++x) {
+                double q = 1.0;
+                if (spread > 0.0) {
+                    double dx = x * g->h[0] - pos[0], dz = z * g->h[2] - pos[2], dy = 0.0;
+                    if (g->ndim == 3) dy = y * g->h[1] - pos[1];
+                    q = exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * spread * spread));
+                }
+                w[((long)z * nn[1] + y) * nn[0] + x] = q;
+                sum += q;
+            }
+    for (z = lo[2]; z <= hi[2]; ++z)
+        for (y = lo[1]; y <= hi[1]; ++y)
+            for (x = lo[0]; x <= hi[0]; ++x)
+                w[((long)z * nn[1] + y) * nn[0] + x] /= sum * hd;
+}
+
+int or_num_fields(int physics) { return physics == OR_ACOUSTIC ? 3 : 9; }
+
+static double sample(const or_source *s, long k)
+{
+    return (k >= 0 && k < s->nt) ? s->wavelet[k] : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Strang stepper                                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const or_grid *g;
+    axis_tab T[3];
+    deriv_ctx c[3];
+    long tot;
+    double *tmp;     /* one field of scratch */
+} stepper;
+
+static void deriv_into(stepper *S, int axis, const double *in, double *out)
+{
+    apply_lines(S->g, axis, in, out, deriv_op, &S->c[axis], S->g->M[axis] + 3);
+}
+
+static int check_grid(const or_grid *g, int physics)
+{
+    int a;
+    if (physics == OR_ACOUSTIC && g->ndim != 2) return -1;
+    if (physics == OR_ELASTIC && g->ndim != 3) return -1;
+    for (a = 0; a < 3; ++a) {
+        if (a == 1 && g->ndim == 2) continue;
+        if (g->n[a] < 2 || g->M[a] < 1 || g->h[a] <= 0) return -1;
+        if (g->end_mode == OR_END_PERIODIC && 2 * g->halo + 1 > g->n[a]) return -1;
+    }
+    if (g->halo < 1) return -1;
+    return 0;
+}
+
+int or_run_from(const or_grid *g, int physics, double dt, int step0, int nsteps,
+                const double *vp, const double *vs, const double *rho,
+                int nsrc, const or_source *src,
+                int nrec, const int *rec_idx, int rec_comp,
+                const double *fields_in, double *fields, double *traces)
+{
+    stepper S;
+    long nn[3], tot, i;
+    int nf = or_num_fields(physics), a, k, n, r;
+    double *F, *K1, *K2, *b, *d[9], **W;
+    if (check_grid(g, physics)) return -1;
+    grid_nodes(g, nn);
+    tot = grid_total(g);
+    S.g = g; S.tot = tot;
+    for (a = 0; a < 3; ++a) {
+        if (a == 1 && g->ndim == 2) { memset(&S.T[a], 0, sizeof(axis_tab)); continue; }
+        tab_for_axis(g, a, &S.T[a]);
+        S.c[a].T = &S.T[a];
+        S.c[a].order = 1;
+    }
+    F = (double *)calloc((size_t)tot * (nf + 3 + 9), sizeof(double));
+    K1 = F + (size_t)tot * nf;   /* acoustic: K = rho c^2 ; elastic: lambda */
+    K2 = K1 + tot;               /* elastic: mu */
+    b = K2 + tot;                /* 1 / rho */
+    for (k = 0; k < 9; ++k) d[k] = b + tot + (size_t)k * tot;
+    if (fields_in) memcpy(F, fields_in, sizeof(double) * (size_t)tot * nf);
+    for (i = 0; i < tot; ++i) {
+        b[i] = 1.0 / rho[i];
+        if (physics == OR_ACOUSTIC) {
+            K1[i] = rho[i] * vp[i] * vp[i];
+        } else {
+            K2[i] = rho[i] * vs[i] * vs[i];
+            K1[i] = rho[i] * vp[i] * vp[i] - 2.0 * K2[i];
+        }
+    }
+    W = (double **)malloc(sizeof(double *) * (nsrc > 0 ? nsrc : 1));
+    for (k = 0; k < nsrc; ++k) {
+        W[k] = (double *)malloc(sizeof(double) * tot);
+        or_source_weights(g, src[k].pos, src[k].spread, W[k]);
+    }
+
+    for (n = 0; n < nsteps; ++n) {
+        long sn = (long)step0 + n;
+        int half;
+        for (half = 0; half < 3; ++half) {
+            if (half == 0 || half == 2) {
+                /* (A) velocity sub-flow over dt/2 with the stress frozen */
+                long fk = half == 0 ? sn : sn + 1;   /* force sample time index */
+                double hdt = 0.5 * dt;
+                if (physics == OR_ACOUSTIC) {
+                    deriv_into(&S, 0, F + OR_A_SIGMA * tot, d[0]);
+                    deriv_into(&S, 2, F + OR_A_SIGMA * tot, d[1]);
+                    for (i = 0; i < tot; ++i) {
+                        F[OR_A_V1 * tot + i] -= hdt * b[i] * d[0][i];
+                        F[OR_A_V3 * tot + i] -= hdt * b[i] * d[1][i];
+                    }
+                    for (k = 0; k < nsrc; ++k) {
+                        int fld = src[k].kind == OR_SRC_FORCE_X ? OR_A_V1
+                                : src[k].kind == OR_SRC_FORCE_Z ? OR_A_V3 : -1;
+                        double s = sample(&src[k], fk);
+                        if (fld < 0) continue;
+                        for (i = 0; i < tot; ++i) F[fld * tot + i] += hdt * b[i] * s * W[k][i];
+                    }
+                } else {
+                    /* v_i += dt/2 * b * (d_j sigma_ij + f_i) */
+                    deriv_into(&S, 0, F + OR_E_S11 * tot, d[0]);
+                    deriv_into(&S, 1, F + OR_E_S12 * tot, d[1]);
+                    deriv_into(&S, 2, F + OR_E_S13 * tot, d[2]);
+                    deriv_into(&S, 0, F + OR_E_S12 * tot, d[3]);
+                    deriv_into(&S, 1, F + OR_E_S22 * tot, d[4]);
+                    deriv_into(&S, 2, F + OR_E_S23 * tot, d[5]);
+                    deriv_into(&S, 0, F + OR_E_S13 * tot, d[6]);
+                    deriv_into(&S, 1, F + OR_E_S23 * tot, d[7]);
+                    deriv_into(&S, 2, F + OR_E_S33 * tot, d[8]);
+                    for (i = 0; i < tot; ++i) {
+                        F[OR_E_V1 * tot + i] += hdt * b[i] * (d[0][i] + d[1][i] + d[2][i]);
+                        F[OR_E_V2 * tot + i] += hdt * b[i] * (d[3][i] + d[4][i] + d[5][i]);
+                        F[OR_E_V3 * tot + i] += hdt * b[i] * (d[6][i] + d[7][i] + d[8][i]);
+                    }
+                    for (k = 0; k < nsrc; ++k) {
+                        int fld = src[k].kind == OR_SRC_FORCE_X ? OR_E_V1
+                                : src[k].kind == OR_SRC_FORCE_Y ? OR_E_V2
+                                : src[k].kind == OR_SRC_FORCE_Z ? OR_E_V3 : -1;
+                        double s = sample(&src[k], fk);
+                        if (fld < 0) continue;
+                        for (i = 0; i < tot; ++i) F[fld * tot + i] += hdt * b[i] * s * W[k][i];
+                    }
+                }
+            } else {
+                /* (B) stress sub-flow over dt with the velocity frozen */
+                if (physics == OR_ACOUSTIC) {
+                    deriv_into(&S, 0, F + OR_A_V1 * tot, d[0]);
+                    deriv_into(&S, 2, F + OR_A_V3 * tot, d[1]);
+                    for (i = 0; i < tot; ++i)
+                        F[OR_A_SIGMA * tot + i] -= dt * K1[i] * (d[0][i] + d[1][i]);
+                    for (k = 0; k < nsrc; ++k) {
+                        double s = sample(&src[k], sn);
+                        if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                        for (i = 0; i < tot; ++i) F[OR_A_SIGMA * tot + i] += dt * s * W[k][i];
+                    }
+                } else {
+                    deriv_into(&S, 0, F + OR_E_V1 * tot, d[0]);  /* d1 v1 */
+                    deriv_into(&S, 1, F + OR_E_V2 * tot, d[1]);  /* d2 v2 */
+                    deriv_into(&S, 2, F + OR_E_V3 * tot, d[2]);  /* d3 v3 */
+                    deriv_into(&S, 1, F + OR_E_V1 * tot, d[3]);  /* d2 v1 */
+                    deriv_into(&S, 0, F + OR_E_V2 * tot, d[4]);  /* d1 v2 */
+                    deriv_into(&S, 2, F + OR_E_V1 * tot, d[5]);  /* d3 v1 */
+                    deriv_into(&S, 0, F + OR_E_V3 * tot, d[6]);  /* d1 v3 */
+                    deriv_into(&S, 2, F + OR_E_V2 * tot, d[7]);  /* d3 v2 */
+                    deriv_into(&S, 1, F + OR_E_V3 * tot, d[8]);  /* d2 v3 */
+                    for (i = 0; i < tot; ++i) {
+                        double div = d[0][i] + d[1][i] + d[2][i];
+                        double lam = K1[i], mu = K2[i];
+                        F[OR_E_S11 * tot + i] += dt * (lam * div + 2.0 * mu * d[0][i]);
+                        F[OR_E_S22 * tot + i] += dt * (lam * div + 2.0 * mu * d[1][i]);
+                        F[OR_E_S33 * tot + i] += dt * (lam * div + 2.0 * mu * d[2][i]);
+                        F[OR_E_S12 * tot + i] += dt * mu * (d[3][i] + d[4][i]);
+                        F[OR_E_S13 * tot + i] += dt * mu * (d[5][i] + d[6][i]);
+                        F[OR_E_S23 * tot + i] += dt * mu * (d[7][i] + d[8][i]);
+                    }
+                    for (k = 0; k < nsrc; ++k) {
+                        double s = sample(&src[k], sn);
+                        if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                        for (i = 0; i < tot; ++i) {
+                            F[OR_E_S11 * tot + i] += dt * s * W[k][i];
+                            F[OR_E_S22 * tot + i] += dt * s * W[k][i];
+                            F[OR_E_S33 * tot + i] += dt * s * W[k][i];
+                        }
+                    }
+                }
+            }
+        }
+        if (traces) {
+            int comp = physics == OR_ACOUSTIC ? OR_A_SIGMA : rec_comp;
+            for (r = 0; r < nrec; ++r) {
+                long ix = rec_idx[3 * r], iy = rec_idx[3 * r + 1], iz = rec_idx[3 * r + 2];
+                traces[(size_t)r * nsteps + n] = F[(size_t)comp * tot + (iz * nn[1] + iy) * nn[0] + ix];
+            }
+        }
+    }
+    if (fields) memcpy(fields, F, sizeof(double) * (size_t)tot * nf);
+    for (k = 0; k < nsrc; ++k) free(W[k]);
+    free(W);
+    free(F);
+    for (a = 0; a < 3; ++a)
+        if (!(a == 1 && g->ndim == 2)) axis_tab_free(&S.T[a]);
+    return 0;
+}
+
+int or_run(const or_grid *g, int physics, double dt, int nsteps,
+           const double *vp, const double *vs, const double *rho,
+           int nsrc, const or_source *src,
+           int nrec, const int *rec_idx, int rec_comp,
+           double *fields, double *traces)
+{
+    return or_run_from(g, physics, dt, 0, nsteps, vp, vs, rho, nsrc, src, nrec, rec_idx,
+                       rec_comp, NULL, fields, traces);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of the acoustic 2-D Strang scheme                        */
+/* ------------------------------------------------------------------------ */
+int or_acoustic_adjoint(const or_grid *g, double dt, int nsteps,
+                        const double *vp, const double *rho,
+                        int nsrc, const or_source *src,
+                        int nrec, const int *rec_idx,
+                        const double *res, double *grad_K)
+{
+    long nn[3], tot, i;
+    int n, r, k, ax[2] = {0, 2};
+    double *Dm[2];
+    dense_ctx dc[2];
+    double *sig, *v1, *v3, *K, *b, *t0, *t1, *divA, **W;
+    double *ls, *m1, *m3, *gs;
+    if (check_grid(g, OR_ACOUSTIC)) return -1;
+    grid_nodes(g, nn);
+    tot = grid_total(g);
+    for (k = 0; k < 2; ++k) {
+        int N = g->n[ax[k]];
+        Dm[k] = (double *)malloc(sizeof(double) * (size_t)(N + 1) * (N + 1));
+        or_line_deriv_matrix(N, g->h[ax[k]], g->M[ax[k]], g->halo, g->end_mode, Dm[k]);
+        dc[k].D = Dm[k]; dc[k].n = N + 1; dc[k].transpose = 0;
+    }
+    sig = (double *)calloc((size_t)tot * 11, sizeof(double));
+    v1 = sig + tot; v3 = v1 + tot; K = v3 + tot; b = K + tot; t0 = b + tot; t1 = t0 + tot;
+    ls = t1 + tot; m1 = ls + tot; m3 = m1 + tot; gs = m3 + tot;
+    divA = (double *)malloc(sizeof(double) * (size_t)tot * nsteps);
+    if (!divA) { free(sig); return -2; }
+    for (i = 0; i < tot; ++i) { K[i] = rho[i] * vp[i] * vp[i]; b[i] = 1.0 / rho[i]; }
+    W = (double **)malloc(sizeof(double *) * (nsrc > 0 ? nsrc : 1));
+    for (k = 0; k < nsrc; ++k) {
+        W[k] = (double *)malloc(sizeof(double) * tot);
+        or_source_weights(g, src[k].pos, src[k].spread, W[k]);
+    }
+    /* forward, same canonical sequence as or_run, keeping div v at the half step */
+    for (n = 0; n < nsteps; ++n) {
+        int half;
+        for (half = 0; half < 2; ++half) {
+            long fk = half == 0 ? n : n + 1;
+            dc[0].transpose = dc[1].transpose = 0;
+            apply_lines(g, 0, sig, t0, dense_op, &dc[0], 0);
+            apply_lines(g, 2, sig, t1, dense_op, &dc[1], 0);
+            for (i = 0; i < tot; ++i) { v1[i] -= 0.5 * dt * b[i] * t0[i]; v3[i] -= 0.5 * dt * b[i] * t1[i]; }
+            for (k = 0; k < nsrc; ++k) {
+                double *f = src[k].kind == OR_SRC_FORCE_X ? v1 : src[k].kind == OR_SRC_FORCE_Z ? v3 : NULL;
+                double s = sample(&src[k], fk);
+                if (!f) continue;
+                for (i = 0; i < tot; ++i) f[i] += 0.5 * dt * b[i] * s * W[k][i];
+            }
+            if (half == 1) break;
+            apply_lines(g, 0, v1, t0, dense_op, &dc[0], 0);
+            apply_lines(g, 2, v3, t1, dense_op, &dc[1], 0);
+            for (i = 0; i < tot; ++i) {
+                divA[(size_t)n * tot + i] = t0[i] + t1[i];
+                sig[i] -= dt * K[i] * (t0[i] + t1[i]);
+            }
+            for (k = 0; k < nsrc; ++k) {
+                double s = sample(&src[k], n);
+                if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                for (i = 0; i < tot; ++i) sig[i] += dt * s * W[k][i];
+            }
+        }
+    }
+    /* reverse sweep: ls = adjoint of sigma^{n+1}; m1, m3 = adjoint of v^{n+1} */
+    for (i = 0; i < tot; ++i) { ls[i] = m1[i] = m3[i] = 0.0; grad_K[i] = 0.0; }
+    dc[0].transpose = dc[1].transpose = 1;
+    for (n = nsteps - 1; n >= 0; --n) {
+        /* trace injection and the second velocity half step */
+        for (r = 0; r < nrec; ++r) {
+            long ix = rec_idx[3 * r], iz = rec_idx[3 * r + 2];
+            ls[iz * nn[0] + ix] += res[(size_t)r * nsteps + n];
+        }
+        for (i = 0; i < tot; ++i) { t0[i] = b[i] * m1[i]; t1[i] = b[i] * m3[i]; }
+        apply_lines(g, 0, t0, gs, dense_op, &dc[0], 0);
+        for (i = 0; i < tot; ++i) ls[i] -= 0.5 * dt * gs[i];
+        apply_lines(g, 2, t1, gs, dense_op, &dc[1], 0);
+        for (i = 0; i < tot; ++i) ls[i] -= 0.5 * dt * gs[i];
+        /* stress sub-flow: gradient, then the velocity adjoint */
+        for (i = 0; i < tot; ++i) {
+            grad_K[i] -= dt * ls[i] * divA[(size_t)n * tot + i];
+            t0[i] = K[i] * ls[i];
+        }
+        apply_lines(g, 0, t0, gs, dense_op, &dc[0], 0);
+        for (i = 0; i < tot; ++i) m1[i] -= dt * gs[i];
+        apply_lines(g, 2, t0, gs, dense_op, &dc[1], 0);
+        for (i = 0; i < tot; ++i) m3[i] -= dt * gs[i];
+        /* first velocity half step */
+        for (i = 0; i < tot; ++i) { t0[i] = b[i] * m1[i]; t1[i] = b[i] * m3[i]; }
+        apply_lines(g, 0, t0, gs, dense_op, &dc[0], 0);
+        for (i = 0; i < tot; ++i) ls[i] -= 0.5 * dt * gs[i];
+        apply_lines(g, 2, t1, gs, dense_op, &dc[1], 0);
+        for (i = 0; i < tot; ++i) ls[i] -= 0.5 * dt * gs[i];
+    }
+    for (k = 0; k < nsrc; ++k) free(W[k]);
+    free(W);
+    free(divA);
+    free(sig);
+    free(Dm[0]); free(Dm[1]);
+    return 0;
+}
