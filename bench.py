@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the LOSS hot path on one MI355X.
+
+Workload (default): 2-D acoustic, 2048x2048 intervals (2049^2 nodes), h = 10 m,
+dt = 1 ms, 8x8 patches of 256 intervals, PMBC halo 12, velocity = smooth Gaussian
+random field in [1500, 4500] m/s (seed 2301, correlation 200 m), 20 Hz Ricker at the
+centre, receivers on every node of row z = 20 m; synthetic inputs.
+
+One step = one Strang step of the whole hot path: PMBC junction slopes, patch
+tridiagonal solves and derivative epilogues along x and z for the stress and the
+velocity sub-flows, source injection, receiver recording.  Inputs are resident in
+device memory before the timed region; the timed region replays the step graph.
+
+Prints one JSON line.  value = Mcell-updates/s (nodes x shots x steps / time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic (compulsory) bytes per node per launch of each kernel class, FP32:
+# every field a kernel must read or write, counted once (halo re-reads excluded)
+ALGO_BYTES = {
+    0: {  # acoustic
+        "stress_line_x": 8,      # read v1, write T = dv1/dx
+        "stress_line_z": 20,     # read v3, T, sigma, K; write sigma
+        "velocity_line_x": 16,   # read sigma, v1, b; write v1
+        "velocity_line_z": 16,   # read sigma, v3, b; write v3
+    },
+}
+STEP_BYTES = {0: 44, 1: 120}   # compulsory bytes per cell-step (whole step)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2000)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--workload", default="cfg2")
+    p.add_argument("--shots", type=int, default=1)
+    p.add_argument("--timing-steps", type=int, default=200)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-steps", type=int, default=40)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="also run one 1 GiB device copy (HBM counter calibration)")
+    return p.parse_args()
+
+
+def workload_desc(w, shots):
+    g = w["grid"]
+    n = g["n"]
+    dims = "x".join(str(v) for v in ((n[0], n[2]) if g["ndim"] == 2 else n))
+    return ("%s: %s %d-D, %s intervals, h=%g m, dt=%g s, patches of %s, halo %d, %d shot(s)"
+            % (w["name"], "acoustic" if w["physics"] == 0 else "elastic", g["ndim"], dims, g["h"][0],
+               w["dt"], "x".join(str(m) for m in (g["M"][0], g["M"][2])), g["halo"], shots))
+
+
+def cpu_baseline(w, nsteps):
+    import oracle
+    oracle.build()
+    sh = w["shots"][0]
+    t0 = time.perf_counter()
+    oracle.run(w["grid"], w["physics"], w["dt"], nsteps, w["vp"], w["rho"], vs=w.get("vs"),
+               sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh.get("rec_comp", 0))
+    el = time.perf_counter() - t0
+    nodes = int(np.prod([v + 1 for v in w["grid"]["n"] if True]))
+    if w["grid"]["ndim"] == 2:
+        nodes = (w["grid"]["n"][0] + 1) * (w["grid"]["n"][2] + 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nodes * nsteps / el / 1e6, "unit": "Mcell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d steps of the same workload, one shot, FP64 C oracle (canonical unfused "
+                      "Strang, OpenMP over lines), %.1f s wall" % (nsteps, el)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported (shots and "
+              "space would shard across GPUs, see DESIGN.md)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2301_05127_amd import inputs, loss
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    torch.cuda.init()
+    total = a.warmup + a.steps
+    w = inputs.config(a.workload, nsteps=total)
+    S = a.shots
+    shots = (w["shots"] * S)[:S]
+    g = w["grid"]
+    sim = loss.Simulation(g, w["physics"], w["dt"], nshots=S, trace_len=total)
+    sim.setup_workload(w, shots=shots)
+    nodes = sim.nodes
+    # warmup (also builds the step graph)
+    sim.step(a.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(a.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = nodes * S * a.steps / el / 1e6
+    finite = bool(np.isfinite(sim.get_field(0)).all())
+
+    # per-kernel durations (HIP events around every launch on the simulation stream)
+    ts = min(a.timing_steps, a.steps)
+    kt = []
+    if ts > 0:
+        sim.set_timing(True)
+        sim.step(ts)
+        sim.sync()
+        kt = [(n, ms, c) for (n, ms, c) in sim.kernel_timing() if c > 0]
+        sim.set_timing(False)
+    kernels = {n: {"avg_us": 1e3 * ms / c, "launches": c, "total_ms": ms} for (n, ms, c) in kt}
+    dom = max(kt, key=lambda t: t[1]) if kt else None
+    algo = ALGO_BYTES.get(w["physics"], {})
+    roof = None
+    if dom and dom[0] in algo:
+        bytes_per_launch = algo[dom[0]] * nodes * S
+        avg_s = dom[1] / dom[2] / 1e3
+        ach = bytes_per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom[0], "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_node": algo[dom[0]]}
+    for n, d in kernels.items():
+        if n in algo:
+            d["algo_GBs"] = round(algo[n] * nodes * S / (d["avg_us"] * 1e-6) / 1e9, 1)
+    step_bytes = STEP_BYTES[w["physics"]]
+    eff = value * 1e6 * step_bytes / 1e9
+
+    if a.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+
+    res = {
+        "metric": "Mcell-updates/s",
+        "value": round(value, 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * el / a.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload_desc(w, S), "nodes": nodes, "shots": S,
+                   "hbm_effective_GBs": round(eff, 1),
+                   "hbm_effective_frac": round(eff / HBM_PEAK_GBS, 4),
+                   "compulsory_bytes_per_cell_step": step_bytes, "finite": finite},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(inputs.config(a.workload, nsteps=a.cpu_sample_steps),
+                                           a.cpu_sample_steps)
+    sim.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * loss.h -- C ABI of the MI355X local spline simulator (LOSS) of arXiv 2301.05127,
+ * "Distributed local spline simulator for wave propagation" (Guo, Li, Xiong).
+ *
+ * The library (libloss.so, HIP for gfx950) owns all device memory.  Plain pointers
+ * and sizes only; no C++ or framework types cross this boundary.  Every function
+ * returns a status (0 = LOSS_OK, < 0 = error) and never throws; loss_last_error()
+ * gives a thread-local message for the last failure.  A handle is not thread safe:
+ * use one handle per thread / HIP stream.
+ *
+ * Memory arguments: `mem` = LOSS_MEM_HOST for host pointers (copied synchronously),
+ * LOSS_MEM_DEVICE for device pointers on the simulation's device (used in stream
+ * order on the simulation's stream; the caller keeps them alive until loss_sync).
+ *
+ * Field layout at the boundary: dense node arrays [z][y][x], x fastest, float32;
+ * a 2-D grid uses axes x and z (n[1] = 0, one y node).  Internally rows are padded.
+ *
+ * Physics (paper Sec. 2):
+ *   acoustic, eq. acoustic_wave:  dv1/dt = -b dsigma/dx, dv3/dt = -b dsigma/dz,
+ *                                 dsigma/dt = -K (dv1/dx + dv3/dz),  K = rho c^2, b = 1/rho;
+ *   elastic velocity-stress (Sec. 2): rho dv_i/dt = d_j sigma_ij + f_i,
+ *                                 dsigma/dt = lambda tr(e) I + 2 mu e,  e = sym grad v,
+ *                                 lambda = rho (Vp^2 - 2 Vs^2), mu = rho Vs^2.
+ * Spatial derivatives (Sec. 3.1-3.2): patched cubic B-splines with the perfectly
+ * matched boundary condition at patch junctions; time (Sec. 3.3): Strang splitting
+ * of the velocity sub-flow (A) and the stress sub-flow (B), A(dt/2) B(dt) A(dt/2).
+ * No absorbing layer: the outer ends use the end mode below.
+ */
+#ifndef LOSS_H
+#define LOSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct loss_sim loss_sim;   /* opaque, library owned */
+typedef int32_t loss_status;
+
+#define LOSS_OK            0
+#define LOSS_EINVAL       -1   /* bad argument (size, index, null pointer, kind) */
+#define LOSS_ENOMEM       -2   /* device or host allocation failed */
+#define LOSS_EHIP         -3   /* a HIP runtime call failed */
+#define LOSS_ESTATE       -4   /* call out of order (e.g. step before set_media) */
+#define LOSS_EUNSUPPORTED -5   /* valid request this build does not implement */
+#define LOSS_EUNSTABLE    -6   /* dt above the stability bound, or a non-finite field */
+
+/* physics */
+#define LOSS_ACOUSTIC 0        /* 2-D (x, z) */
+#define LOSS_ELASTIC  1        /* 3-D (x, y, z) */
+
+/* End rows of the outermost patches:
+ *  NATURAL       the global spline's natural row v~_{-1} - 2 v~_0 + v~_1 = 0 (Sec. 3.1,
+ *                eq. natural_boundary), applied exactly;
+ *  PAPER_STENCIL the truncated one-sided slope stencil that closes the first and last
+ *                patch in Sec. 3.2 (the formulas after eq. PMBC_coeffcients);
+ *  PERIODIC      node N is node 0; every junction, 0 = N included, uses the PMBC built
+ *                from the circulant collocation matrix. */
+#define LOSS_END_NATURAL       0
+#define LOSS_END_PAPER_STENCIL 1
+#define LOSS_END_PERIODIC      2
+
+#define LOSS_MEM_HOST   0
+#define LOSS_MEM_DEVICE 1
+
+/* field ids: acoustic */
+#define LOSS_F_SIGMA 0
+#define LOSS_F_V1    1
+#define LOSS_F_V3    2
+/* field ids: elastic */
+#define LOSS_F_EV1  0
+#define LOSS_F_EV2  1
+#define LOSS_F_EV3  2
+#define LOSS_F_S11  3
+#define LOSS_F_S22  4
+#define LOSS_F_S33  5
+#define LOSS_F_S12  6
+#define LOSS_F_S13  7
+#define LOSS_F_S23  8
+
+/* source kinds (spatial amplitude A(x) times a time function, paper Sec. 4.3) */
+#define LOSS_SRC_PRESSURE  0   /* rate added to sigma (acoustic) or sigma_ii (elastic) */
+#define LOSS_SRC_EXPLOSIVE 1   /* same as PRESSURE */
+#define LOSS_SRC_FORCE_X   2   /* body force f_1: dv1/dt += b f */
+#define LOSS_SRC_FORCE_Y   3
+#define LOSS_SRC_FORCE_Z   4
+
+/* desc.flags */
+#define LOSS_FLAG_NO_GRAPH 1   /* launch every step eagerly instead of replaying a hipGraph */
+
+typedef struct {
+    int32_t physics;      /* LOSS_ACOUSTIC (ndim 2) or LOSS_ELASTIC (ndim 3) */
+    int32_t ndim;         /* 2 or 3 */
+    int64_t n[3];         /* intervals along x, y, z (nodes = n + 1); n[1] = 0 in 2-D */
+    double h[3];          /* node spacing [m] per axis */
+    double dt;            /* time step [s] */
+    int32_t patch[3];     /* patch length M in intervals per axis; the last patch of an
+                             axis takes the remainder n mod M */
+    int32_t halo;         /* n_nb of the PMBC: taps j = -n_nb..n_nb around a junction */
+    int32_t end_mode;     /* LOSS_END_* */
+    int32_t nshots;       /* independent shots stepped together (same grid and media) */
+    int32_t flags;        /* LOSS_FLAG_* */
+    int64_t trace_len;    /* samples kept per receiver trace (0 = no traces) */
+} loss_desc;
+
+/* Create a simulation on the current HIP device.  `hip_stream` is a hipStream_t to
+ * run on (NULL: the library creates its own).  Builds the per-axis PMBC and
+ * tridiagonal factor tables in FP64 on the host (Sec. 3.2: truncated rows of the
+ * inverse of the global collocation matrix) and stores them as float32.
+ * Errors: LOSS_EINVAL for an inconsistent desc (ndim/physics mismatch, M < 1,
+ * n < 2, halo < 1 or > 64, periodic with 2*halo+1 > n), LOSS_ENOMEM, LOSS_EHIP. */
+loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out);
+
+/* Free every resource of the handle (NULL is accepted). */
+loss_status loss_destroy(loss_sim *sim);
+
+/* Media per node (dense [z][y][x]): vp (c_P), vs (c_S; NULL for acoustic), rho.
+ * Derived on the device: acoustic K = rho vp^2, b = 1/rho; elastic lambda, mu, b.
+ * Returns LOSS_EUNSTABLE (media kept) if dt exceeds the bound
+ * 2 h_min / (sqrt(3) sqrt(ndim) max vp) of the Strang scheme with the spline symbol. */
+loss_status loss_set_media(loss_sim *sim, const float *vp, const float *vs, const float *rho,
+                           int32_t mem);
+
+/* Add a source to `shot`.  pos: metres from node 0 along x, y, z.  spread_m > 0: a
+ * Gaussian exp(-d^2 / (2 spread^2)) over nodes within 4 spread, normalised to unit
+ * integral; spread_m == 0: weight 1/h^d at the nearest node.  wavelet (host, nt
+ * samples): stress kinds use wavelet[n] in step n (sample it at t_n + dt/2); forces
+ * use wavelet[k] = f(t_k) in the velocity half steps at t_n and t_{n+1}.  Samples
+ * past nt are zero.  At most 16 sources per shot. */
+loss_status loss_add_source(loss_sim *sim, int32_t shot, const double pos[3], int32_t kind,
+                            const float *wavelet, int64_t nt, double spread_m);
+
+/* Add receivers to `shot`: node_idx (host) = nrec triples (ix, iy, iz).  After every
+ * step n (counted from the last reset) sample n of each trace receives the field
+ * `component` at t_{n+1} (acoustic: LOSS_F_SIGMA only; elastic: any field id),
+ * accumulated in float64.  Replaces earlier receivers of the shot. */
+loss_status loss_add_receivers(loss_sim *sim, int32_t shot, int64_t nrec, const int32_t *node_idx,
+                               int32_t component);
+
+/* Zero every wavefield, trace and the step counter (media and sources are kept). */
+loss_status loss_reset(loss_sim *sim);
+
+/* Advance all shots by nsteps Strang steps, asynchronously on the sim stream.
+ * Per step: stress sub-flow B(dt) then the velocity sub-flow, the two velocity half
+ * steps of consecutive steps fused into one (the state holds the velocity half a
+ * step ahead; loss_get_field returns it at the integer time). */
+loss_status loss_step(loss_sim *sim, int64_t nsteps);
+
+/* Copy one field of one shot at the current integer time into dst (nodes floats). */
+loss_status loss_get_field(loss_sim *sim, int32_t shot, int32_t field, float *dst, int32_t mem);
+
+/* Overwrite one field of one shot at the current integer time. */
+loss_status loss_set_field(loss_sim *sim, int32_t shot, int32_t field, const float *src,
+                           int32_t mem);
+
+/* Receiver traces of one shot: dst = nrec x trace_len doubles, receiver-major. */
+loss_status loss_get_traces(loss_sim *sim, int32_t shot, double *dst, int32_t mem);
+
+/* Hot-path primitive: the patched spline derivative of order 1 (eq.
+ * derivative_approximation) or 2 (second difference of the coefficients) along
+ * axis 0 (x), 1 (y) or 2 (z) of `batch` dense fields in[batch][nodes] -> out.
+ * The PMBC junction slopes come from a halo of n_nb nodes on each side. */
+loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *in, float *out,
+                       int64_t batch, int32_t mem);
+
+/* Adjoint-state gradient (acoustic only).  loss_forward_ckpt resets, runs nsteps
+ * steps from rest recording traces and keeping the state every ckpt_every steps in
+ * device memory.  loss_adjoint then takes the trace residual
+ * residual[shot][rec][n] (float64, n < nsteps) of J = 1/2 sum residual^2 and returns
+ * dJ/dparam summed over shots (float64, nodes), param = LOSS_GRAD_K (bulk modulus)
+ * or LOSS_GRAD_VP (c with rho fixed).  The adjoint applies the exact transpose of
+ * every discrete operator of the fused scheme; forward states are recomputed from
+ * the checkpoints segment by segment. */
+#define LOSS_GRAD_K  0
+#define LOSS_GRAD_VP 1
+loss_status loss_forward_ckpt(loss_sim *sim, int64_t nsteps, int64_t ckpt_every);
+loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, double *grad,
+                         int32_t mem);
+
+/* Wait for all work queued on the sim stream. */
+loss_status loss_sync(loss_sim *sim);
+
+/* Per-kernel timing (for roofline accounting): when on, loss_step launches every
+ * kernel eagerly between HIP events on the sim stream and accumulates each kernel
+ * class's duration.  loss_kernel_timing returns the accumulated milliseconds and
+ * launch count of class `id` and its name; LOSS_EINVAL past the last class. */
+loss_status loss_set_timing(loss_sim *sim, int32_t on);
+loss_status loss_kernel_timing(loss_sim *sim, int32_t id, double *ms, int64_t *launches,
+                               const char **name);
+
+/* Steps taken since the last reset. */
+int64_t loss_current_step(const loss_sim *sim);
+
+const char *loss_status_str(loss_status s);
+const char *loss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

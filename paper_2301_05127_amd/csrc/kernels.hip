@@ -1,0 +1,646 @@
+// HIP kernels (gfx950) of the local spline simulator.
+//
+// Line kernels: one work unit = one patch of one grid line (paper Sec. 3.2: the
+// patches are coupled only through the junction slopes phi).  A unit's nodes
+// [s, e) are split into chunks of C consecutive nodes, one chunk per lane; the
+// closing row e (the next junction, or the natural end N) is handled by the lane
+// that holds e-1.  The tridiagonal solve (LU factors from the axis table) runs as
+// two first-order linear recurrences (forward elimination, back substitution);
+// each lane runs them over its chunk in registers from a zero carry, records the
+// affine map carry_out = A * carry_in + B, and the carries are composed across the
+// unit (wave shuffles for the contiguous x axis, LDS across waves for y and z),
+// then every lane adds A_local * carry_in.  The derivative is fused with the
+// field update (epilogue).
+//
+//   x axis: lanes own C = 4 or 16 consecutive x nodes; G lanes per unit (power of 2).
+//   y, z axes: lanes own one x column each (coalesced), wave w owns chunk w of the
+//             unit along the axis; up to 16 waves per unit.
+#include <hip/hip_runtime.h>
+
+#include "loss_internal.h"
+
+namespace loss {
+
+namespace {
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// PMBC junction slope (eq. PMBC): phi_J = sum_t c_t u[idx_t] along the line.
+__device__ __forceinline__ float pmbc_phi(const AxisDev &ax, int slot, const float *__restrict__ in,
+                                          int64_t base, int64_t stride)
+{
+    const int *ti = ax.tap_idx + (int64_t)slot * ax.ntap;
+    const float *tc = ax.tap_c + (int64_t)slot * ax.ntap;
+    float acc = 0.f;
+    for (int t = 0; t < ax.ntap; ++t) {
+        const int k = ti[t];
+        if (k >= 0) acc = fmaf(tc[t], in[base + (int64_t)k * stride], acc);
+    }
+    return acc;
+}
+
+template <int EPI>
+__device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_t midx, int shot,
+                                         float D)
+{
+    if constexpr (EPI == EPI_STORE) {
+        a.out[0][oidx] = D;
+    } else if constexpr (EPI == EPI_AXPY) {
+        for (int j = 0; j < a.nout; ++j) {
+            const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
+            a.out[j][oidx] = fmaf(a.alpha * c, D, a.out[j][oidx]);
+        }
+    } else if constexpr (EPI == EPI_AXPY_AUX) {
+        const float dv = D + a.aux[oidx];
+        const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
+        a.out[0][oidx] = fmaf(a.alpha * c, dv, a.out[0][oidx]);
+        if (a.div) a.div[(int64_t)shot * a.div_shot_stride + midx] = dv;
+    } else {  // EPI_BASE
+        const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
+        a.out[0][oidx] = fmaf(a.alpha * c, D, a.aux[oidx]);
+    }
+}
+
+// Right-hand side of row i of the solved system for the chunk value layout
+// u[c] = node q-1+c (so node i = q+cc sits at u[cc+1]).
+template <int SOLVE>
+__device__ __forceinline__ float row_rhs(const AxisDev &ax, int i, int s, float um, float u0, float up,
+                                         const float *__restrict__ in, int64_t base, int64_t stride,
+                                         float4 &fac)
+{
+    if constexpr (SOLVE == SOLVE_D1) {
+        fac = ax.lu[i];
+        const float4 rc = ax.rc[i];
+        float r = fmaf(rc.x, um, fmaf(rc.y, u0, rc.z * up));
+        if (rc.w >= 0.f) r = pmbc_phi(ax, (int)rc.w, in, base, stride);
+        return r;
+    } else if constexpr (SOLVE == SOLVE_T1) {
+        fac = ax.luT[i];
+        return u0;
+    } else {  // SOLVE_D2: moment system of the patch starting at s
+        fac = ax.lu2[i];
+        const float ih = 1.f / ax.h;
+        if (i == s) {
+            const float4 l = ax.lu[i];
+            if (l.w == (float)ROW_NATURAL_L) return 0.f;
+            const float phi = pmbc_phi(ax, (int)ax.rc[i].w, in, base, stride);
+            return 6.f * ih * fmaf(up - u0, ih, -phi);
+        }
+        return 6.f * ih * ih * (um - 2.f * u0 + up);
+    }
+}
+
+// Closing row e of a unit: given the eliminated value at e-1, return the solution at e.
+template <int SOLVE>
+__device__ __forceinline__ float closing_row(const AxisDev &ax, int e, float ylast, float ulast,
+                                             float ue, const float *__restrict__ in, int64_t base,
+                                             int64_t stride)
+{
+    if constexpr (SOLVE == SOLVE_D1) {
+        const float4 lu = ax.lu[e];
+        const float4 rc = ax.rc[e];
+        const float r = (rc.w >= 0.f) ? pmbc_phi(ax, (int)rc.w, in, base, stride)
+                                       : fmaf(rc.x, ulast, rc.y * ue);
+        return (r - lu.x * ylast) * lu.y;
+    } else if constexpr (SOLVE == SOLVE_T1) {
+        const float4 lu = ax.luT[e];
+        return (ue - lu.x * ylast) * lu.y;
+    } else {
+        const float2 f = ax.lu2c[e];
+        const float4 l = ax.lu[e];
+        float r = 0.f;
+        if (l.w != (float)ROW_NATURAL_R) {
+            const float ih = 1.f / ax.h;
+            const float phi = pmbc_phi(ax, (int)ax.rc[e].w, in, base, stride);
+            r = 6.f * ih * fmaf(-(ue - ulast), ih, phi);
+        }
+        return (r - f.x * ylast) * f.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x axis (contiguous): G lanes per unit, C nodes per lane, 64/G units per wave.
+// ---------------------------------------------------------------------------
+template <int C, int SOLVE, int EPI>
+__global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunits)
+{
+    const AxisDev &ax = a.ax;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int k = lane & (G - 1);
+    const int grp = lane / G;
+    const int upw = 64 / G;
+    int64_t unit = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wid) * upw + grp;
+    const bool uact = unit < nunits;
+    if (!uact) unit = nunits - 1;
+    const int N = ax.N, M = ax.M, p = ax.p;
+    const int l = (int)(unit % p);
+    const int64_t line = unit / p;
+    const int shot = (int)(line / ((int64_t)a.nz * a.ny));
+    const int64_t base = line * a.pitch;
+    const int64_t mbase = base - (int64_t)shot * a.shot_stride;
+    const int s = l * M;
+    const int e = min(s + M, N);
+    const int q = s + k * C;
+    const float *__restrict__ in = a.in;
+
+    float u[C + 2];
+#pragma unroll
+    for (int c = 0; c < C + 2; ++c) u[c] = in[base + clampi(q - 1 + c, 0, N)];
+
+    float y[C], P[C];
+    float4 fac[C];
+    float yv = 0.f, pv = 1.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int i = min(q + c, N);
+        const float r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, fac[c]);
+        yv = fmaf(-fac[c].x, yv, r);
+        pv = -fac[c].x * pv;
+        y[c] = yv;
+        P[c] = pv;
+    }
+    // compose the forward carries over the unit (inclusive scan of affine maps)
+    float A = pv, B = yv;
+    for (int d = 1; d < G; d <<= 1) {
+        const float Ap = __shfl_up(A, d, G), Bp = __shfl_up(B, d, G);
+        if (k >= d) { B = fmaf(A, Bp, B); A = A * Ap; }
+    }
+    float yin = __shfl_up(B, 1, G);
+    if (k == 0) yin = 0.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
+
+    // closing row
+    const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
+    float we = 0.f;
+    if (k == kc) {
+        float ylast = 0.f, ulast = 0.f, ue = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
+        we = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, 1);
+    }
+    we = __shfl(we, kc, G);
+
+    // back substitution
+    float w[C], Q[C];
+    float wv = 0.f, qv = 1.f;
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        if (q + c < e) {
+            const float inv = fac[c].y, sp = fac[c].z;
+            wv = fmaf(-sp, wv, y[c]) * inv;
+            qv = -sp * inv * qv;
+        }
+        w[c] = wv;
+        Q[c] = qv;
+    }
+    float Qm = qv, Wm = wv;
+    for (int d = 1; d < G; d <<= 1) {
+        const float Qn = __shfl_down(Qm, d, G), Wn = __shfl_down(Wm, d, G);
+        if (k + d < G) { Wm = fmaf(Qm, Wn, Wm); Qm = Qm * Qn; }
+    }
+    float Qx = __shfl_down(Qm, 1, G), Wx = __shfl_down(Wm, 1, G);
+    if (k == G - 1) { Qx = 1.f; Wx = 0.f; }
+    const float wr = fmaf(Qx, we, Wx);
+
+    if (uact) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = q + c;
+            if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, fmaf(Q[c], wr, w[c]));
+        }
+        if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y / z axes (strided): lanes = x columns, wave w = chunk w of C nodes along the axis.
+// ---------------------------------------------------------------------------
+constexpr int kMaxWaves = 16;
+
+template <int C, int SOLVE, int EPI>
+__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
+{
+    __shared__ float sA[kMaxWaves][64], sB[kMaxWaves][64], sQ[kMaxWaves][64], sW[kMaxWaves][64];
+    __shared__ float sWe[64];
+    const AxisDev &ax = a.ax;
+    const int W = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = blockIdx.x * 64 + lane;
+    const bool cact = col < a.nx;
+    const int l = blockIdx.y;
+    const int n_other = (axis == 1) ? a.nz : a.ny;
+    const int shot = blockIdx.z / n_other, o = blockIdx.z % n_other;
+    const int64_t stride = (axis == 1) ? a.pitch : a.plane;
+    const int64_t obase = (axis == 1) ? (int64_t)o * a.plane : (int64_t)o * a.pitch;
+    const int64_t mbase = obase + min(col, a.nx - 1);
+    const int64_t base = (int64_t)shot * a.shot_stride + mbase;
+    const int N = ax.N, M = ax.M;
+    const int s = l * M;
+    const int e = min(s + M, N);
+    const int q = s + wv * C;
+    const float *__restrict__ in = a.in;
+
+    float u[C + 2];
+#pragma unroll
+    for (int c = 0; c < C + 2; ++c) u[c] = in[base + (int64_t)clampi(q - 1 + c, 0, N) * stride];
+
+    float y[C], P[C];
+    float4 fac[C];
+    float yv = 0.f, pv = 1.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int i = min(q + c, N);
+        const float r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, stride, fac[c]);
+        yv = fmaf(-fac[c].x, yv, r);
+        pv = -fac[c].x * pv;
+        y[c] = yv;
+        P[c] = pv;
+    }
+    sA[wv][lane] = pv;
+    sB[wv][lane] = yv;
+    __syncthreads();
+    float yin = 0.f;
+    for (int j = 0; j < wv; ++j) yin = fmaf(sA[j][lane], yin, sB[j][lane]);
+#pragma unroll
+    for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
+
+    const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
+    if (wv == kc) {
+        float ylast = 0.f, ulast = 0.f, ue = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
+        sWe[lane] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, stride);
+    }
+
+    float w[C], Q[C];
+    float wvv = 0.f, qv = 1.f;
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        if (q + c < e) {
+            const float inv = fac[c].y, sp = fac[c].z;
+            wvv = fmaf(-sp, wvv, y[c]) * inv;
+            qv = -sp * inv * qv;
+        }
+        w[c] = wvv;
+        Q[c] = qv;
+    }
+    sQ[wv][lane] = qv;
+    sW[wv][lane] = wvv;
+    __syncthreads();
+    const float we = sWe[lane];
+    float wr = we;
+    for (int j = W - 1; j > wv; --j) wr = fmaf(sQ[j][lane], wr, sW[j][lane]);
+
+    if (cact) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = q + c;
+            if (i < e)
+                epilogue<EPI>(a, base + (int64_t)i * stride, mbase + (int64_t)i * stride, shot,
+                              fmaf(Q[c], wr, w[c]));
+        }
+        if (e == N && wv == kc)
+            epilogue<EPI>(a, base + (int64_t)N * stride, mbase + (int64_t)N * stride, shot, we);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint phase 2: out_j = (G^T y)_j, with y at junction rows recovered from the
+// junction row of T^T:  y_J = z_J - subT_J y_{J-1} - supT_J y_{J+1}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float adj_y(const AxisDev &ax, const float *__restrict__ Y,
+                                       const float *__restrict__ Z, int64_t lb, int64_t stride, int i)
+{
+    const float4 lu = ax.lu[i];
+    if (lu.w != (float)ROW_JUNCTION) return Y[lb + (int64_t)i * stride];
+    const float4 t = ax.luT[i];
+    float v = Z[lb + (int64_t)i * stride];
+    if (i > 0) v = fmaf(-t.w, Y[lb + (int64_t)(i - 1) * stride], v);
+    if (i < ax.N) v = fmaf(-t.z, Y[lb + (int64_t)(i + 1) * stride], v);
+    return v;
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_adj_gather(LineArgs a, const float *__restrict__ Y, int axis,
+                                                    int64_t total)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const AxisDev &ax = a.ax;
+    const int x = (int)(idx % a.nx);
+    int64_t r = idx / a.nx;
+    const int yy = (int)(r % a.ny);
+    r /= a.ny;
+    const int z = (int)(r % a.nz);
+    const int shot = (int)(r / a.nz);
+    const int64_t midx = (int64_t)z * a.plane + (int64_t)yy * a.pitch + x;
+    const int64_t oidx = (int64_t)shot * a.shot_stride + midx;
+    const int j = axis == 0 ? x : (axis == 1 ? yy : z);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? a.pitch : a.plane);
+    const int64_t lb = oidx - (int64_t)j * stride;
+    const float *Z = a.in;
+    float out = 0.f;
+    const float4 rc = ax.rc[j];
+    out = rc.y * adj_y(ax, Y, Z, lb, stride, j);
+    if (j > 0) out = fmaf(ax.rc[j - 1].z, adj_y(ax, Y, Z, lb, stride, j - 1), out);
+    if (j < ax.N) out = fmaf(ax.rc[j + 1].x, adj_y(ax, Y, Z, lb, stride, j + 1), out);
+    const int *gn = ax.g_node + (int64_t)j * kMaxGatherTaps;
+    const float *gc = ax.g_c + (int64_t)j * kMaxGatherTaps;
+#pragma unroll
+    for (int t = 0; t < kMaxGatherTaps; ++t) {
+        const int J = gn[t];
+        if (J >= 0) out = fmaf(gc[t], adj_y(ax, Y, Z, lb, stride, J), out);
+    }
+    epilogue<EPI>(a, oidx, midx, shot, out);
+}
+
+// ---------------------------------------------------------------------------
+// sources, receivers, bookkeeping
+// ---------------------------------------------------------------------------
+__global__ void k_inject(const SrcDev *__restrict__ src, float *const *fields, const float *__restrict__ b,
+                         const float *__restrict__ wpool, const float *__restrict__ wavpool,
+                         int64_t shot_stride, int64_t pitch, int64_t plane, const int64_t *d_step,
+                         int time_offset, float scale, int want_force)
+{
+    const SrcDev sd = src[blockIdx.x];
+    if (sd.force != want_force) return;
+    const int64_t n = *d_step + time_offset;
+    if (n < 0 || n >= sd.nt) return;
+    const float amp = scale * wavpool[sd.wav_off + n];
+    const int tot = sd.bx * sd.by * sd.bz;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        const int ix = t % sd.bx, iy = (t / sd.bx) % sd.by, iz = t / (sd.bx * sd.by);
+        const int64_t midx = (int64_t)(sd.z0 + iz) * plane + (int64_t)(sd.y0 + iy) * pitch + (sd.x0 + ix);
+        float v = amp * wpool[sd.w_off + t];
+        if (sd.force) v *= b[midx];
+        for (int f = 0; f < sd.nfield; ++f) {
+            float *F = fields[sd.field0 + f];
+            F[(int64_t)sd.shot * shot_stride + midx] += v;
+        }
+    }
+}
+
+__global__ void k_record(const RecDev *__restrict__ rec, int nrec, const float *const *fields,
+                         int64_t shot_stride, double *traces, const int64_t *d_step, int64_t trace_len,
+                         float weight, int accumulate)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const int64_t n = *d_step;
+    if (n >= trace_len) return;
+    const RecDev rd = rec[r];
+    const double v = (double)weight * (double)fields[rd.comp][(int64_t)rd.shot * shot_stride + rd.node];
+    double *t = traces + rd.trace_off + n;
+    *t = accumulate ? *t + v : v;
+}
+
+__global__ void k_advance(int64_t *d_step) { *d_step += 1; }
+
+__global__ void k_pad_copy(const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, int nz,
+                           int64_t pitch, int to_padded, int64_t total)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int x = (int)(idx % nx);
+    const int64_t row = idx / nx;  // (batch, z, y) rows
+    const int64_t p = row * pitch + x;
+    if (to_padded) dst[p] = src[idx];
+    else dst[idx] = src[p];
+}
+
+__global__ void k_media(const float *__restrict__ vp, const float *__restrict__ vs,
+                        const float *__restrict__ rho, float *m0, float *m1, float *m2, float *m3,
+                        int physics, int nx, int64_t pitch, int64_t total)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int x = (int)(idx % nx);
+    const int64_t p = (idx / nx) * pitch + x;
+    const double r = rho[idx], c = vp[idx];
+    if (physics == 0) {
+        m0[p] = (float)(r * c * c);   // K
+        m1[p] = (float)(1.0 / r);     // b
+    } else {
+        const double cs = vs[idx];
+        const double mu = r * cs * cs, lam = r * c * c - 2.0 * mu;
+        m0[p] = (float)lam;
+        m1[p] = (float)mu;
+        m2[p] = (float)(lam + 2.0 * mu);
+        m3[p] = (float)(1.0 / r);
+    }
+}
+
+__global__ void k_fill(float *p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_axpby(float *y, const float *x, float a, float b, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = fmaf(a, x[i], b * y[i]);
+}
+
+// g[node] += scale * sum_shots lam[shot][node] * div[shot][node], fixed shot order.
+__global__ void k_grad_accum(double *g, const float *__restrict__ lam, const float *__restrict__ div,
+                             float scale, int S, int64_t shot_stride, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s)
+        acc += (double)lam[(int64_t)s * shot_stride + i] * (double)div[(int64_t)s * shot_stride + i];
+    g[i] += (double)scale * acc;
+}
+
+__global__ void k_grad_unpad(const double *gp, double *g, int nx, int64_t pitch, const float *vp,
+                             const float *rho, int param, int64_t total)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int x = (int)(idx % nx);
+    const int64_t p = (idx / nx) * pitch + x;
+    double v = gp[p];
+    if (param == 1) v *= 2.0 * (double)rho[idx] * (double)vp[idx];   // dK/dc = 2 rho c
+    g[idx] = v;
+}
+
+__global__ void k_nonfinite(const float *p, int64_t n, int *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(p[i])) *flag = 1;
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int C, int SOLVE>
+hipError_t dispatch_x(int epi, const LineArgs &a, hipStream_t st)
+{
+    const int M = a.ax.M;
+    int G = 1;
+    while (G * C < M) G <<= 1;
+    if (G > 64) return hipErrorInvalidValue;
+    const int64_t lines = (int64_t)a.S * a.nz * a.ny;
+    const int64_t nunits = lines * a.ax.p;
+    const int threads = 256;
+    const int64_t units_per_block = (threads / 64) * (64 / G);
+    const unsigned blocks = nblk(nunits, (int)units_per_block);
+    switch (epi) {
+    case EPI_STORE: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_STORE>), blocks, threads, 0, st, a, G, nunits); break;
+    case EPI_AXPY: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_AXPY>), blocks, threads, 0, st, a, G, nunits); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_AXPY_AUX>), blocks, threads, 0, st, a, G, nunits); break;
+    case EPI_BASE: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_BASE>), blocks, threads, 0, st, a, G, nunits); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int C, int SOLVE>
+hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
+{
+    const int M = a.ax.M;
+    const int W = (M + C - 1) / C;
+    if (W > kMaxWaves) return hipErrorInvalidValue;
+    const int n_other = axis == 1 ? a.nz : a.ny;
+    dim3 grid((a.nx + 63) / 64, a.ax.p, a.S * n_other);
+    const int threads = 64 * W;
+    switch (epi) {
+    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, 0, st, a, axis); break;
+    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, 0, st, a, axis); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, 0, st, a, axis); break;
+    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, 0, st, a, axis); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int SOLVE>
+hipError_t dispatch_solve(int axis, int epi, const LineArgs &a, hipStream_t st)
+{
+    const int M = a.ax.M;
+    if (axis == 0) {
+        if (M <= 256) return dispatch_x<4, SOLVE>(epi, a, st);
+        if (M <= 1024) return dispatch_x<16, SOLVE>(epi, a, st);
+        return hipErrorInvalidValue;
+    }
+    if (M <= 16 * kMaxWaves) return dispatch_s<16, SOLVE>(axis, epi, a, st);
+    if (M <= 64 * kMaxWaves) return dispatch_s<64, SOLVE>(axis, epi, a, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_line(int axis, int solve, int epi, const LineArgs &a, hipStream_t st)
+{
+    switch (solve) {
+    case SOLVE_D1: return dispatch_solve<SOLVE_D1>(axis, epi, a, st);
+    case SOLVE_D2: return dispatch_solve<SOLVE_D2>(axis, epi, a, st);
+    case SOLVE_T1: return dispatch_solve<SOLVE_T1>(axis, epi, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.S * a.nz * a.ny * a.nx;
+    const unsigned blocks = nblk(total, 256);
+    switch (epi) {
+    case EPI_STORE: hipLaunchKernelGGL(k_adj_gather<EPI_STORE>, blocks, 256, 0, st, a, Y, axis, total); break;
+    case EPI_AXPY: hipLaunchKernelGGL(k_adj_gather<EPI_AXPY>, blocks, 256, 0, st, a, Y, axis, total); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL(k_adj_gather<EPI_AXPY_AUX>, blocks, 256, 0, st, a, Y, axis, total); break;
+    case EPI_BASE: hipLaunchKernelGGL(k_adj_gather<EPI_BASE>, blocks, 256, 0, st, a, Y, axis, total); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_inject(const SrcDev *src, int nsrc, float *const *fields, const float *b,
+                         const float *wpool, const float *wavpool, int64_t shot_stride, int64_t pitch,
+                         int64_t plane, const int64_t *d_step, int time_offset, float scale,
+                         int want_force, hipStream_t st)
+{
+    if (nsrc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_inject, nsrc, 256, 0, st, src, fields, b, wpool, wavpool, shot_stride, pitch,
+                       plane, d_step, time_offset, scale, want_force);
+    return hipGetLastError();
+}
+
+hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields, int64_t shot_stride,
+                         double *traces, const int64_t *d_step, int64_t trace_len, float weight,
+                         int accumulate, hipStream_t st)
+{
+    if (nrec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_record, nblk(nrec, 256), 256, 0, st, rec, nrec, fields, shot_stride, traces,
+                       d_step, trace_len, weight, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t *d_step, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance, 1, 1, 0, st, d_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_copy(const float *src, float *dst, int nx, int rows, int64_t pitch, int to_padded,
+                           hipStream_t st)
+{
+    const int64_t total = (int64_t)rows * nx;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_copy, nblk(total, 256), 256, 0, st, src, dst, nx, 0, 0, pitch, to_padded,
+                       total);
+    return hipGetLastError();
+}
+
+hipError_t launch_media(const float *vp, const float *vs, const float *rho, float *const *media,
+                        int physics, int nx, int rows, int64_t pitch, hipStream_t st)
+{
+    const int64_t total = (int64_t)rows * nx;
+    hipLaunchKernelGGL(k_media, nblk(total, 256), 256, 0, st, vp, vs, rho, media[0], media[1],
+                       physics ? media[2] : nullptr, physics ? media[3] : nullptr, physics, nx, pitch,
+                       total);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, nblk(n, 256), 256, 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(float *y, const float *x, float a, float b, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpby, nblk(n, 256), 256, 0, st, y, x, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_accum(double *g, const float *lam, const float *div, float scale, int S,
+                             int64_t shot_stride, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grad_accum, nblk(n, 256), 256, 0, st, g, lam, div, scale, S, shot_stride, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_unpad(const double *gp, double *g, int nx, int rows, int64_t pitch, const float *vp,
+                             const float *rho, int param, hipStream_t st)
+{
+    const int64_t total = (int64_t)rows * nx;
+    hipLaunchKernelGGL(k_grad_unpad, nblk(total, 256), 256, 0, st, gp, g, nx, pitch, vp, rho, param, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const float *p, int64_t n, int *flag, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nonfinite, nblk(n, 256), 256, 0, st, p, n, flag);
+    return hipGetLastError();
+}
+
+}  // namespace loss

@@ -1,0 +1,972 @@
+// C ABI of include/loss.h: buffer ownership, table upload, step orchestration,
+// hipGraph capture and replay, sources, receivers, the adjoint driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/loss.h"
+#include "loss_internal.h"
+
+using namespace loss;
+
+namespace {
+
+thread_local std::string g_err;
+
+loss_status fail(loss_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess)                                                          \
+            return fail(LOSS_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+struct SrcHost {
+    int kind;
+    double pos[3];
+    double spread;
+    std::vector<float> wavelet;
+};
+
+struct RecHost {
+    std::vector<int32_t> idx;  // nrec * 3
+    int comp = 0;
+};
+
+// Kernel classes reported by loss_kernel_timing.
+enum KClass {
+    KC_STRESS_X, KC_STRESS_Y, KC_STRESS_Z, KC_VEL_X, KC_VEL_Y, KC_VEL_Z, KC_SOURCE, KC_RECEIVER,
+    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_COUNT
+};
+const char *kKClassName[KC_COUNT] = {
+    "stress_line_x", "stress_line_y", "stress_line_z", "velocity_line_x", "velocity_line_y",
+    "velocity_line_z", "source_inject", "receiver_record", "step_advance", "adjoint_line_solve",
+    "adjoint_gather", "gradient_accumulate"};
+
+}  // namespace
+
+struct loss_sim {
+    loss_desc d{};
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    int nf = 0, S = 0;
+    int nx = 0, ny = 0, nz = 0;
+    int64_t pitch = 0, plane = 0, shot_stride = 0, nodes = 0;
+    std::vector<void *> allocs;
+    std::vector<float *> f;        // nf fields [S][nz][ny][pitch]
+    std::vector<float *> med;      // acoustic K, b; elastic lambda, mu, lambda+2mu, b
+    float *tmp[3] = {nullptr, nullptr, nullptr};
+    float **d_fields = nullptr;    // device copy of f
+    float **d_tmpfields = nullptr; // device pointer table used for unfused velocity output
+    AxisHost axh[3];
+    AxisDev axd[3]{};
+    bool media_set = false;
+    bool fused = false;
+    // sources
+    std::vector<std::vector<SrcHost>> src;
+    bool src_dirty = true;
+    SrcDev *d_src = nullptr;
+    int nsrc = 0;
+    float *d_wpool = nullptr, *d_wavpool = nullptr;
+    // receivers
+    std::vector<RecHost> rec;
+    bool rec_dirty = true;
+    RecDev *d_rec = nullptr;
+    int nrec_total = 0;
+    bool rec_has_vel = false, rec_has_stress = false;
+    RecDev *d_rec_vel = nullptr, *d_rec_str = nullptr;
+    int nrec_vel = 0, nrec_str = 0;
+    std::vector<int64_t> rec_off;  // per shot trace offset
+    double *traces = nullptr;
+    int64_t trace_total = 0;
+    // step counter
+    int64_t *d_step = nullptr;
+    int64_t step = 0;
+    // graphs
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0;
+    // timing
+    bool timing = false;
+    double kms[KC_COUNT] = {0};
+    int64_t kcount[KC_COUNT] = {0};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // adjoint
+    std::vector<float *> ckpt;     // checkpoint states (nf fields each, S shots)
+    int64_t ck_every = 0, ck_steps = 0;
+    float *divstore = nullptr;     // [ck_every][S][shot_stride]
+    double *grad_pad = nullptr;
+    float *d_vp = nullptr, *d_rho = nullptr;   // dense copies of the media for the gradient map
+
+    template <class T>
+    loss_status alloc(T **p, size_t count)
+    {
+        void *q = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) return fail(LOSS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(q);
+        *p = (T *)q;
+        return LOSS_OK;
+    }
+    void release(void *p)
+    {
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) {
+            (void)hipFree(p);
+            allocs.erase(it);
+        }
+    }
+};
+
+namespace {
+
+int64_t field_elems(const loss_sim *s) { return (int64_t)s->S * s->shot_stride; }
+
+LineArgs base_args(const loss_sim *s, int axis)
+{
+    LineArgs a{};
+    a.S = s->S;
+    a.nx = s->nx; a.ny = s->ny; a.nz = s->nz;
+    a.pitch = s->pitch; a.plane = s->plane; a.shot_stride = s->shot_stride;
+    a.ax = s->axd[axis];
+    a.nout = 1;
+    return a;
+}
+
+// 3-D axis index of the grid axis for a 2-D acoustic grid: (x, z) -> (0, 2).
+int grid_axis_count(const loss_sim *s) { return s->d.ndim; }
+
+loss_status timed_begin(loss_sim *s)
+{
+    if (s->timing) HIPCHK(hipEventRecord(s->ev0, s->st));
+    return LOSS_OK;
+}
+
+loss_status timed_end(loss_sim *s, int kc)
+{
+    if (!s->timing) return LOSS_OK;
+    HIPCHK(hipEventRecord(s->ev1, s->st));
+    HIPCHK(hipEventSynchronize(s->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->kms[kc] += ms;
+    s->kcount[kc] += 1;
+    return LOSS_OK;
+}
+
+loss_status run_line(loss_sim *s, int kc, int axis, int solve, int epi, const LineArgs &a)
+{
+    loss_status r = timed_begin(s);
+    if (r) return r;
+    hipError_t e = launch_line(axis, solve, epi, a, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("line kernel launch: ") + hipGetErrorString(e));
+    return timed_end(s, kc);
+}
+
+// derivative of field `in` along axis, out[j] += alpha * coef[j] * D
+loss_status deriv_axpy(loss_sim *s, int kc, int axis, const float *in, float alpha, int nout,
+                       float *const *out, const float *const *coef)
+{
+    LineArgs a = base_args(s, axis);
+    a.in = in;
+    a.alpha = alpha;
+    a.nout = nout;
+    for (int j = 0; j < nout; ++j) { a.out[j] = out[j]; a.coef[j] = coef[j]; }
+    return run_line(s, kc, axis, SOLVE_D1, EPI_AXPY, a);
+}
+
+loss_status inject(loss_sim *s, float **fields_dev, int time_offset, float scale, int want_force)
+{
+    if (s->nsrc == 0) return LOSS_OK;
+    loss_status r = timed_begin(s);
+    if (r) return r;
+    const float *b = s->med.back();
+    hipError_t e = launch_inject(s->d_src, s->nsrc, fields_dev, b, s->d_wpool, s->d_wavpool, s->shot_stride,
+                                 s->pitch, s->plane, s->d_step, time_offset, scale * (float)s->d.dt,
+                                 want_force, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("inject: ") + hipGetErrorString(e));
+    return timed_end(s, KC_SOURCE);
+}
+
+loss_status record(loss_sim *s, const RecDev *rec, int nrec, float weight, int accumulate)
+{
+    if (nrec == 0 || s->d.trace_len == 0) return LOSS_OK;
+    loss_status r = timed_begin(s);
+    if (r) return r;
+    hipError_t e = launch_record(rec, nrec, s->d_fields, s->shot_stride, s->traces, s->d_step,
+                                 s->d.trace_len, weight, accumulate, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("record: ") + hipGetErrorString(e));
+    return timed_end(s, KC_RECEIVER);
+}
+
+// ---- velocity sub-flow (A) over alpha_dt with the stress frozen -------------
+// acoustic: v1 -= a b dsigma/dx, v3 -= a b dsigma/dz ; elastic: v_i += a b d_j sigma_ij
+// `vel` are the velocity destinations (state or a temporary), `base` optional source
+// for EPI_BASE on the first pass of each component.
+loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const float *const *base)
+{
+    const float *b = s->med.back();
+    loss_status r;
+    if (s->d.physics == LOSS_ACOUSTIC) {
+        const float *sig = s->f[LOSS_F_SIGMA];
+        for (int c = 0; c < 2; ++c) {
+            const int axis = c == 0 ? 0 : 2;
+            LineArgs a = base_args(s, axis);
+            a.in = sig;
+            a.alpha = -a_dt;
+            a.out[0] = vel[c];
+            a.coef[0] = b;
+            int epi = EPI_AXPY;
+            if (base) { a.aux = base[c]; epi = EPI_BASE; }
+            r = run_line(s, c == 0 ? KC_VEL_X : KC_VEL_Z, axis, SOLVE_D1, epi, a);
+            if (r) return r;
+        }
+        return LOSS_OK;
+    }
+    // elastic: component i gets d_x sigma_{i1} + d_y sigma_{i2} + d_z sigma_{i3}
+    static const int sidx[3][3] = {{LOSS_F_S11, LOSS_F_S12, LOSS_F_S13},
+                                   {LOSS_F_S12, LOSS_F_S22, LOSS_F_S23},
+                                   {LOSS_F_S13, LOSS_F_S23, LOSS_F_S33}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            LineArgs a = base_args(s, j);
+            a.in = s->f[sidx[i][j]];
+            a.alpha = a_dt;
+            a.out[0] = vel[i];
+            a.coef[0] = b;
+            int epi = EPI_AXPY;
+            if (base && j == 0) { a.aux = base[i]; epi = EPI_BASE; }
+            r = run_line(s, KC_VEL_X + j, j, SOLVE_D1, epi, a);
+            if (r) return r;
+        }
+    return LOSS_OK;
+}
+
+// ---- stress sub-flow (B) over dt with the velocity frozen --------------------
+loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
+{
+    const float dt = (float)s->d.dt;
+    loss_status r;
+    if (s->d.physics == LOSS_ACOUSTIC) {
+        // T = d v1/dx ; sigma -= dt K (T + d v3/dz)
+        LineArgs a = base_args(s, 0);
+        a.in = s->f[LOSS_F_V1];
+        a.out[0] = s->tmp[0];
+        r = run_line(s, KC_STRESS_X, 0, SOLVE_D1, EPI_STORE, a);
+        if (r) return r;
+        LineArgs c = base_args(s, 2);
+        c.in = s->f[LOSS_F_V3];
+        c.out[0] = s->f[LOSS_F_SIGMA];
+        c.coef[0] = s->med[0];
+        c.aux = s->tmp[0];
+        c.alpha = -dt;
+        c.div = div_store;
+        c.div_shot_stride = div_shot_stride;
+        return run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_AXPY_AUX, c);
+    }
+    float *const *F = s->f.data();
+    const float *lam = s->med[0], *mu = s->med[1], *l2m = s->med[2];
+    // normal components from d_i v_i
+    for (int i = 0; i < 3; ++i) {
+        float *out[3] = {F[LOSS_F_S11], F[LOSS_F_S22], F[LOSS_F_S33]};
+        const float *coef[3] = {lam, lam, lam};
+        coef[i] = l2m;
+        r = deriv_axpy(s, KC_STRESS_X + i, i, F[LOSS_F_EV1 + i], dt, 3, out, coef);
+        if (r) return r;
+    }
+    // shear components: sigma_ij += dt mu (d_i v_j + d_j v_i)
+    static const int sh[3][3] = {{LOSS_F_S12, 0, 1}, {LOSS_F_S13, 0, 2}, {LOSS_F_S23, 1, 2}};
+    for (int k = 0; k < 3; ++k) {
+        const int sij = sh[k][0], i = sh[k][1], j = sh[k][2];
+        float *out[1] = {F[sij]};
+        const float *coef[1] = {mu};
+        r = deriv_axpy(s, KC_STRESS_X + i, i, F[LOSS_F_EV1 + j], dt, 1, out, coef);
+        if (r) return r;
+        r = deriv_axpy(s, KC_STRESS_X + j, j, F[LOSS_F_EV1 + i], dt, 1, out, coef);
+        if (r) return r;
+    }
+    return LOSS_OK;
+}
+
+loss_status upload_sources(loss_sim *s)
+{
+    if (!s->src_dirty) return LOSS_OK;
+    std::vector<SrcDev> sd;
+    std::vector<float> wpool, wavpool;
+    const int nax = s->d.ndim;
+    const int axes[3] = {0, nax == 3 ? 1 : 2, 2};
+    for (int shot = 0; shot < s->S; ++shot)
+        for (const SrcHost &h : s->src[shot]) {
+            SrcDev d{};
+            d.shot = shot;
+            d.kind = h.kind;
+            d.force = h.kind >= LOSS_SRC_FORCE_X;
+            if (d.force) {
+                int comp = h.kind - LOSS_SRC_FORCE_X;   // 0 x, 1 y, 2 z
+                if (s->d.physics == LOSS_ACOUSTIC) d.field0 = comp == 0 ? LOSS_F_V1 : LOSS_F_V3;
+                else d.field0 = LOSS_F_EV1 + comp;
+                d.nfield = 1;
+            } else if (s->d.physics == LOSS_ACOUSTIC) {
+                d.field0 = LOSS_F_SIGMA; d.nfield = 1;
+            } else {
+                d.field0 = LOSS_F_S11; d.nfield = 3;
+            }
+            // footprint box and Gaussian weights (unit integral)
+            int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            double hd = 1.0;
+            for (int q = 0; q < nax; ++q) {
+                const int ax = axes[q];
+                const double hh = s->d.h[ax];
+                hd *= hh;
+                int c = (int)std::floor(h.pos[ax] / hh + 0.5);
+                c = std::max(0, std::min((int)s->d.n[ax], c));
+                int rad = h.spread > 0 ? (int)std::ceil(4.0 * h.spread / hh) : 0;
+                lo[ax] = std::max(0, c - rad);
+                hi[ax] = std::min((int)s->d.n[ax], c + rad);
+            }
+            d.x0 = lo[0]; d.y0 = lo[1]; d.z0 = lo[2];
+            d.bx = hi[0] - lo[0] + 1; d.by = hi[1] - lo[1] + 1; d.bz = hi[2] - lo[2] + 1;
+            std::vector<double> w((size_t)d.bx * d.by * d.bz);
+            double sum = 0.0;
+            for (int iz = 0; iz < d.bz; ++iz)
+                for (int iy = 0; iy < d.by; ++iy)
+                    for (int ix = 0; ix < d.bx; ++ix) {
+                        double q = 1.0;
+                        if (h.spread > 0) {
+                            const double dx = (lo[0] + ix) * s->d.h[0] - h.pos[0];
+                            const double dy = nax == 3 ? (lo[1] + iy) * s->d.h[1] - h.pos[1] : 0.0;
+                            const double dz = (lo[2] + iz) * s->d.h[2] - h.pos[2];
+                            q = std::exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * h.spread * h.spread));
+                        }
+                        w[((size_t)iz * d.by + iy) * d.bx + ix] = q;
+                        sum += q;
+                    }
+            d.w_off = (int64_t)wpool.size();
+            for (double q : w) wpool.push_back((float)(q / (sum * hd)));
+            d.wav_off = (int64_t)wavpool.size();
+            d.nt = (int)h.wavelet.size();
+            wavpool.insert(wavpool.end(), h.wavelet.begin(), h.wavelet.end());
+            sd.push_back(d);
+        }
+    if (s->d_src) { s->release(s->d_src); s->d_src = nullptr; }
+    if (s->d_wpool) { s->release(s->d_wpool); s->d_wpool = nullptr; }
+    if (s->d_wavpool) { s->release(s->d_wavpool); s->d_wavpool = nullptr; }
+    s->nsrc = (int)sd.size();
+    if (s->nsrc) {
+        loss_status r;
+        if ((r = s->alloc(&s->d_src, sd.size()))) return r;
+        if ((r = s->alloc(&s->d_wpool, wpool.size()))) return r;
+        if ((r = s->alloc(&s->d_wavpool, wavpool.size()))) return r;
+        HIPCHK(hipMemcpy(s->d_src, sd.data(), sd.size() * sizeof(SrcDev), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s->d_wpool, wpool.data(), wpool.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s->d_wavpool, wavpool.data(), wavpool.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    s->src_dirty = false;
+    return LOSS_OK;
+}
+
+bool is_velocity(const loss_sim *s, int field)
+{
+    if (s->d.physics == LOSS_ACOUSTIC) return field == LOSS_F_V1 || field == LOSS_F_V3;
+    return field <= LOSS_F_EV3;
+}
+
+loss_status upload_receivers(loss_sim *s)
+{
+    if (!s->rec_dirty) return LOSS_OK;
+    std::vector<RecDev> vel, str;
+    s->rec_off.assign(s->S, 0);
+    int64_t off = 0;
+    for (int shot = 0; shot < s->S; ++shot) {
+        const RecHost &rh = s->rec[shot];
+        s->rec_off[shot] = off;
+        const int64_t nr = (int64_t)rh.idx.size() / 3;
+        for (int64_t r = 0; r < nr; ++r) {
+            RecDev d{};
+            d.shot = shot;
+            d.comp = rh.comp;
+            const int64_t ix = rh.idx[3 * r], iy = rh.idx[3 * r + 1], iz = rh.idx[3 * r + 2];
+            d.node = iz * s->plane + iy * s->pitch + ix;
+            d.trace_off = off + r * s->d.trace_len;
+            (is_velocity(s, rh.comp) ? vel : str).push_back(d);
+        }
+        off += nr * s->d.trace_len;
+    }
+    if (s->d_rec_vel) { s->release(s->d_rec_vel); s->d_rec_vel = nullptr; }
+    if (s->d_rec_str) { s->release(s->d_rec_str); s->d_rec_str = nullptr; }
+    if (s->traces) { s->release(s->traces); s->traces = nullptr; }
+    loss_status r;
+    s->nrec_vel = (int)vel.size();
+    s->nrec_str = (int)str.size();
+    if (s->nrec_vel) {
+        if ((r = s->alloc(&s->d_rec_vel, vel.size()))) return r;
+        HIPCHK(hipMemcpy(s->d_rec_vel, vel.data(), vel.size() * sizeof(RecDev), hipMemcpyHostToDevice));
+    }
+    if (s->nrec_str) {
+        if ((r = s->alloc(&s->d_rec_str, str.size()))) return r;
+        HIPCHK(hipMemcpy(s->d_rec_str, str.data(), str.size() * sizeof(RecDev), hipMemcpyHostToDevice));
+    }
+    s->trace_total = off;
+    if ((r = s->alloc(&s->traces, std::max<int64_t>(off, 1)))) return r;
+    HIPCHK(hipMemsetAsync(s->traces, 0, sizeof(double) * std::max<int64_t>(off, 1), s->st));
+    s->rec_dirty = false;
+    return LOSS_OK;
+}
+
+void drop_graph(loss_sim *s)
+{
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+    s->gsteps = 0;
+}
+
+// Convert (v at integer time) -> fused state (u half a step ahead), in place.
+loss_status fuse(loss_sim *s)
+{
+    if (s->fused) return LOSS_OK;
+    const float hdt = 0.5f * (float)s->d.dt;
+    std::vector<float *> vel;
+    if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
+    else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
+    loss_status r = velocity_stage(s, hdt, vel.data(), nullptr);
+    if (r) return r;
+    r = inject(s, s->d_fields, 0, 0.5f, 1);
+    if (r) return r;
+    s->fused = true;
+    return LOSS_OK;
+}
+
+// Velocity at the integer time from the fused state: v = u - (A half step), into tmp.
+// Returns, per velocity component, the pointer that holds it.
+loss_status unfused_velocity(loss_sim *s, std::vector<float *> &vout)
+{
+    std::vector<float *> vel;
+    if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
+    else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
+    if (!s->fused) { vout = vel; return LOSS_OK; }
+    const int nv = (int)vel.size();
+    std::vector<float *> dst(s->tmp, s->tmp + nv);
+    std::vector<const float *> base(vel.begin(), vel.end());
+    loss_status r = velocity_stage(s, -0.5f * (float)s->d.dt, dst.data(), base.data());
+    if (r) return r;
+    if (s->nsrc) {
+        // forces: subtract the half-step force term, on a pointer table aimed at tmp
+        std::vector<float *> tab(s->f.begin(), s->f.end());
+        for (int c = 0; c < nv; ++c) {
+            int fid = s->d.physics == LOSS_ACOUSTIC ? (c == 0 ? LOSS_F_V1 : LOSS_F_V3) : LOSS_F_EV1 + c;
+            tab[fid] = dst[c];
+        }
+        HIPCHK(hipMemcpyAsync(s->d_tmpfields, tab.data(), sizeof(float *) * s->nf, hipMemcpyHostToDevice, s->st));
+        r = inject(s, s->d_tmpfields, 0, -0.5f, 1);
+        if (r) return r;
+    }
+    vout = dst;
+    return LOSS_OK;
+}
+
+// Undo the fusion in place (before a user overwrites a field).
+loss_status unfuse_in_place(loss_sim *s)
+{
+    if (!s->fused) return LOSS_OK;
+    std::vector<float *> v;
+    loss_status r = unfused_velocity(s, v);
+    if (r) return r;
+    const int nv = (int)v.size();
+    for (int c = 0; c < nv; ++c) {
+        int fid = s->d.physics == LOSS_ACOUSTIC ? (c == 0 ? LOSS_F_V1 : LOSS_F_V3) : LOSS_F_EV1 + c;
+        HIPCHK(hipMemcpyAsync(s->f[fid], v[c], sizeof(float) * field_elems(s), hipMemcpyDeviceToDevice, s->st));
+    }
+    s->fused = false;
+    drop_graph(s);
+    return LOSS_OK;
+}
+
+// One fused step: B(dt), sources, stress receivers, A(dt) [two half steps], forces,
+// velocity receivers, counter.
+loss_status one_step(loss_sim *s, float *div_store, int64_t div_shot_stride)
+{
+    loss_status r;
+    if ((r = stress_stage(s, div_store, div_shot_stride))) return r;
+    if ((r = inject(s, s->d_fields, 0, 1.0f, 0))) return r;
+    if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0))) return r;
+    if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 0))) return r;
+    std::vector<float *> vel;
+    if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
+    else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
+    if ((r = velocity_stage(s, (float)s->d.dt, vel.data(), nullptr))) return r;
+    if ((r = inject(s, s->d_fields, 1, 1.0f, 1))) return r;
+    if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 1))) return r;
+    if ((r = timed_begin(s))) return r;
+    hipError_t e = launch_advance(s->d_step, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+    return timed_end(s, KC_ADVANCE);
+}
+
+loss_status ensure_ready(loss_sim *s)
+{
+    if (!s->media_set) return fail(LOSS_ESTATE, "loss_set_media must be called first");
+    loss_status r;
+    if ((r = upload_sources(s))) return r;
+    if ((r = upload_receivers(s))) return r;
+    return LOSS_OK;
+}
+
+constexpr int kGraphSteps = 10;
+
+loss_status build_graph(loss_sim *s)
+{
+    drop_graph(s);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+    loss_status r = LOSS_OK;
+    for (int i = 0; i < kGraphSteps && r == LOSS_OK; ++i) r = one_step(s, nullptr, 0);
+    hipError_t e = hipStreamEndCapture(s->st, &g);
+    if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { s->gexec = nullptr; return fail(LOSS_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e)); }
+    s->gsteps = kGraphSteps;
+    return LOSS_OK;
+}
+
+loss_status run_steps(loss_sim *s, int64_t nsteps, float *div_store, int64_t div_shot_stride)
+{
+    loss_status r;
+    if ((r = ensure_ready(s))) return r;
+    if ((r = fuse(s))) return r;
+    const bool use_graph = !(s->d.flags & LOSS_FLAG_NO_GRAPH) && !s->timing && div_store == nullptr;
+    int64_t done = 0;
+    if (use_graph && nsteps >= kGraphSteps) {
+        if (!s->gexec && (r = build_graph(s))) return r;
+        while (nsteps - done >= s->gsteps) {
+            HIPCHK(hipGraphLaunch(s->gexec, s->st));
+            done += s->gsteps;
+        }
+    }
+    for (; done < nsteps; ++done) {
+        float *ds = div_store ? div_store + done * s->S * div_shot_stride : nullptr;
+        if ((r = one_step(s, ds, div_shot_stride))) return r;
+    }
+    s->step += nsteps;
+    return LOSS_OK;
+}
+
+loss_status copy_field_in(loss_sim *s, float *dst_padded, const float *src_dense, int mem, int64_t batch)
+{
+    const int64_t dense = (int64_t)s->nx * s->ny * s->nz;
+    const float *src = src_dense;
+    float *staging = nullptr;
+    if (mem == LOSS_MEM_HOST) {
+        loss_status r = s->alloc(&staging, dense * batch);
+        if (r) return r;
+        HIPCHK(hipMemcpyAsync(staging, src_dense, sizeof(float) * dense * batch, hipMemcpyHostToDevice, s->st));
+        src = staging;
+    }
+    hipError_t e = launch_pad_copy(src, dst_padded, s->nx, (int)(batch * s->ny * s->nz), s->pitch, 1, s->st);
+    if (staging) { (void)hipStreamSynchronize(s->st); s->release(staging); }
+    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+    return LOSS_OK;
+}
+
+loss_status copy_field_out(loss_sim *s, float *dst_dense, const float *src_padded, int mem, int64_t batch)
+{
+    const int64_t dense = (int64_t)s->nx * s->ny * s->nz;
+    float *dst = dst_dense;
+    float *staging = nullptr;
+    if (mem == LOSS_MEM_HOST) {
+        loss_status r = s->alloc(&staging, dense * batch);
+        if (r) return r;
+        dst = staging;
+    }
+    hipError_t e = launch_pad_copy(src_padded, dst, s->nx, (int)(batch * s->ny * s->nz), s->pitch, 0, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+    if (staging) {
+        HIPCHK(hipMemcpyAsync(dst_dense, staging, sizeof(float) * dense * batch, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        s->release(staging);
+    }
+    return LOSS_OK;
+}
+
+loss_status upload_axis(loss_sim *s, int axis)
+{
+    const AxisHost &h = s->axh[axis];
+    const int n = h.N + 1;
+    std::vector<float4> lu(n), rc(n), luT(n), lu2(n);
+    std::vector<float2> lu2c(n);
+    for (int i = 0; i < n; ++i) {
+        lu[i] = make_float4((float)h.m[i], (float)h.invd[i], (float)h.sup[i], (float)h.kind[i]);
+        rc[i] = make_float4((float)h.cm[i], (float)h.c0[i], (float)h.cp[i], (float)h.slot[i]);
+        luT[i] = make_float4((float)h.mT[i], (float)h.invdT[i], (float)h.supT[i], (float)h.subT[i]);
+        lu2[i] = make_float4((float)h.m2[i], (float)h.invd2[i], (float)h.sup2[i], 0.f);
+        lu2c[i] = make_float2((float)h.m2c[i], (float)h.invd2c[i]);
+    }
+    std::vector<float> tc(h.tap_c.begin(), h.tap_c.end()), gc(h.g_c.begin(), h.g_c.end());
+    float4 *dlu, *drc, *dluT, *dlu2;
+    float2 *dlu2c;
+    int *dti, *dgn;
+    float *dtc, *dgc;
+    loss_status r;
+    if ((r = s->alloc(&dlu, n)) || (r = s->alloc(&drc, n)) || (r = s->alloc(&dluT, n)) ||
+        (r = s->alloc(&dlu2, n)) || (r = s->alloc(&dlu2c, n)) ||
+        (r = s->alloc(&dti, std::max<size_t>(1, h.tap_idx.size()))) ||
+        (r = s->alloc(&dtc, std::max<size_t>(1, tc.size()))) ||
+        (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())))
+        return r;
+    HIPCHK(hipMemcpy(dlu, lu.data(), n * sizeof(float4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(drc, rc.data(), n * sizeof(float4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dluT, luT.data(), n * sizeof(float4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dlu2, lu2.data(), n * sizeof(float4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dlu2c, lu2c.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+    if (!h.tap_idx.empty()) {
+        HIPCHK(hipMemcpy(dti, h.tap_idx.data(), h.tap_idx.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dtc, tc.data(), tc.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(dgn, h.g_node.data(), h.g_node.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dgc, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice));
+    AxisDev &d = s->axd[axis];
+    d.N = h.N; d.M = h.M; d.p = h.p; d.ntap = 2 * h.halo + 1; d.h = (float)h.h;
+    d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
+    d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc;
+    return LOSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *loss_last_error(void) { return g_err.c_str(); }
+
+const char *loss_status_str(loss_status s)
+{
+    switch (s) {
+    case LOSS_OK: return "ok";
+    case LOSS_EINVAL: return "invalid argument";
+    case LOSS_ENOMEM: return "out of memory";
+    case LOSS_EHIP: return "HIP runtime error";
+    case LOSS_ESTATE: return "call out of order";
+    case LOSS_EUNSUPPORTED: return "unsupported";
+    case LOSS_EUNSTABLE: return "unstable";
+    default: return "unknown status";
+    }
+}
+
+loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out)
+{
+    if (!desc || !out) return fail(LOSS_EINVAL, "null argument");
+    *out = nullptr;
+    const loss_desc &d = *desc;
+    if (d.physics == LOSS_ACOUSTIC && d.ndim != 2) return fail(LOSS_EINVAL, "acoustic physics is 2-D (x, z)");
+    if (d.physics == LOSS_ELASTIC && d.ndim != 3) return fail(LOSS_EINVAL, "elastic physics is 3-D");
+    if (d.physics != LOSS_ACOUSTIC && d.physics != LOSS_ELASTIC) return fail(LOSS_EINVAL, "unknown physics");
+    if (d.nshots < 1) return fail(LOSS_EINVAL, "nshots must be >= 1");
+    if (!(d.dt > 0)) return fail(LOSS_EINVAL, "dt must be positive");
+    if (d.trace_len < 0) return fail(LOSS_EINVAL, "trace_len must be >= 0");
+    if (d.ndim == 2 && d.n[1] != 0) return fail(LOSS_EINVAL, "2-D grids have n[1] == 0");
+    loss_sim *s = new loss_sim();
+    s->d = d;
+    s->nf = d.physics == LOSS_ACOUSTIC ? 3 : 9;
+    s->S = d.nshots;
+    s->nx = (int)d.n[0] + 1;
+    s->ny = d.ndim == 3 ? (int)d.n[1] + 1 : 1;
+    s->nz = (int)d.n[2] + 1;
+    s->pitch = ((int64_t)s->nx + 31) / 32 * 32;
+    s->plane = s->pitch * s->ny;
+    s->shot_stride = s->plane * s->nz;
+    s->nodes = (int64_t)s->nx * s->ny * s->nz;
+    auto bail = [&](loss_status st) { loss_destroy(s); return st; };
+    for (int a = 0; a < 3; ++a) {
+        if (a == 1 && d.ndim == 2) continue;
+        std::string err = build_axis(s->axh[a], (int)d.n[a], d.h[a], d.patch[a], d.halo, d.end_mode);
+        if (!err.empty()) { loss_destroy(s); return fail(LOSS_EINVAL, "axis " + std::to_string(a) + ": " + err); }
+        const int M = d.patch[a];
+        if ((a == 0 && M > 1024) || (a != 0 && M > 1024))
+            { loss_destroy(s); return fail(LOSS_EUNSUPPORTED, "patch length above 1024"); }
+    }
+    (void)hipGetDevice(&s->device);
+    if (hip_stream) {
+        s->st = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(LOSS_EHIP, "hipStreamCreate failed"));
+        s->own_stream = true;
+    }
+    loss_status r;
+    const int64_t fe = field_elems(s);
+    s->f.assign(s->nf, nullptr);
+    for (int i = 0; i < s->nf; ++i)
+        if ((r = s->alloc(&s->f[i], fe))) return bail(r);
+    for (int i = 0; i < 3; ++i)
+        if ((r = s->alloc(&s->tmp[i], fe))) return bail(r);
+    const int nmed = d.physics == LOSS_ACOUSTIC ? 2 : 4;
+    s->med.assign(nmed, nullptr);
+    for (int i = 0; i < nmed; ++i)
+        if ((r = s->alloc(&s->med[i], s->shot_stride))) return bail(r);
+    if ((r = s->alloc(&s->d_fields, s->nf)) || (r = s->alloc(&s->d_tmpfields, s->nf)) ||
+        (r = s->alloc(&s->d_step, 1)))
+        return bail(r);
+    for (int a = 0; a < 3; ++a) {
+        if (a == 1 && d.ndim == 2) continue;
+        if ((r = upload_axis(s, a))) return bail(r);
+    }
+    if (hipMemcpy(s->d_fields, s->f.data(), sizeof(float *) * s->nf, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(LOSS_EHIP, "pointer table upload"));
+    if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
+        return bail(fail(LOSS_EHIP, "hipEventCreate"));
+    s->src.assign(s->S, {});
+    s->rec.assign(s->S, RecHost());
+    // zero state (fill kernels, no memset nodes)
+    for (int i = 0; i < s->nf; ++i)
+        if (launch_fill(s->f[i], fe, 0.f, s->st) != hipSuccess) return bail(fail(LOSS_EHIP, "fill"));
+    for (int i = 0; i < 3; ++i)
+        if (launch_fill(s->tmp[i], fe, 0.f, s->st) != hipSuccess) return bail(fail(LOSS_EHIP, "fill"));
+    for (int i = 0; i < nmed; ++i)
+        if (launch_fill(s->med[i], s->shot_stride, 0.f, s->st) != hipSuccess) return bail(fail(LOSS_EHIP, "fill"));
+    int64_t zero = 0;
+    if (hipMemcpy(s->d_step, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(LOSS_EHIP, "step counter"));
+    if (hipStreamSynchronize(s->st) != hipSuccess) return bail(fail(LOSS_EHIP, "sync"));
+    *out = s;
+    return LOSS_OK;
+}
+
+loss_status loss_destroy(loss_sim *s)
+{
+    if (!s) return LOSS_OK;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    drop_graph(s);
+    for (void *p : s->allocs) (void)hipFree(p);
+    s->allocs.clear();
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+    return LOSS_OK;
+}
+
+loss_status loss_set_media(loss_sim *s, const float *vp, const float *vs, const float *rho, int32_t mem)
+{
+    if (!s || !vp || !rho) return fail(LOSS_EINVAL, "null argument");
+    if (s->d.physics == LOSS_ELASTIC && !vs) return fail(LOSS_EINVAL, "elastic media need vs");
+    const int64_t n = s->nodes;
+    loss_status r;
+    float *dv[3] = {nullptr, nullptr, nullptr};
+    const float *srcs[3] = {vp, vs, rho};
+    for (int i = 0; i < 3; ++i) {
+        if (!srcs[i]) continue;
+        if ((r = s->alloc(&dv[i], n))) return r;
+        HIPCHK(hipMemcpyAsync(dv[i], srcs[i], sizeof(float) * n,
+                              mem == LOSS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->st));
+    }
+    hipError_t e = launch_media(dv[0], dv[1], dv[2], s->med.data(), s->d.physics, s->nx, s->ny * s->nz,
+                                s->pitch, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+    // keep dense vp and rho for the gradient map
+    if (s->d_vp) s->release(s->d_vp);
+    if (s->d_rho) s->release(s->d_rho);
+    s->d_vp = dv[0];
+    s->d_rho = dv[2];
+    if (dv[1]) { HIPCHK(hipStreamSynchronize(s->st)); s->release(dv[1]); }
+    // stability bound of the Strang scheme with the spline symbol (max k* h = sqrt 3)
+    std::vector<float> hv(n);
+    HIPCHK(hipMemcpyAsync(hv.data(), s->d_vp, sizeof(float) * n, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    double cmax = 0;
+    for (float v : hv) cmax = std::max(cmax, (double)v);
+    double hmin = s->d.h[0];
+    hmin = std::min(hmin, s->d.h[2]);
+    if (s->d.ndim == 3) hmin = std::min(hmin, s->d.h[1]);
+    s->media_set = true;
+    drop_graph(s);
+    const double bound = 2.0 * hmin / (std::sqrt(3.0) * std::sqrt((double)s->d.ndim) * cmax);
+    if (s->d.dt > bound)
+        return fail(LOSS_EUNSTABLE, "dt " + std::to_string(s->d.dt) + " exceeds the stability bound " +
+                                         std::to_string(bound));
+    return LOSS_OK;
+}
+
+loss_status loss_add_source(loss_sim *s, int32_t shot, const double pos[3], int32_t kind, const float *wavelet,
+                            int64_t nt, double spread_m)
+{
+    if (!s || !pos || (!wavelet && nt > 0)) return fail(LOSS_EINVAL, "null argument");
+    if (shot < 0 || shot >= s->S) return fail(LOSS_EINVAL, "shot out of range");
+    if (kind < LOSS_SRC_PRESSURE || kind > LOSS_SRC_FORCE_Z) return fail(LOSS_EINVAL, "unknown source kind");
+    if (s->d.physics == LOSS_ACOUSTIC && kind == LOSS_SRC_FORCE_Y) return fail(LOSS_EINVAL, "2-D grid has no y force");
+    if (spread_m < 0 || nt < 0 || nt > (1ll << 30)) return fail(LOSS_EINVAL, "bad spread or nt");
+    if ((int)s->src[shot].size() >= 16) return fail(LOSS_EINVAL, "at most 16 sources per shot");
+    for (int a = 0; a < 3; ++a) {
+        if (a == 1 && s->d.ndim == 2) continue;
+        if (!(pos[a] >= 0.0 && pos[a] <= s->d.n[a] * s->d.h[a])) return fail(LOSS_EINVAL, "source outside the grid");
+    }
+    SrcHost h;
+    h.kind = kind;
+    for (int a = 0; a < 3; ++a) h.pos[a] = pos[a];
+    h.spread = spread_m;
+    h.wavelet.assign(wavelet, wavelet + nt);
+    s->src[shot].push_back(h);
+    s->src_dirty = true;
+    drop_graph(s);
+    return LOSS_OK;
+}
+
+loss_status loss_add_receivers(loss_sim *s, int32_t shot, int64_t nrec, const int32_t *node_idx, int32_t component)
+{
+    if (!s || (nrec > 0 && !node_idx)) return fail(LOSS_EINVAL, "null argument");
+    if (shot < 0 || shot >= s->S) return fail(LOSS_EINVAL, "shot out of range");
+    if (component < 0 || component >= s->nf) return fail(LOSS_EINVAL, "bad receiver component");
+    if (s->d.physics == LOSS_ACOUSTIC && component != LOSS_F_SIGMA)
+        return fail(LOSS_EUNSUPPORTED, "acoustic receivers record sigma");
+    const int lim[3] = {s->nx, s->ny, s->nz};
+    for (int64_t r = 0; r < nrec; ++r)
+        for (int a = 0; a < 3; ++a)
+            if (node_idx[3 * r + a] < 0 || node_idx[3 * r + a] >= lim[a])
+                return fail(LOSS_EINVAL, "receiver node outside the grid");
+    RecHost h;
+    h.idx.assign(node_idx, node_idx + 3 * nrec);
+    h.comp = component;
+    s->rec[shot] = h;
+    s->rec_dirty = true;
+    drop_graph(s);
+    return LOSS_OK;
+}
+
+loss_status loss_reset(loss_sim *s)
+{
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    const int64_t fe = field_elems(s);
+    for (int i = 0; i < s->nf; ++i)
+        if (launch_fill(s->f[i], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    if (s->traces && s->trace_total > 0)
+        HIPCHK(hipMemsetAsync(s->traces, 0, sizeof(double) * s->trace_total, s->st));
+    int64_t zero = 0;
+    HIPCHK(hipMemcpyAsync(s->d_step, &zero, sizeof(zero), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->step = 0;
+    s->fused = false;
+    return LOSS_OK;
+}
+
+loss_status loss_step(loss_sim *s, int64_t nsteps)
+{
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    if (nsteps < 0) return fail(LOSS_EINVAL, "nsteps must be >= 0");
+    return run_steps(s, nsteps, nullptr, 0);
+}
+
+loss_status loss_get_field(loss_sim *s, int32_t shot, int32_t field, float *dst, int32_t mem)
+{
+    if (!s || !dst) return fail(LOSS_EINVAL, "null argument");
+    if (shot < 0 || shot >= s->S || field < 0 || field >= s->nf) return fail(LOSS_EINVAL, "bad shot or field");
+    const float *src = s->f[field];
+    if (is_velocity(s, field) && s->fused) {
+        std::vector<float *> v;
+        loss_status r = unfused_velocity(s, v);
+        if (r) return r;
+        int c = s->d.physics == LOSS_ACOUSTIC ? (field == LOSS_F_V1 ? 0 : 1) : field - LOSS_F_EV1;
+        src = v[c];
+    }
+    return copy_field_out(s, dst, src + (int64_t)shot * s->shot_stride, mem, 1);
+}
+
+loss_status loss_set_field(loss_sim *s, int32_t shot, int32_t field, const float *src, int32_t mem)
+{
+    if (!s || !src) return fail(LOSS_EINVAL, "null argument");
+    if (shot < 0 || shot >= s->S || field < 0 || field >= s->nf) return fail(LOSS_EINVAL, "bad shot or field");
+    loss_status r = unfuse_in_place(s);
+    if (r) return r;
+    return copy_field_in(s, s->f[field] + (int64_t)shot * s->shot_stride, src, mem, 1);
+}
+
+loss_status loss_get_traces(loss_sim *s, int32_t shot, double *dst, int32_t mem)
+{
+    if (!s || !dst) return fail(LOSS_EINVAL, "null argument");
+    if (shot < 0 || shot >= s->S) return fail(LOSS_EINVAL, "bad shot");
+    loss_status r = upload_receivers(s);
+    if (r) return r;
+    const int64_t nr = (int64_t)s->rec[shot].idx.size() / 3;
+    const int64_t cnt = nr * s->d.trace_len;
+    if (cnt == 0) return LOSS_OK;
+    HIPCHK(hipMemcpyAsync(dst, s->traces + s->rec_off[shot], sizeof(double) * cnt,
+                          mem == LOSS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s->st));
+    if (mem == LOSS_MEM_HOST) HIPCHK(hipStreamSynchronize(s->st));
+    return LOSS_OK;
+}
+
+loss_status loss_deriv(loss_sim *s, int32_t axis, int32_t order, const float *in, float *out, int64_t batch,
+                       int32_t mem)
+{
+    if (!s || !in || !out) return fail(LOSS_EINVAL, "null argument");
+    if (axis < 0 || axis > 2 || (axis == 1 && s->d.ndim == 2)) return fail(LOSS_EINVAL, "bad axis");
+    if (order != 1 && order != 2) return fail(LOSS_EINVAL, "order must be 1 or 2");
+    if (batch < 1) return fail(LOSS_EINVAL, "batch must be >= 1");
+    // tmp[1] and tmp[2] hold up to S fields each
+    const int64_t dense = s->nodes;
+    loss_status r = unfuse_in_place(s);
+    if (r) return r;
+    for (int64_t b0 = 0; b0 < batch; b0 += s->S) {
+        const int64_t nb = std::min<int64_t>(s->S, batch - b0);
+        if ((r = copy_field_in(s, s->tmp[1], in + b0 * dense, mem, nb))) return r;
+        LineArgs a = base_args(s, axis);
+        a.S = (int)nb;
+        a.in = s->tmp[1];
+        a.out[0] = s->tmp[2];
+        if ((r = run_line(s, KC_VEL_X + axis, axis, order == 1 ? SOLVE_D1 : SOLVE_D2, EPI_STORE, a))) return r;
+        if ((r = copy_field_out(s, out + b0 * dense, s->tmp[2], mem, nb))) return r;
+    }
+    return LOSS_OK;
+}
+
+loss_status loss_sync(loss_sim *s)
+{
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    HIPCHK(hipStreamSynchronize(s->st));
+    return LOSS_OK;
+}
+
+loss_status loss_set_timing(loss_sim *s, int32_t on)
+{
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    s->timing = on != 0;
+    for (int i = 0; i < KC_COUNT; ++i) { s->kms[i] = 0; s->kcount[i] = 0; }
+    return LOSS_OK;
+}
+
+loss_status loss_kernel_timing(loss_sim *s, int32_t id, double *ms, int64_t *launches, const char **name)
+{
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    if (id < 0 || id >= KC_COUNT) return fail(LOSS_EINVAL, "no such kernel class");
+    if (ms) *ms = s->kms[id];
+    if (launches) *launches = s->kcount[id];
+    if (name) *name = kKClassName[id];
+    return LOSS_OK;
+}
+
+int64_t loss_current_step(const loss_sim *s) { return s ? s->step : -1; }
+
+loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
+{
+    (void)nsteps; (void)ckpt_every;
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    return fail(LOSS_EUNSUPPORTED, "adjoint not built yet");
+}
+
+loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, double *grad, int32_t mem)
+{
+    (void)residual; (void)param; (void)grad; (void)mem;
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    return fail(LOSS_EUNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"

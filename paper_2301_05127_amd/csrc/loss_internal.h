@@ -1,0 +1,140 @@
+// Internal declarations of the HIP library behind include/loss.h.
+//
+// Derivative of a line along one axis (paper Sec. 3.1-3.2), as computed on the GPU.
+// The spline slopes w_i = (v~_{i+1} - v~_{i-1}) / (2h) of a patch with Hermite ends
+// satisfy, at every patch-interior node, the three-term relation obtained by
+// differencing two neighbouring collocation rows:
+//     w_{i-1} + 4 w_i + w_{i+1} = (3/h) (u_{i+1} - u_{i-1}),
+// with w = phi (the PMBC slope) at the junction rows, and at a natural end
+//     2 w_0 + w_1 = (3/h)(u_1 - u_0),   w_{N-1} + 2 w_N = (3/h)(u_N - u_{N-1}).
+// Every line is therefore one tridiagonal system T w = G u whose junction rows are
+// identity rows; T decouples into the patches.  The GPU solves it with the LU
+// factors of T (one table per axis, built in FP64 on the host) by chunked affine
+// scans: each lane eliminates a chunk of C nodes in registers and the chunk carries
+// are composed across lanes (wave shuffles) or waves (LDS).  The adjoint applies
+// T^{-T} (another table) and G^T (stencil plus the transposed PMBC gather).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace loss {
+
+constexpr int kMaxHalo = 64;
+constexpr int kMaxGatherTaps = 4;   // junction rows reaching one node (transposed PMBC)
+
+// Row kinds of the derivative system of one axis.
+enum RowKind : int { ROW_INTERIOR = 0, ROW_JUNCTION = 1, ROW_NATURAL_L = 2, ROW_NATURAL_R = 3 };
+
+// Host FP64 tables of one axis.
+struct AxisHost {
+    int N = 0, M = 0, p = 0, halo = 0, end_mode = 0;
+    double h = 0.0;
+    std::vector<int> kind;              // [N+1]
+    std::vector<double> sub, diag, sup; // rows of T
+    std::vector<double> cm, c0, cp;     // stencil rows of G (zero on junction rows)
+    std::vector<int> slot;              // [N+1] junction slot or -1
+    std::vector<int> tap_idx;           // [nslot][2*halo+1] node index, -1 = none
+    std::vector<double> tap_c;          // [nslot][2*halo+1]
+    std::vector<int> junction_node;     // [nslot]
+    // LU of T (forward) and of T^T (adjoint), no pivoting
+    std::vector<double> m, invd;        // T:   y_i = rhs_i - m_i y_{i-1}; w_i = (y_i - sup_i w_{i+1}) invd_i
+    std::vector<double> mT, invdT, supT, subT;
+    // transposed PMBC: for node j, up to kMaxGatherTaps (junction node, coefficient)
+    std::vector<int> g_node;            // [N+1][kMaxGatherTaps], -1 = none
+    std::vector<double> g_c;
+    // second-derivative system (per patch, Hermite/natural end rows)
+    std::vector<double> m2, invd2, sup2;    // factors for rows as the first/interior row of a patch
+    std::vector<double> m2c, invd2c;        // factors of node i as the closing row of the patch ending at i
+};
+
+// Build the tables; returns an empty string on success, else the reason.
+std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_mode);
+
+// Device copy of one axis (float32).
+struct AxisDev {
+    int N, M, p, ntap;
+    float h;
+    const float4 *lu;      // {m, invd, sup, kind}
+    const float4 *rc;      // {cm, c0, cp, slot}
+    const float4 *luT;     // {mT, invdT, supT, subT}
+    const float4 *lu2;     // {m2, invd2, sup2, 0}
+    const float2 *lu2c;    // {m2c, invd2c}
+    const int *tap_idx;    // [nslot][ntap]
+    const float *tap_c;
+    const int *g_node;     // [N+1][kMaxGatherTaps]
+    const float *g_c;
+};
+
+// Epilogue of a line kernel.
+enum EpiKind : int {
+    EPI_STORE = 0,        // out0 = D
+    EPI_AXPY = 1,         // out_j += alpha * coef_j * D       (j < nout, coef_j may be null)
+    EPI_AXPY_AUX = 2,     // out0 += alpha * coef0 * (D + aux); optional div store: div = D + aux
+    EPI_BASE = 3,         // out0 = aux + alpha * coef0 * D
+};
+
+// Which system the line kernel solves.
+enum SolveKind : int {
+    SOLVE_D1 = 0,         // first derivative, rhs = G u
+    SOLVE_D2 = 1,         // second derivative, per-patch moment system
+    SOLVE_T1 = 2,         // adjoint phase 1: y = T^{-T} z on patch interiors
+};
+
+struct LineArgs {
+    const float *in;
+    float *out[3];
+    const float *coef[3];
+    const float *aux;
+    float *div;            // optional store of D + aux (EPI_AXPY_AUX)
+    int64_t div_shot_stride;
+    float alpha;
+    int nout;
+    // geometry (elements, padded layout [S][nz][ny][pitch])
+    int S, nx, ny, nz;     // node counts
+    int64_t pitch, plane, shot_stride;
+    AxisDev ax;
+};
+
+// Launch helpers (kernels.hip).  axis: 0 = x (contiguous), 1 = y, 2 = z.
+hipError_t launch_line(int axis, int solve, int epi, const LineArgs &a, hipStream_t st);
+hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st);
+
+struct SrcDev {
+    int shot, kind, field0, nfield;   // fields field0 .. field0+nfield-1 (consecutive ids)
+    int x0, y0, z0, bx, by, bz;       // footprint box (nodes)
+    int64_t w_off, wav_off;           // offsets into the weight / wavelet pools
+    int nt;
+    int force;                        // 1: scale by b (body force), 0: stress rate
+};
+struct RecDev {
+    int shot, comp;
+    int64_t node;                     // padded node offset within a shot field
+    int64_t trace_off;                // offset of sample 0 in the trace pool
+};
+
+hipError_t launch_inject(const SrcDev *src, int nsrc, float *const *fields, const float *b,
+                         const float *wpool, const float *wavpool, int64_t shot_stride, int64_t pitch,
+                         int64_t plane, const int64_t *d_step, int time_offset, float scale,
+                         int want_force, hipStream_t st);
+hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields, int64_t shot_stride,
+                         double *traces, const int64_t *d_step, int64_t trace_len, float weight,
+                         int accumulate, hipStream_t st);
+hipError_t launch_advance(int64_t *d_step, hipStream_t st);
+// rows = number of x rows (batch * nz * ny); dense <-> padded (row pitch `pitch`)
+hipError_t launch_pad_copy(const float *src, float *dst, int nx, int rows, int64_t pitch, int to_padded,
+                           hipStream_t st);
+hipError_t launch_media(const float *vp, const float *vs, const float *rho, float *const *media,
+                        int physics, int nx, int rows, int64_t pitch, hipStream_t st);
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
+hipError_t launch_axpby(float *y, const float *x, float a, float b, int64_t n, hipStream_t st);
+hipError_t launch_grad_accum(double *g, const float *lam, const float *div, float scale, int S,
+                             int64_t shot_stride, int64_t n, hipStream_t st);
+hipError_t launch_grad_unpad(const double *gp, double *g, int nx, int rows, int64_t pitch, const float *vp,
+                             const float *rho, int param, hipStream_t st);
+hipError_t launch_nonfinite(const float *p, int64_t n, int *flag, hipStream_t st);
+
+}  // namespace loss

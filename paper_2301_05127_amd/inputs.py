@@ -8,7 +8,8 @@ Workloads (the paper measures on synthetic models only, Sec. 4; none of its data
 available, and these recipes stand in for its experiments):
 
 * ``cfg1`` 2-D acoustic, 128x128 intervals, h = 10 m, dt = 1 ms, c = 2000 m/s,
-  2x2 patches of 64 intervals, halo 8, 15 Hz Ricker at the centre node, 300 steps.
+  2x2 patches of 64 intervals, halo 8, 15 Hz Ricker at the centre node, 300 steps;
+  receivers on the row z = 320 m below the source.
 * ``cfg2`` 2-D acoustic, 2048x2048 intervals, 8x8 patches of 256, halo 12,
   c = smooth Gaussian random field in [1500, 4500] m/s (seed 2301, correlation
   length 200 m), 20 Hz Ricker at the centre, 2000 steps.
@@ -96,8 +97,9 @@ def config(name: str, **over):
         dt, nsteps, f0 = 1e-3, 300, 15.0
         vp = np.full(shape, 2000.0)
         rho = np.full(shape, RHO_ACOUSTIC)
+        rec = np.array([[ix, 0, 96] for ix in range(16, 113, 4)], dtype=np.int32)
         shots = [{"sources": [_src(0, (640.0, 0.0, 640.0), 20.0, f0, 1.2 / f0, dt, nsteps + 1)],
-                  "receivers": _rec_row(g, 2, step=4), "rec_comp": 0}]
+                  "receivers": rec, "rec_comp": 0}]
         w = dict(name=name, grid=g, physics=0, dt=dt, nsteps=nsteps, vp=vp, vs=None, rho=rho,
                  shots=shots)
     elif name == "cfg2":
