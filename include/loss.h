@@ -160,18 +160,22 @@ loss_status loss_get_traces(loss_sim *sim, int32_t shot, double *dst, int32_t me
 /* Hot-path primitive: the patched spline derivative of order 1 (eq.
  * derivative_approximation) or 2 (second difference of the coefficients) along
  * axis 0 (x), 1 (y) or 2 (z) of `batch` dense fields in[batch][nodes] -> out.
- * The PMBC junction slopes come from a halo of n_nb nodes on each side. */
+ * The PMBC junction slopes come from a halo of n_nb nodes on each side.
+ * order = -1 applies the transpose of the order-1 operator (used by the adjoint).
+ * Any fused step state is converted back to integer time first. */
 loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *in, float *out,
                        int64_t batch, int32_t mem);
 
 /* Adjoint-state gradient (acoustic only).  loss_forward_ckpt resets, runs nsteps
- * steps from rest recording traces and keeping the state every ckpt_every steps in
- * device memory.  loss_adjoint then takes the trace residual
- * residual[shot][rec][n] (float64, n < nsteps) of J = 1/2 sum residual^2 and returns
- * dJ/dparam summed over shots (float64, nodes), param = LOSS_GRAD_K (bulk modulus)
- * or LOSS_GRAD_VP (c with rho fixed).  The adjoint applies the exact transpose of
- * every discrete operator of the fused scheme; forward states are recomputed from
- * the checkpoints segment by segment. */
+ * (<= trace_len) steps from rest recording traces and keeping the state every
+ * ckpt_every steps in device memory.  loss_adjoint then takes the trace residual
+ * of J = 1/2 sum residual^2, laid out like the traces of all shots concatenated
+ * (residual[shot][rec][t], t < trace_len, float64; samples t >= nsteps are ignored)
+ * and returns dJ/dparam summed over shots (float64, nodes), param = LOSS_GRAD_K
+ * (bulk modulus K) or LOSS_GRAD_VP (c with rho fixed: 2 rho c dJ/dK).  The adjoint
+ * applies the exact transpose of every discrete operator of the time-stepping
+ * scheme; forward states are recomputed from the checkpoints segment by segment.
+ * Afterwards the wavefields hold an intermediate state (call loss_reset). */
 #define LOSS_GRAD_K  0
 #define LOSS_GRAD_VP 1
 loss_status loss_forward_ckpt(loss_sim *sim, int64_t nsteps, int64_t ckpt_every);

@@ -39,6 +39,13 @@ __device__ __forceinline__ float pmbc_phi(const AxisDev &ax, int slot, const flo
     return acc;
 }
 
+// value of the input at element `idx` (media element `midx`), times the optional factor
+__device__ __forceinline__ float load_in(const LineArgs &a, int64_t idx, int64_t midx)
+{
+    const float v = a.in[idx];
+    return a.in_coef ? v * a.in_coef[midx] : v;
+}
+
 template <int EPI>
 __device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_t midx, int shot,
                                          float D)
@@ -146,7 +153,10 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
 
     float u[C + 2];
 #pragma unroll
-    for (int c = 0; c < C + 2; ++c) u[c] = in[base + clampi(q - 1 + c, 0, N)];
+    for (int c = 0; c < C + 2; ++c) {
+        const int i = clampi(q - 1 + c, 0, N);
+        u[c] = load_in(a, base + i, mbase + i);
+    }
 
     float y[C], P[C];
     float4 fac[C];
@@ -246,7 +256,10 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
 
     float u[C + 2];
 #pragma unroll
-    for (int c = 0; c < C + 2; ++c) u[c] = in[base + (int64_t)clampi(q - 1 + c, 0, N) * stride];
+    for (int c = 0; c < C + 2; ++c) {
+        const int64_t off = (int64_t)clampi(q - 1 + c, 0, N) * stride;
+        u[c] = load_in(a, base + off, mbase + off);
+    }
 
     float y[C], P[C];
     float4 fac[C];
@@ -314,12 +327,12 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
 // junction row of T^T:  y_J = z_J - subT_J y_{J-1} - supT_J y_{J+1}.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float adj_y(const AxisDev &ax, const float *__restrict__ Y,
-                                       const float *__restrict__ Z, int64_t lb, int64_t stride, int i)
+                                       const LineArgs &a, int64_t lb, int64_t mlb, int64_t stride, int i)
 {
     const float4 lu = ax.lu[i];
     if (lu.w != (float)ROW_JUNCTION) return Y[lb + (int64_t)i * stride];
     const float4 t = ax.luT[i];
-    float v = Z[lb + (int64_t)i * stride];
+    float v = load_in(a, lb + (int64_t)i * stride, mlb + (int64_t)i * stride);
     if (i > 0) v = fmaf(-t.w, Y[lb + (int64_t)(i - 1) * stride], v);
     if (i < ax.N) v = fmaf(-t.z, Y[lb + (int64_t)(i + 1) * stride], v);
     return v;
@@ -343,18 +356,18 @@ __global__ void __launch_bounds__(256) k_adj_gather(LineArgs a, const float *__r
     const int j = axis == 0 ? x : (axis == 1 ? yy : z);
     const int64_t stride = axis == 0 ? 1 : (axis == 1 ? a.pitch : a.plane);
     const int64_t lb = oidx - (int64_t)j * stride;
-    const float *Z = a.in;
+    const int64_t mlb = midx - (int64_t)j * stride;
     float out = 0.f;
     const float4 rc = ax.rc[j];
-    out = rc.y * adj_y(ax, Y, Z, lb, stride, j);
-    if (j > 0) out = fmaf(ax.rc[j - 1].z, adj_y(ax, Y, Z, lb, stride, j - 1), out);
-    if (j < ax.N) out = fmaf(ax.rc[j + 1].x, adj_y(ax, Y, Z, lb, stride, j + 1), out);
+    out = rc.y * adj_y(ax, Y, a, lb, mlb, stride, j);
+    if (j > 0) out = fmaf(ax.rc[j - 1].z, adj_y(ax, Y, a, lb, mlb, stride, j - 1), out);
+    if (j < ax.N) out = fmaf(ax.rc[j + 1].x, adj_y(ax, Y, a, lb, mlb, stride, j + 1), out);
     const int *gn = ax.g_node + (int64_t)j * kMaxGatherTaps;
     const float *gc = ax.g_c + (int64_t)j * kMaxGatherTaps;
 #pragma unroll
     for (int t = 0; t < kMaxGatherTaps; ++t) {
         const int J = gn[t];
-        if (J >= 0) out = fmaf(gc[t], adj_y(ax, Y, Z, lb, stride, J), out);
+        if (J >= 0) out = fmaf(gc[t], adj_y(ax, Y, a, lb, mlb, stride, J), out);
     }
     epilogue<EPI>(a, oidx, midx, shot, out);
 }
@@ -400,6 +413,17 @@ __global__ void k_record(const RecDev *__restrict__ rec, int nrec, const float *
 }
 
 __global__ void k_advance(int64_t *d_step) { *d_step += 1; }
+
+__global__ void k_set_step(int64_t *d_step, int64_t v) { *d_step = v; }
+
+__global__ void k_residual_inject(const RecDev *__restrict__ rec, int nrec, float *lam, int64_t shot_stride,
+                                  const double *__restrict__ res, int64_t n)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const RecDev rd = rec[r];
+    atomicAdd(lam + (int64_t)rd.shot * shot_stride + rd.node, (float)res[rd.trace_off + n]);
+}
 
 __global__ void k_pad_copy(const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, int nz,
                            int64_t pitch, int to_padded, int64_t total)
@@ -578,6 +602,20 @@ hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields
     if (nrec <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_record, nblk(nrec, 256), 256, 0, st, rec, nrec, fields, shot_stride, traces,
                        d_step, trace_len, weight, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_inject(const RecDev *rec, int nrec, float *lam, int64_t shot_stride,
+                                  const double *res, int64_t n, hipStream_t st)
+{
+    if (nrec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_residual_inject, nblk(nrec, 256), 256, 0, st, rec, nrec, lam, shot_stride, res, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(int64_t *d_step, int64_t v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_step, 1, 1, 0, st, d_step, v);
     return hipGetLastError();
 }
 

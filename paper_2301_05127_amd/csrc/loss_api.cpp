@@ -102,10 +102,11 @@ struct loss_sim {
     int64_t kcount[KC_COUNT] = {0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // adjoint
-    std::vector<float *> ckpt;     // checkpoint states (nf fields each, S shots)
-    int64_t ck_every = 0, ck_steps = 0;
+    float *ckpt = nullptr;         // [nseg][3 fields][S][shot_stride] fused states
+    int64_t ck_every = 0, ck_steps = 0, ck_nseg = 0;
     float *divstore = nullptr;     // [ck_every][S][shot_stride]
-    double *grad_pad = nullptr;
+    float *adj[4] = {nullptr, nullptr, nullptr, nullptr};   // lambda, mu1, mu3, Y scratch
+    double *grad_pad = nullptr, *grad_dense = nullptr, *res_dev = nullptr;
     float *d_vp = nullptr, *d_rho = nullptr;   // dense copies of the media for the gradient map
 
     template <class T>
@@ -184,6 +185,30 @@ loss_status deriv_axpy(loss_sim *s, int kc, int axis, const float *in, float alp
     a.nout = nout;
     for (int j = 0; j < nout; ++j) { a.out[j] = out[j]; a.coef[j] = coef[j]; }
     return run_line(s, kc, axis, SOLVE_D1, EPI_AXPY, a);
+}
+
+// out (+)= alpha * D^T (in_coef * in) along axis: the transposed solve y = T^{-T} z on
+// the patch interiors into Y, then G^T y (stencil, junction rows, transposed PMBC).
+loss_status adj_deriv(loss_sim *s, int axis, const float *in, const float *in_coef, float *out,
+                      float alpha, int epi, float *Y, int nshots)
+{
+    LineArgs a = base_args(s, axis);
+    a.S = nshots;
+    a.in = in;
+    a.in_coef = in_coef;
+    a.out[0] = Y;
+    loss_status r = run_line(s, KC_ADJ_SOLVE, axis, SOLVE_T1, EPI_STORE, a);
+    if (r) return r;
+    LineArgs g = base_args(s, axis);
+    g.S = nshots;
+    g.in = in;
+    g.in_coef = in_coef;
+    g.out[0] = out;
+    g.alpha = alpha;
+    if ((r = timed_begin(s))) return r;
+    hipError_t e = launch_adj_gather(axis, epi, g, Y, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("adjoint gather: ") + hipGetErrorString(e));
+    return timed_end(s, KC_ADJ_GATHER);
 }
 
 loss_status inject(loss_sim *s, float **fields_dev, int time_offset, float scale, int want_force)
@@ -850,8 +875,7 @@ loss_status loss_reset(loss_sim *s)
         if (launch_fill(s->f[i], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
     if (s->traces && s->trace_total > 0)
         HIPCHK(hipMemsetAsync(s->traces, 0, sizeof(double) * s->trace_total, s->st));
-    int64_t zero = 0;
-    HIPCHK(hipMemcpyAsync(s->d_step, &zero, sizeof(zero), hipMemcpyHostToDevice, s->st));
+    HIPCHK(launch_set_step(s->d_step, 0, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     s->step = 0;
     s->fused = false;
@@ -909,7 +933,7 @@ loss_status loss_deriv(loss_sim *s, int32_t axis, int32_t order, const float *in
 {
     if (!s || !in || !out) return fail(LOSS_EINVAL, "null argument");
     if (axis < 0 || axis > 2 || (axis == 1 && s->d.ndim == 2)) return fail(LOSS_EINVAL, "bad axis");
-    if (order != 1 && order != 2) return fail(LOSS_EINVAL, "order must be 1 or 2");
+    if (order != 1 && order != 2 && order != -1) return fail(LOSS_EINVAL, "order must be 1, 2 or -1");
     if (batch < 1) return fail(LOSS_EINVAL, "batch must be >= 1");
     // tmp[1] and tmp[2] hold up to S fields each
     const int64_t dense = s->nodes;
@@ -918,11 +942,17 @@ loss_status loss_deriv(loss_sim *s, int32_t axis, int32_t order, const float *in
     for (int64_t b0 = 0; b0 < batch; b0 += s->S) {
         const int64_t nb = std::min<int64_t>(s->S, batch - b0);
         if ((r = copy_field_in(s, s->tmp[1], in + b0 * dense, mem, nb))) return r;
-        LineArgs a = base_args(s, axis);
-        a.S = (int)nb;
-        a.in = s->tmp[1];
-        a.out[0] = s->tmp[2];
-        if ((r = run_line(s, KC_VEL_X + axis, axis, order == 1 ? SOLVE_D1 : SOLVE_D2, EPI_STORE, a))) return r;
+        if (order == -1) {
+            if ((r = adj_deriv(s, axis, s->tmp[1], nullptr, s->tmp[2], 1.f, EPI_STORE, s->tmp[0], (int)nb)))
+                return r;
+        } else {
+            LineArgs a = base_args(s, axis);
+            a.S = (int)nb;
+            a.in = s->tmp[1];
+            a.out[0] = s->tmp[2];
+            if ((r = run_line(s, KC_VEL_X + axis, axis, order == 1 ? SOLVE_D1 : SOLVE_D2, EPI_STORE, a)))
+                return r;
+        }
         if ((r = copy_field_out(s, out + b0 * dense, s->tmp[2], mem, nb))) return r;
     }
     return LOSS_OK;
@@ -957,16 +987,96 @@ int64_t loss_current_step(const loss_sim *s) { return s ? s->step : -1; }
 
 loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
 {
-    (void)nsteps; (void)ckpt_every;
     if (!s) return fail(LOSS_EINVAL, "null argument");
-    return fail(LOSS_EUNSUPPORTED, "adjoint not built yet");
+    if (s->d.physics != LOSS_ACOUSTIC) return fail(LOSS_EUNSUPPORTED, "the adjoint is built for the acoustic system");
+    if (nsteps < 1 || ckpt_every < 1) return fail(LOSS_EINVAL, "nsteps and ckpt_every must be >= 1");
+    if (s->d.trace_len < nsteps) return fail(LOSS_EINVAL, "trace_len must cover nsteps");
+    loss_status r;
+    if ((r = ensure_ready(s))) return r;
+    if ((r = loss_reset(s))) return r;
+    if ((r = fuse(s))) return r;
+    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    const int64_t fe = field_elems(s);
+    if (s->ckpt && s->ck_nseg != nseg) { s->release(s->ckpt); s->ckpt = nullptr; }
+    if (!s->ckpt && (r = s->alloc(&s->ckpt, (size_t)(nseg * 3 * fe)))) return r;
+    if (s->divstore && s->ck_every != ckpt_every) { s->release(s->divstore); s->divstore = nullptr; }
+    s->ck_nseg = nseg;
+    s->ck_every = ckpt_every;
+    s->ck_steps = 0;
+    const int fid[3] = {LOSS_F_SIGMA, LOSS_F_V1, LOSS_F_V3};
+    for (int64_t c = 0; c < nseg; ++c) {
+        for (int k = 0; k < 3; ++k)
+            HIPCHK(hipMemcpyAsync(s->ckpt + (c * 3 + k) * fe, s->f[fid[k]], sizeof(float) * fe,
+                                  hipMemcpyDeviceToDevice, s->st));
+        const int64_t nc = std::min(ckpt_every, nsteps - c * ckpt_every);
+        if ((r = run_steps(s, nc, nullptr, 0))) return r;
+    }
+    s->ck_steps = nsteps;
+    return LOSS_OK;
 }
 
 loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, double *grad, int32_t mem)
 {
-    (void)residual; (void)param; (void)grad; (void)mem;
-    if (!s) return fail(LOSS_EINVAL, "null argument");
-    return fail(LOSS_EUNSUPPORTED, "adjoint not built yet");
+    if (!s || !residual || !grad) return fail(LOSS_EINVAL, "null argument");
+    if (param != LOSS_GRAD_K && param != LOSS_GRAD_VP) return fail(LOSS_EINVAL, "unknown gradient parameter");
+    if (s->ck_steps < 1) return fail(LOSS_ESTATE, "loss_forward_ckpt must run first");
+    loss_status r;
+    const int64_t fe = field_elems(s), S = s->S, ss = s->shot_stride;
+    const float dt = (float)s->d.dt;
+    for (int k = 0; k < 4; ++k)
+        if (!s->adj[k] && (r = s->alloc(&s->adj[k], fe))) return r;
+    if (!s->divstore && (r = s->alloc(&s->divstore, (size_t)(s->ck_every * fe)))) return r;
+    if (!s->grad_pad && (r = s->alloc(&s->grad_pad, ss))) return r;
+    if (!s->grad_dense && (r = s->alloc(&s->grad_dense, s->nodes))) return r;
+    if (!s->res_dev && (r = s->alloc(&s->res_dev, std::max<int64_t>(1, s->trace_total)))) return r;
+    if (s->trace_total > 0)
+        HIPCHK(hipMemcpyAsync(s->res_dev, residual, sizeof(double) * s->trace_total,
+                              mem == LOSS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->st));
+    for (int k = 0; k < 3; ++k)
+        if (launch_fill(s->adj[k], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    HIPCHK(hipMemsetAsync(s->grad_pad, 0, sizeof(double) * ss, s->st));
+    float *lam = s->adj[0], *mu1 = s->adj[1], *mu3 = s->adj[2], *Y = s->adj[3];
+    const float *K = s->med[0], *b = s->med[1];
+    const int fid[3] = {LOSS_F_SIGMA, LOSS_F_V1, LOSS_F_V3};
+    for (int64_t c = s->ck_nseg - 1; c >= 0; --c) {
+        const int64_t n0 = c * s->ck_every, nc = std::min(s->ck_every, s->ck_steps - n0);
+        // restore the fused state at step n0 and recompute the segment, keeping div u
+        for (int k = 0; k < 3; ++k)
+            HIPCHK(hipMemcpyAsync(s->f[fid[k]], s->ckpt + (c * 3 + k) * fe, sizeof(float) * fe,
+                                  hipMemcpyDeviceToDevice, s->st));
+        HIPCHK(launch_set_step(s->d_step, n0, s->st));
+        s->fused = true;
+        for (int64_t k = 0; k < nc; ++k)
+            if ((r = one_step(s, s->divstore + k * fe, ss))) return r;
+        // reverse sweep over the segment
+        for (int64_t k = nc - 1; k >= 0; --k) {
+            const int64_t n = n0 + k;
+            if ((r = timed_begin(s))) return r;
+            hipError_t e = launch_residual_inject(s->d_rec_str, s->nrec_str, lam, ss, s->res_dev, n, s->st);
+            if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+            if ((r = timed_end(s, KC_RECEIVER))) return r;
+            // lambda^{n+1} += -dt (Dx^T(b mu1) + Dz^T(b mu3))
+            if ((r = adj_deriv(s, 0, mu1, b, lam, -dt, EPI_AXPY, Y, (int)S))) return r;
+            if ((r = adj_deriv(s, 2, mu3, b, lam, -dt, EPI_AXPY, Y, (int)S))) return r;
+            // dJ/dK += -dt lambda^{n+1} div u^n
+            if ((r = timed_begin(s))) return r;
+            e = launch_grad_accum(s->grad_pad, lam, s->divstore + k * fe, -dt, (int)S, ss, ss, s->st);
+            if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+            if ((r = timed_end(s, KC_GRAD))) return r;
+            // mu^n = mu^{n+1} - dt D^T(K lambda^{n+1})
+            if ((r = adj_deriv(s, 0, lam, K, mu1, -dt, EPI_AXPY, Y, (int)S))) return r;
+            if ((r = adj_deriv(s, 2, lam, K, mu3, -dt, EPI_AXPY, Y, (int)S))) return r;
+        }
+    }
+    hipError_t e = launch_grad_unpad(s->grad_pad, s->grad_dense, s->nx, s->ny * s->nz, s->pitch, s->d_vp,
+                                     s->d_rho, param, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(grad, s->grad_dense, sizeof(double) * s->nodes,
+                          mem == LOSS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    // the wavefields now hold a recomputed intermediate state
+    s->step = s->ck_every < s->ck_steps ? s->ck_every : s->ck_steps;
+    return LOSS_OK;
 }
 
 }  // extern "C"

@@ -86,6 +86,7 @@ enum SolveKind : int {
 
 struct LineArgs {
     const float *in;
+    const float *in_coef;  // optional per-node factor applied to `in` as it is read
     float *out[3];
     const float *coef[3];
     const float *aux;
@@ -124,6 +125,7 @@ hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields
                          double *traces, const int64_t *d_step, int64_t trace_len, float weight,
                          int accumulate, hipStream_t st);
 hipError_t launch_advance(int64_t *d_step, hipStream_t st);
+hipError_t launch_set_step(int64_t *d_step, int64_t v, hipStream_t st);
 // rows = number of x rows (batch * nz * ny); dense <-> padded (row pitch `pitch`)
 hipError_t launch_pad_copy(const float *src, float *dst, int nx, int rows, int64_t pitch, int to_padded,
                            hipStream_t st);
@@ -136,5 +138,8 @@ hipError_t launch_grad_accum(double *g, const float *lam, const float *div, floa
 hipError_t launch_grad_unpad(const double *gp, double *g, int nx, int rows, int64_t pitch, const float *vp,
                              const float *rho, int param, hipStream_t st);
 hipError_t launch_nonfinite(const float *p, int64_t n, int *flag, hipStream_t st);
+// lambda[shot][node] += residual[trace_off + n] for every receiver
+hipError_t launch_residual_inject(const RecDev *rec, int nrec, float *lam, int64_t shot_stride,
+                                  const double *res, int64_t n, hipStream_t st);
 
 }  // namespace loss
