@@ -46,21 +46,47 @@ __device__ __forceinline__ float load_in(const LineArgs &a, int64_t idx, int64_t
     return a.in_coef ? v * a.in_coef[midx] : v;
 }
 
+// Source terms for output j at node (x, y, z) of `shot` (sources sorted by shot).
+__device__ __forceinline__ float source_terms(const LineArgs &a, int j, int shot, int x, int y, int z,
+                                              int64_t midx)
+{
+    const int fid = a.out_field[j];
+    float add = 0.f;
+    const int k1 = a.src_begin[shot + 1];
+    for (int k = a.src_begin[shot]; k < k1; ++k) {
+        const SrcDev &sd = a.src[k];
+        if (fid < sd.field0 || fid >= sd.field0 + sd.nfield) continue;
+        const unsigned ix = (unsigned)(x - sd.x0), iy = (unsigned)(y - sd.y0), iz = (unsigned)(z - sd.z0);
+        if (ix >= (unsigned)sd.bx || iy >= (unsigned)sd.by || iz >= (unsigned)sd.bz) continue;
+        const int64_t n = *a.d_step + a.src_time_offset;
+        if (n < 0 || n >= sd.nt) continue;
+        float v = a.src_scale * a.wavpool[sd.wav_off + n] *
+                  a.wpool[sd.w_off + ((int64_t)iz * sd.by + iy) * sd.bx + ix];
+        if (sd.force) v *= a.bcoef[midx];
+        add += v;
+    }
+    return add;
+}
+
 template <int EPI>
-__device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_t midx, int shot,
-                                         float D)
+__device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float D,
+                                         int x, int y, int z)
 {
     if constexpr (EPI == EPI_STORE) {
         a.out[0][oidx] = D;
     } else if constexpr (EPI == EPI_AXPY) {
         for (int j = 0; j < a.nout; ++j) {
             const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
-            a.out[j][oidx] = fmaf(a.alpha * c, D, a.out[j][oidx]);
+            float v = fmaf(a.alpha * c, D, a.out[j][oidx]);
+            if (a.src) v += source_terms(a, j, shot, x, y, z, midx);
+            a.out[j][oidx] = v;
         }
     } else if constexpr (EPI == EPI_AXPY_AUX) {
         const float dv = D + a.aux[oidx];
         const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
-        a.out[0][oidx] = fmaf(a.alpha * c, dv, a.out[0][oidx]);
+        float v = fmaf(a.alpha * c, dv, a.out[0][oidx]);
+        if (a.src) v += source_terms(a, 0, shot, x, y, z, midx);
+        a.out[0][oidx] = v;
         if (a.div) a.div[(int64_t)shot * a.div_shot_stride + midx] = dv;
     } else {  // EPI_BASE
         const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
@@ -146,6 +172,8 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
     const int shot = (int)(line / ((int64_t)a.nz * a.ny));
     const int64_t base = line * a.pitch;
     const int64_t mbase = base - (int64_t)shot * a.shot_stride;
+    const int rowz = (int)((line / a.ny) % a.nz), rowy = (int)(line % a.ny);
+    if (a.step_inc && blockIdx.x == 0 && threadIdx.x == 0) *a.step_inc += 1;
     const int s = l * M;
     const int e = min(s + M, N);
     const int q = s + k * C;
@@ -219,9 +247,9 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int i = q + c;
-            if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, fmaf(Q[c], wr, w[c]));
+            if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, fmaf(Q[c], wr, w[c]), i, rowy, rowz);
         }
-        if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we);
+        if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we, N, rowy, rowz);
     }
 }
 
@@ -248,6 +276,8 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
     const int64_t obase = (axis == 1) ? (int64_t)o * a.plane : (int64_t)o * a.pitch;
     const int64_t mbase = obase + min(col, a.nx - 1);
     const int64_t base = (int64_t)shot * a.shot_stride + mbase;
+    if (a.step_inc && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
+        *a.step_inc += 1;
     const int N = ax.N, M = ax.M;
     const int s = l * M;
     const int e = min(s + M, N);
@@ -315,10 +345,11 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
             const int i = q + c;
             if (i < e)
                 epilogue<EPI>(a, base + (int64_t)i * stride, mbase + (int64_t)i * stride, shot,
-                              fmaf(Q[c], wr, w[c]));
+                              fmaf(Q[c], wr, w[c]), col, axis == 1 ? i : o, axis == 1 ? o : i);
         }
         if (e == N && wv == kc)
-            epilogue<EPI>(a, base + (int64_t)N * stride, mbase + (int64_t)N * stride, shot, we);
+            epilogue<EPI>(a, base + (int64_t)N * stride, mbase + (int64_t)N * stride, shot, we, col,
+                          axis == 1 ? N : o, axis == 1 ? o : N);
     }
 }
 
@@ -369,7 +400,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(LineArgs a, const float *__r
         const int J = gn[t];
         if (J >= 0) out = fmaf(gc[t], adj_y(ax, Y, a, lb, mlb, stride, J), out);
     }
-    epilogue<EPI>(a, oidx, midx, shot, out);
+    epilogue<EPI>(a, oidx, midx, shot, out, x, yy, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,6 +444,28 @@ __global__ void k_record(const RecDev *__restrict__ rec, int nrec, const float *
 }
 
 __global__ void k_advance(int64_t *d_step) { *d_step += 1; }
+
+__global__ void k_record2(const RecDev *__restrict__ rec0, int nrec0, float w0, int acc0,
+                          const RecDev *__restrict__ rec1, int nrec1, float w1, int acc1,
+                          const float *const *fields, int64_t shot_stride, double *traces,
+                          const int64_t *d_step, int offset, int64_t trace_len)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const RecDev *rec = rec0;
+    float w = w0;
+    int acc = acc0;
+    if (r >= nrec0) {
+        r -= nrec0;
+        if (r >= nrec1) return;
+        rec = rec1; w = w1; acc = acc1;
+    }
+    const int64_t n = *d_step + offset;
+    if (n < 0 || n >= trace_len) return;
+    const RecDev rd = rec[r];
+    const double v = (double)w * (double)fields[rd.comp][(int64_t)rd.shot * shot_stride + rd.node];
+    double *t = traces + rd.trace_off + n;
+    *t = acc ? *t + v : v;
+}
 
 __global__ void k_set_step(int64_t *d_step, int64_t v) { *d_step = v; }
 
@@ -616,6 +669,18 @@ hipError_t launch_residual_inject(const RecDev *rec, int nrec, float *lam, int64
 hipError_t launch_set_step(int64_t *d_step, int64_t v, hipStream_t st)
 {
     hipLaunchKernelGGL(k_set_step, 1, 1, 0, st, d_step, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_record2(const RecDev *rec0, int nrec0, float w0, int acc0, const RecDev *rec1, int nrec1,
+                          float w1, int acc1, const float *const *fields, int64_t shot_stride,
+                          double *traces, const int64_t *d_step, int offset, int64_t trace_len,
+                          hipStream_t st)
+{
+    const int tot = nrec0 + nrec1;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_record2, nblk(tot, 256), 256, 0, st, rec0, nrec0, w0, acc0, rec1, nrec1, w1, acc1,
+                       fields, shot_stride, traces, d_step, offset, trace_len);
     return hipGetLastError();
 }
 

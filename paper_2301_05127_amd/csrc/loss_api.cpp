@@ -77,7 +77,9 @@ struct loss_sim {
     std::vector<std::vector<SrcHost>> src;
     bool src_dirty = true;
     SrcDev *d_src = nullptr;
+    int *d_src_begin = nullptr;    // [S+1]
     int nsrc = 0;
+    bool pending_inc = false;      // next line kernel advances the step counter
     float *d_wpool = nullptr, *d_wavpool = nullptr;
     // receivers
     std::vector<RecHost> rec;
@@ -166,8 +168,13 @@ loss_status timed_end(loss_sim *s, int kc)
     return LOSS_OK;
 }
 
-loss_status run_line(loss_sim *s, int kc, int axis, int solve, int epi, const LineArgs &a)
+loss_status run_line(loss_sim *s, int kc, int axis, int solve, int epi, const LineArgs &a0)
 {
+    LineArgs a = a0;
+    if (s->pending_inc) {
+        a.step_inc = s->d_step;
+        s->pending_inc = false;
+    }
     loss_status r = timed_begin(s);
     if (r) return r;
     hipError_t e = launch_line(axis, solve, epi, a, s->st);
@@ -185,6 +192,21 @@ loss_status deriv_axpy(loss_sim *s, int kc, int axis, const float *in, float alp
     a.nout = nout;
     for (int j = 0; j < nout; ++j) { a.out[j] = out[j]; a.coef[j] = coef[j]; }
     return run_line(s, kc, axis, SOLVE_D1, EPI_AXPY, a);
+}
+
+// Let the epilogue of a line kernel add the sources whose fields are among out_field.
+void attach_sources(const loss_sim *s, LineArgs &a, int time_offset, const int *out_field, int nout)
+{
+    if (s->nsrc == 0) return;
+    a.src = s->d_src;
+    a.src_begin = s->d_src_begin;
+    a.wpool = s->d_wpool;
+    a.wavpool = s->d_wavpool;
+    a.bcoef = s->med.back();
+    a.d_step = s->d_step;
+    a.src_time_offset = time_offset;
+    a.src_scale = (float)s->d.dt;
+    for (int j = 0; j < 3; ++j) a.out_field[j] = j < nout ? out_field[j] : -1;
 }
 
 // out (+)= alpha * D^T (in_coef * in) along axis: the transposed solve y = T^{-T} z on
@@ -224,13 +246,15 @@ loss_status inject(loss_sim *s, float **fields_dev, int time_offset, float scale
     return timed_end(s, KC_SOURCE);
 }
 
-loss_status record(loss_sim *s, const RecDev *rec, int nrec, float weight, int accumulate)
+// record one or two receiver lists into trace sample (*d_step - 1) (inside a step)
+loss_status record(loss_sim *s, const RecDev *rec0, int nrec0, float w0, int acc0,
+                   const RecDev *rec1 = nullptr, int nrec1 = 0, float w1 = 0.f, int acc1 = 0)
 {
-    if (nrec == 0 || s->d.trace_len == 0) return LOSS_OK;
+    if (nrec0 + nrec1 == 0 || s->d.trace_len == 0) return LOSS_OK;
     loss_status r = timed_begin(s);
     if (r) return r;
-    hipError_t e = launch_record(rec, nrec, s->d_fields, s->shot_stride, s->traces, s->d_step,
-                                 s->d.trace_len, weight, accumulate, s->st);
+    hipError_t e = launch_record2(rec0, nrec0, w0, acc0, rec1, nrec1, w1, acc1, s->d_fields, s->shot_stride,
+                                  s->traces, s->d_step, -1, s->d.trace_len, s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("record: ") + hipGetErrorString(e));
     return timed_end(s, KC_RECEIVER);
 }
@@ -239,7 +263,8 @@ loss_status record(loss_sim *s, const RecDev *rec, int nrec, float weight, int a
 // acoustic: v1 -= a b dsigma/dx, v3 -= a b dsigma/dz ; elastic: v_i += a b d_j sigma_ij
 // `vel` are the velocity destinations (state or a temporary), `base` optional source
 // for EPI_BASE on the first pass of each component.
-loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const float *const *base)
+loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const float *const *base,
+                           bool with_forces = false)
 {
     const float *b = s->med.back();
     loss_status r;
@@ -254,6 +279,10 @@ loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const flo
             a.coef[0] = b;
             int epi = EPI_AXPY;
             if (base) { a.aux = base[c]; epi = EPI_BASE; }
+            if (with_forces) {
+                const int fid = c == 0 ? LOSS_F_V1 : LOSS_F_V3;
+                attach_sources(s, a, 0, &fid, 1);
+            }
             r = run_line(s, c == 0 ? KC_VEL_X : KC_VEL_Z, axis, SOLVE_D1, epi, a);
             if (r) return r;
         }
@@ -272,6 +301,10 @@ loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const flo
             a.coef[0] = b;
             int epi = EPI_AXPY;
             if (base && j == 0) { a.aux = base[i]; epi = EPI_BASE; }
+            if (with_forces && j == 2) {
+                const int fid = LOSS_F_EV1 + i;
+                attach_sources(s, a, 0, &fid, 1);
+            }
             r = run_line(s, KC_VEL_X + j, j, SOLVE_D1, epi, a);
             if (r) return r;
         }
@@ -298,16 +331,26 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         c.alpha = -dt;
         c.div = div_store;
         c.div_shot_stride = div_shot_stride;
+        const int fid = LOSS_F_SIGMA;
+        attach_sources(s, c, -1, &fid, 1);
         return run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_AXPY_AUX, c);
     }
     float *const *F = s->f.data();
     const float *lam = s->med[0], *mu = s->med[1], *l2m = s->med[2];
     // normal components from d_i v_i
     for (int i = 0; i < 3; ++i) {
-        float *out[3] = {F[LOSS_F_S11], F[LOSS_F_S22], F[LOSS_F_S33]};
-        const float *coef[3] = {lam, lam, lam};
-        coef[i] = l2m;
-        r = deriv_axpy(s, KC_STRESS_X + i, i, F[LOSS_F_EV1 + i], dt, 3, out, coef);
+        LineArgs a = base_args(s, i);
+        a.in = F[LOSS_F_EV1 + i];
+        a.alpha = dt;
+        a.nout = 3;
+        a.out[0] = F[LOSS_F_S11]; a.out[1] = F[LOSS_F_S22]; a.out[2] = F[LOSS_F_S33];
+        a.coef[0] = a.coef[1] = a.coef[2] = lam;
+        a.coef[i] = l2m;
+        if (i == 2) {
+            const int fid[3] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33};
+            attach_sources(s, a, -1, fid, 3);
+        }
+        r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_AXPY, a);
         if (r) return r;
     }
     // shear components: sigma_ij += dt mu (d_i v_j + d_j v_i)
@@ -384,6 +427,10 @@ loss_status upload_sources(loss_sim *s)
             wavpool.insert(wavpool.end(), h.wavelet.begin(), h.wavelet.end());
             sd.push_back(d);
         }
+    std::vector<int> begin(s->S + 1, 0);
+    for (const SrcDev &d : sd) begin[d.shot + 1]++;
+    for (int k = 0; k < s->S; ++k) begin[k + 1] += begin[k];
+    if (s->d_src_begin) { s->release(s->d_src_begin); s->d_src_begin = nullptr; }
     if (s->d_src) { s->release(s->d_src); s->d_src = nullptr; }
     if (s->d_wpool) { s->release(s->d_wpool); s->d_wpool = nullptr; }
     if (s->d_wavpool) { s->release(s->d_wavpool); s->d_wavpool = nullptr; }
@@ -394,6 +441,8 @@ loss_status upload_sources(loss_sim *s)
         if ((r = s->alloc(&s->d_wpool, wpool.size()))) return r;
         if ((r = s->alloc(&s->d_wavpool, wavpool.size()))) return r;
         HIPCHK(hipMemcpy(s->d_src, sd.data(), sd.size() * sizeof(SrcDev), hipMemcpyHostToDevice));
+        if ((r = s->alloc(&s->d_src_begin, begin.size()))) return r;
+        HIPCHK(hipMemcpy(s->d_src_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(s->d_wpool, wpool.data(), wpool.size() * sizeof(float), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(s->d_wavpool, wavpool.data(), wavpool.size() * sizeof(float), hipMemcpyHostToDevice));
     }
@@ -517,25 +566,21 @@ loss_status unfuse_in_place(loss_sim *s)
     return LOSS_OK;
 }
 
-// One fused step: B(dt), sources, stress receivers, A(dt) [two half steps], forces,
-// velocity receivers, counter.
+// One fused step.  The first line kernel advances the step counter, so inside the
+// step *d_step = n + 1: stress sources use sample n (offset -1, added in the stress
+// epilogue), forces sample n + 1 (offset 0, velocity epilogue), traces slot n.
 loss_status one_step(loss_sim *s, float *div_store, int64_t div_shot_stride)
 {
     loss_status r;
+    s->pending_inc = true;
     if ((r = stress_stage(s, div_store, div_shot_stride))) return r;
-    if ((r = inject(s, s->d_fields, 0, 1.0f, 0))) return r;
-    if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0))) return r;
-    if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 0))) return r;
+    if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0, s->d_rec_vel, s->nrec_vel, 0.5f, 0))) return r;
     std::vector<float *> vel;
     if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
     else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
-    if ((r = velocity_stage(s, (float)s->d.dt, vel.data(), nullptr))) return r;
-    if ((r = inject(s, s->d_fields, 1, 1.0f, 1))) return r;
+    if ((r = velocity_stage(s, (float)s->d.dt, vel.data(), nullptr, true))) return r;
     if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 1))) return r;
-    if ((r = timed_begin(s))) return r;
-    hipError_t e = launch_advance(s->d_step, s->st);
-    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
-    return timed_end(s, KC_ADVANCE);
+    return LOSS_OK;
 }
 
 loss_status ensure_ready(loss_sim *s)

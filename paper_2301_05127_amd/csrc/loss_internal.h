@@ -84,6 +84,8 @@ enum SolveKind : int {
     SOLVE_T1 = 2,         // adjoint phase 1: y = T^{-T} z on patch interiors
 };
 
+struct SrcDev;
+
 struct LineArgs {
     const float *in;
     const float *in_coef;  // optional per-node factor applied to `in` as it is read
@@ -98,6 +100,17 @@ struct LineArgs {
     int S, nx, ny, nz;     // node counts
     int64_t pitch, plane, shot_stride;
     AxisDev ax;
+    // step counter: if set, one thread adds 1 at kernel start (first kernel of a step)
+    int64_t *step_inc;
+    // sources added in the epilogue to out[j] when out_field[j] is one of their fields:
+    // out += src_scale * wavelet[*d_step + src_time_offset] * weight (* b for forces)
+    const SrcDev *src;
+    const int *src_begin;  // [S+1] index of the first source of each shot
+    const float *wpool, *wavpool, *bcoef;
+    const int64_t *d_step;
+    int src_time_offset;
+    float src_scale;
+    int out_field[3];
 };
 
 // Launch helpers (kernels.hip).  axis: 0 = x (contiguous), 1 = y, 2 = z.
@@ -124,6 +137,11 @@ hipError_t launch_inject(const SrcDev *src, int nsrc, float *const *fields, cons
 hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields, int64_t shot_stride,
                          double *traces, const int64_t *d_step, int64_t trace_len, float weight,
                          int accumulate, hipStream_t st);
+// two receiver lists in one launch; sample index = *d_step + offset
+hipError_t launch_record2(const RecDev *rec0, int nrec0, float w0, int acc0, const RecDev *rec1, int nrec1,
+                          float w1, int acc1, const float *const *fields, int64_t shot_stride,
+                          double *traces, const int64_t *d_step, int offset, int64_t trace_len,
+                          hipStream_t st);
 hipError_t launch_advance(int64_t *d_step, hipStream_t st);
 hipError_t launch_set_step(int64_t *d_step, int64_t v, hipStream_t st);
 // rows = number of x rows (batch * nz * ny); dense <-> padded (row pitch `pitch`)
