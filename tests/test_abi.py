@@ -44,3 +44,62 @@ def test_desc_layout_matches_header():
     assert Desc.n.offset == 8 and Desc.h.offset == 32 and Desc.dt.offset == 56
     assert Desc.patch.offset == 64 and Desc.flags.offset == 88 and Desc.trace_len.offset == 96
     assert ctypes.sizeof(Desc) == 104
+
+
+def _desc(**kw):
+    from paper_2301_05127_amd.loss import Desc
+    d = Desc()
+    d.physics, d.ndim = 0, 2
+    for a, (n, h, m) in enumerate([(64, 10.0, 32), (0, 10.0, 32), (64, 10.0, 32)]):
+        d.n[a], d.h[a], d.patch[a] = n, h, m
+    d.dt, d.halo, d.end_mode, d.nshots, d.flags, d.trace_len = 1e-3, 8, 0, 1, 0, 0
+    for k, v in kw.items():
+        if k in ("n", "h", "patch"):
+            for a, x in enumerate(v):
+                getattr(d, k)[a] = x
+        else:
+            setattr(d, k, v)
+    return d
+
+
+import pytest  # noqa: E402
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(ndim=3), "acoustic physics is 2-D"),
+    (dict(physics=1), "elastic physics is 3-D"),
+    (dict(physics=7), "unknown physics"),
+    (dict(nshots=0), "nshots"),
+    (dict(dt=0.0), "dt must be positive"),
+    (dict(trace_len=-1), "trace_len"),
+    (dict(n=(64, 5, 64)), "n[1] == 0"),
+    (dict(halo=0), "halo must be in 1..64"),
+    (dict(halo=65), "halo must be in 1..64"),
+    (dict(n=(1, 0, 64)), "at least 2 intervals"),
+    (dict(patch=(0, 32, 32)), "patch length"),
+    (dict(end_mode=2, halo=40), "periodic axis needs"),
+    (dict(end_mode=5), "unknown end mode"),
+    (dict(h=(0.0, 10.0, 10.0)), "spacing"),
+    (dict(patch=(4, 4, 4), halo=9), "patch too short"),
+])
+def test_create_rejects_bad_descriptions(kw, needle):
+    """Invalid descriptions are rejected with LOSS_EINVAL before any device call."""
+    import ctypes as C
+    from paper_2301_05127_amd import loss
+    L = loss.lib()
+    d = _desc(**kw)
+    h = C.c_void_p()
+    st = L.loss_create(C.byref(d), None, C.byref(h))
+    assert st == -1, (st, L.loss_last_error())
+    assert needle in L.loss_last_error().decode(), L.loss_last_error()
+    assert not h.value
+
+
+def test_null_arguments():
+    import ctypes as C
+    from paper_2301_05127_amd import loss
+    L = loss.lib()
+    assert L.loss_create(None, None, None) == -1
+    assert L.loss_destroy(None) == 0
+    assert L.loss_step(None, 1) == -1
+    assert L.loss_current_step(None) == -1
