@@ -94,6 +94,46 @@ __device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_
     }
 }
 
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+__device__ __forceinline__ float4 fma4(float a, float4 c, float4 d, float4 o)
+{
+    return make_float4(fmaf(a * c.x, d.x, o.x), fmaf(a * c.y, d.y, o.y), fmaf(a * c.z, d.z, o.z),
+                       fmaf(a * c.w, d.w, o.w));
+}
+
+// Epilogue of four consecutive x nodes (16-byte aligned, all inside the unit).
+template <int EPI>
+__device__ __forceinline__ void epilogue4(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float4 D,
+                                          int x, int y, int z)
+{
+    if (a.src) {
+        epilogue<EPI>(a, oidx, midx, shot, D.x, x, y, z);
+        epilogue<EPI>(a, oidx + 1, midx + 1, shot, D.y, x + 1, y, z);
+        epilogue<EPI>(a, oidx + 2, midx + 2, shot, D.z, x + 2, y, z);
+        epilogue<EPI>(a, oidx + 3, midx + 3, shot, D.w, x + 3, y, z);
+        return;
+    }
+    const float4 one = make_float4(1.f, 1.f, 1.f, 1.f);
+    if constexpr (EPI == EPI_STORE) {
+        st4(a.out[0] + oidx, D);
+    } else if constexpr (EPI == EPI_AXPY) {
+        for (int j = 0; j < a.nout; ++j) {
+            const float4 c = a.coef[j] ? ld4(a.coef[j] + midx) : one;
+            st4(a.out[j] + oidx, fma4(a.alpha, c, D, ld4(a.out[j] + oidx)));
+        }
+    } else if constexpr (EPI == EPI_AXPY_AUX) {
+        const float4 t = ld4(a.aux + oidx);
+        const float4 dv = make_float4(D.x + t.x, D.y + t.y, D.z + t.z, D.w + t.w);
+        const float4 c = a.coef[0] ? ld4(a.coef[0] + midx) : one;
+        st4(a.out[0] + oidx, fma4(a.alpha, c, dv, ld4(a.out[0] + oidx)));
+        if (a.div) st4(a.div + (int64_t)shot * a.div_shot_stride + midx, dv);
+    } else {
+        const float4 c = a.coef[0] ? ld4(a.coef[0] + midx) : one;
+        st4(a.out[0] + oidx, fma4(a.alpha, c, D, ld4(a.aux + oidx)));
+    }
+}
+
 // Right-hand side of row i of the solved system for the chunk value layout
 // u[c] = node q-1+c (so node i = q+cc sits at u[cc+1]).
 template <int SOLVE>
@@ -179,11 +219,32 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
     const int q = s + k * C;
     const float *__restrict__ in = a.in;
 
+    // chunk values u[1..C] = nodes q..q+C-1 (16-byte loads when aligned and inside
+    // the line); u[0], u[C+1] = the neighbouring lanes' edge nodes
     float u[C + 2];
+    if (!a.in_coef && ((q & 3) == 0) && q + C - 1 <= N) {
 #pragma unroll
-    for (int c = 0; c < C + 2; ++c) {
-        const int i = clampi(q - 1 + c, 0, N);
-        u[c] = load_in(a, base + i, mbase + i);
+        for (int g4 = 0; g4 < C / 4; ++g4) {
+            const float4 v = ld4(in + base + q + 4 * g4);
+            u[1 + 4 * g4] = v.x; u[2 + 4 * g4] = v.y; u[3 + 4 * g4] = v.z; u[4 + 4 * g4] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int c = 1; c <= C; ++c) {
+            const int i = min(q - 1 + c, N);
+            u[c] = load_in(a, base + i, mbase + i);
+        }
+    }
+    {
+        const float left = __shfl_up(u[C], 1, G);
+        const float right = __shfl_down(u[1], 1, G);
+        u[0] = (k == 0) ? u[1] : left;   // row s never uses node s-1
+        if (k == G - 1) {
+            const int i = min(q + C, N);
+            u[C + 1] = load_in(a, base + i, mbase + i);
+        } else {
+            u[C + 1] = right;
+        }
     }
 
     float y[C], P[C];
@@ -192,7 +253,15 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int i = min(q + c, N);
-        const float r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, fac[c]);
+        float r;
+        if (SOLVE == SOLVE_D1 && i != s) {
+            // rows strictly inside the patch: [1 4 1] with rhs (3/h)(u_{i+1} - u_{i-1})
+            const float2 f = ax.lum[i];
+            fac[c] = make_float4(f.x, f.y, 1.f, 0.f);
+            r = ax.s3 * (u[c + 2] - u[c]);
+        } else {
+            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, fac[c]);
+        }
         yv = fmaf(-fac[c].x, yv, r);
         pv = -fac[c].x * pv;
         y[c] = yv;
@@ -245,9 +314,19 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
 
     if (uact) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int i = q + c;
-            if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, fmaf(Q[c], wr, w[c]), i, rowy, rowz);
+        for (int c = 0; c < C; ++c) w[c] = fmaf(Q[c], wr, w[c]);
+        if (((q & 3) == 0) && q + C <= e) {
+#pragma unroll
+            for (int g4 = 0; g4 < C / 4; ++g4)
+                epilogue4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4, shot,
+                               make_float4(w[4 * g4], w[4 * g4 + 1], w[4 * g4 + 2], w[4 * g4 + 3]),
+                               q + 4 * g4, rowy, rowz);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int i = q + c;
+                if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, w[c], i, rowy, rowz);
+            }
         }
         if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we, N, rowy, rowz);
     }

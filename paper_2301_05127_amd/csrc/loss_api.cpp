@@ -675,22 +675,23 @@ loss_status upload_axis(loss_sim *s, int axis)
     const AxisHost &h = s->axh[axis];
     const int n = h.N + 1;
     std::vector<float4> lu(n), rc(n), luT(n), lu2(n);
-    std::vector<float2> lu2c(n);
+    std::vector<float2> lu2c(n), lum(n);
     for (int i = 0; i < n; ++i) {
         lu[i] = make_float4((float)h.m[i], (float)h.invd[i], (float)h.sup[i], (float)h.kind[i]);
         rc[i] = make_float4((float)h.cm[i], (float)h.c0[i], (float)h.cp[i], (float)h.slot[i]);
         luT[i] = make_float4((float)h.mT[i], (float)h.invdT[i], (float)h.supT[i], (float)h.subT[i]);
         lu2[i] = make_float4((float)h.m2[i], (float)h.invd2[i], (float)h.sup2[i], 0.f);
         lu2c[i] = make_float2((float)h.m2c[i], (float)h.invd2c[i]);
+        lum[i] = make_float2((float)h.m[i], (float)h.invd[i]);
     }
     std::vector<float> tc(h.tap_c.begin(), h.tap_c.end()), gc(h.g_c.begin(), h.g_c.end());
     float4 *dlu, *drc, *dluT, *dlu2;
-    float2 *dlu2c;
+    float2 *dlu2c, *dlum;
     int *dti, *dgn;
     float *dtc, *dgc;
     loss_status r;
     if ((r = s->alloc(&dlu, n)) || (r = s->alloc(&drc, n)) || (r = s->alloc(&dluT, n)) ||
-        (r = s->alloc(&dlu2, n)) || (r = s->alloc(&dlu2c, n)) ||
+        (r = s->alloc(&dlu2, n)) || (r = s->alloc(&dlu2c, n)) || (r = s->alloc(&dlum, n)) ||
         (r = s->alloc(&dti, std::max<size_t>(1, h.tap_idx.size()))) ||
         (r = s->alloc(&dtc, std::max<size_t>(1, tc.size()))) ||
         (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())))
@@ -700,6 +701,7 @@ loss_status upload_axis(loss_sim *s, int axis)
     HIPCHK(hipMemcpy(dluT, luT.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dlu2, lu2.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dlu2c, lu2c.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dlum, lum.data(), n * sizeof(float2), hipMemcpyHostToDevice));
     if (!h.tap_idx.empty()) {
         HIPCHK(hipMemcpy(dti, h.tap_idx.data(), h.tap_idx.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(dtc, tc.data(), tc.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -708,6 +710,8 @@ loss_status upload_axis(loss_sim *s, int axis)
     HIPCHK(hipMemcpy(dgc, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice));
     AxisDev &d = s->axd[axis];
     d.N = h.N; d.M = h.M; d.p = h.p; d.ntap = 2 * h.halo + 1; d.h = (float)h.h;
+    d.s3 = (float)(3.0 / h.h);
+    d.lum = dlum;
     d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
     d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc;
     return LOSS_OK;

@@ -58,6 +58,8 @@ std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_m
 struct AxisDev {
     int N, M, p, ntap;
     float h;
+    float s3;              // 3/h, the stencil weight of interior rows of G
+    const float2 *lum;     // {m, invd} of T (compact copy for interior rows)
     const float4 *lu;      // {m, invd, sup, kind}
     const float4 *rc;      // {cm, c0, cp, slot}
     const float4 *luT;     // {mT, invdT, supT, subT}
