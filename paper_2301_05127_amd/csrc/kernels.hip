@@ -337,30 +337,41 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
 // ---------------------------------------------------------------------------
 constexpr int kMaxWaves = 16;
 
+// Columns are the flattened (shot, other coordinate, x) positions of the lines: one
+// lane per column, CW consecutive columns per wave (64, 32 or 16), the 64/CW lane
+// groups of a wave and the waves of the block holding consecutive chunks of C nodes
+// along the axis.  Chunk maps are composed through LDS.
 template <int C, int SOLVE, int EPI>
-__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
+__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW)
 {
-    __shared__ float sA[kMaxWaves][64], sB[kMaxWaves][64], sQ[kMaxWaves][64], sW[kMaxWaves][64];
+    __shared__ float sA[1024], sB[1024], sQ[1024], sW[1024];
     __shared__ float sWe[64];
     const AxisDev &ax = a.ax;
-    const int W = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int col = blockIdx.x * 64 + lane;
-    const bool cact = col < a.nx;
-    const int l = blockIdx.y;
+    const int wv = threadIdx.x >> 6;
+    const int SUB = 64 / CW;
+    const int NCH = (blockDim.x >> 6) * SUB;
+    const int ci = lane % CW;
+    const int chunk = wv * SUB + lane / CW;
     const int n_other = (axis == 1) ? a.nz : a.ny;
-    const int shot = blockIdx.z / n_other, o = blockIdx.z % n_other;
+    const int64_t fcol = (int64_t)blockIdx.x * CW + ci;
+    const int64_t per_shot = (int64_t)n_other * a.pitch;
+    const int shot0 = (int)(fcol / per_shot);
+    const int64_t rem = fcol - (int64_t)shot0 * per_shot;
+    const int o = (int)(rem / a.pitch);
+    const int col = (int)(rem - (int64_t)o * a.pitch);
+    const bool cact = col < a.nx && shot0 < a.S;
+    const int shot = min(shot0, a.S - 1);
+    const int l = blockIdx.y;
     const int64_t stride = (axis == 1) ? a.pitch : a.plane;
     const int64_t obase = (axis == 1) ? (int64_t)o * a.plane : (int64_t)o * a.pitch;
     const int64_t mbase = obase + min(col, a.nx - 1);
     const int64_t base = (int64_t)shot * a.shot_stride + mbase;
-    if (a.step_inc && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0)
-        *a.step_inc += 1;
+    if (a.step_inc && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.step_inc += 1;
     const int N = ax.N, M = ax.M;
     const int s = l * M;
     const int e = min(s + M, N);
-    const int q = s + wv * C;
+    const int q = s + chunk * C;
     const float *__restrict__ in = a.in;
 
     float u[C + 2];
@@ -382,21 +393,21 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
         y[c] = yv;
         P[c] = pv;
     }
-    sA[wv][lane] = pv;
-    sB[wv][lane] = yv;
+    sA[chunk * CW + ci] = pv;
+    sB[chunk * CW + ci] = yv;
     __syncthreads();
     float yin = 0.f;
-    for (int j = 0; j < wv; ++j) yin = fmaf(sA[j][lane], yin, sB[j][lane]);
+    for (int j = 0; j < chunk; ++j) yin = fmaf(sA[j * CW + ci], yin, sB[j * CW + ci]);
 #pragma unroll
     for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
 
     const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
-    if (wv == kc) {
+    if (chunk == kc) {
         float ylast = 0.f, ulast = 0.f, ue = 0.f;
 #pragma unroll
         for (int c = 0; c < C; ++c)
             if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
-        sWe[lane] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, stride);
+        sWe[ci] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, stride);
     }
 
     float w[C], Q[C];
@@ -411,24 +422,25 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis)
         w[c] = wvv;
         Q[c] = qv;
     }
-    sQ[wv][lane] = qv;
-    sW[wv][lane] = wvv;
+    sQ[chunk * CW + ci] = qv;
+    sW[chunk * CW + ci] = wvv;
     __syncthreads();
-    const float we = sWe[lane];
+    const float we = sWe[ci];
     float wr = we;
-    for (int j = W - 1; j > wv; --j) wr = fmaf(sQ[j][lane], wr, sW[j][lane]);
+    for (int j = NCH - 1; j > chunk; --j) wr = fmaf(sQ[j * CW + ci], wr, sW[j * CW + ci]);
 
     if (cact) {
+        const int cy = axis == 1 ? 0 : o, cz = axis == 1 ? o : 0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int i = q + c;
             if (i < e)
                 epilogue<EPI>(a, base + (int64_t)i * stride, mbase + (int64_t)i * stride, shot,
-                              fmaf(Q[c], wr, w[c]), col, axis == 1 ? i : o, axis == 1 ? o : i);
+                              fmaf(Q[c], wr, w[c]), col, axis == 1 ? i : cy, axis == 1 ? cz : i);
         }
-        if (e == N && wv == kc)
+        if (e == N && chunk == kc)
             epilogue<EPI>(a, base + (int64_t)N * stride, mbase + (int64_t)N * stride, shot, we, col,
-                          axis == 1 ? N : o, axis == 1 ? o : N);
+                          axis == 1 ? N : cy, axis == 1 ? cz : N);
     }
 }
 
@@ -661,16 +673,22 @@ template <int C, int SOLVE>
 hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
 {
     const int M = a.ax.M;
-    const int W = (M + C - 1) / C;
-    if (W > kMaxWaves) return hipErrorInvalidValue;
+    const int nch = (M + C - 1) / C;
     const int n_other = axis == 1 ? a.nz : a.ny;
-    dim3 grid((a.nx + 63) / 64, a.ax.p, a.S * n_other);
+    const int64_t F = (int64_t)a.S * n_other * a.pitch;
+    // columns per wave: the widest that still gives >= 2048 blocks (or 16)
+    int CW = 64;
+    while (CW > 16 && ((F + CW - 1) / CW) * a.ax.p < 2048) CW >>= 1;
+    const int sub = 64 / CW;
+    const int W = (nch + sub - 1) / sub;
+    if (W > kMaxWaves) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((F + CW - 1) / CW), a.ax.p, 1);
     const int threads = 64 * W;
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, 0, st, a, axis); break;
-    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, 0, st, a, axis); break;
-    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, 0, st, a, axis); break;
-    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, 0, st, a, axis); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, 0, st, a, axis, CW); break;
+    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, 0, st, a, axis, CW); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, 0, st, a, axis, CW); break;
+    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, 0, st, a, axis, CW); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

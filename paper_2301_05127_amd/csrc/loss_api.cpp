@@ -756,7 +756,7 @@ loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out)
     s->nx = (int)d.n[0] + 1;
     s->ny = d.ndim == 3 ? (int)d.n[1] + 1 : 1;
     s->nz = (int)d.n[2] + 1;
-    s->pitch = ((int64_t)s->nx + 31) / 32 * 32;
+    s->pitch = ((int64_t)s->nx + 3) / 4 * 4;
     s->plane = s->pitch * s->ny;
     s->shot_stride = s->plane * s->nz;
     s->nodes = (int64_t)s->nx * s->ny * s->nz;
