@@ -136,16 +136,17 @@ __device__ __forceinline__ void epilogue4(const LineArgs &a, int64_t oidx, int64
 
 // Right-hand side of row i of the solved system for the chunk value layout
 // u[c] = node q-1+c (so node i = q+cc sits at u[cc+1]).
+// phi_s: the PMBC slope of row s when the caller has already formed it (NAN = form it here)
 template <int SOLVE>
 __device__ __forceinline__ float row_rhs(const AxisDev &ax, int i, int s, float um, float u0, float up,
                                          const float *__restrict__ in, int64_t base, int64_t stride,
-                                         float4 &fac)
+                                         float4 &fac, float phi_s = __builtin_nanf(""))
 {
     if constexpr (SOLVE == SOLVE_D1) {
         fac = ax.lu[i];
         const float4 rc = ax.rc[i];
         float r = fmaf(rc.x, um, fmaf(rc.y, u0, rc.z * up));
-        if (rc.w >= 0.f) r = pmbc_phi(ax, (int)rc.w, in, base, stride);
+        if (rc.w >= 0.f) r = (i == s && phi_s == phi_s) ? phi_s : pmbc_phi(ax, (int)rc.w, in, base, stride);
         return r;
     } else if constexpr (SOLVE == SOLVE_T1) {
         fac = ax.luT[i];
@@ -156,7 +157,7 @@ __device__ __forceinline__ float row_rhs(const AxisDev &ax, int i, int s, float 
         if (i == s) {
             const float4 l = ax.lu[i];
             if (l.w == (float)ROW_NATURAL_L) return 0.f;
-            const float phi = pmbc_phi(ax, (int)ax.rc[i].w, in, base, stride);
+            const float phi = (phi_s == phi_s) ? phi_s : pmbc_phi(ax, (int)ax.rc[i].w, in, base, stride);
             return 6.f * ih * fmaf(up - u0, ih, -phi);
         }
         return 6.f * ih * ih * (um - 2.f * u0 + up);
@@ -167,13 +168,14 @@ __device__ __forceinline__ float row_rhs(const AxisDev &ax, int i, int s, float 
 template <int SOLVE>
 __device__ __forceinline__ float closing_row(const AxisDev &ax, int e, float ylast, float ulast,
                                              float ue, const float *__restrict__ in, int64_t base,
-                                             int64_t stride)
+                                             int64_t stride, float phi_e = __builtin_nanf(""))
 {
     if constexpr (SOLVE == SOLVE_D1) {
         const float4 lu = ax.lu[e];
         const float4 rc = ax.rc[e];
-        const float r = (rc.w >= 0.f) ? pmbc_phi(ax, (int)rc.w, in, base, stride)
-                                       : fmaf(rc.x, ulast, rc.y * ue);
+        const float r = (rc.w >= 0.f)
+                            ? ((phi_e == phi_e) ? phi_e : pmbc_phi(ax, (int)rc.w, in, base, stride))
+                            : fmaf(rc.x, ulast, rc.y * ue);
         return (r - lu.x * ylast) * lu.y;
     } else if constexpr (SOLVE == SOLVE_T1) {
         const float4 lu = ax.luT[e];
@@ -184,7 +186,7 @@ __device__ __forceinline__ float closing_row(const AxisDev &ax, int e, float yla
         float r = 0.f;
         if (l.w != (float)ROW_NATURAL_R) {
             const float ih = 1.f / ax.h;
-            const float phi = pmbc_phi(ax, (int)ax.rc[e].w, in, base, stride);
+            const float phi = (phi_e == phi_e) ? phi_e : pmbc_phi(ax, (int)ax.rc[e].w, in, base, stride);
             r = 6.f * ih * fmaf(-(ue - ulast), ih, phi);
         }
         return (r - f.x * ylast) * f.y;
@@ -247,6 +249,31 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
         }
     }
 
+    // PMBC slopes of rows s and e: the G lanes of the unit share the taps, then a
+    // butterfly sum over the group (no lane walks the halo alone)
+    float phs = 0.f, phe = 0.f;
+    if constexpr (SOLVE == SOLVE_D1 || SOLVE == SOLVE_D2) {
+        const int ss = (int)ax.rc[s].w, se = (int)ax.rc[e].w;
+        // tap t of the row at junction J sits at node J - halo + t (wrapped on a periodic
+        // axis; taps outside the line carry a zero coefficient)
+        for (int t = k; t < ax.ntap; t += G) {
+            if (ss >= 0) {
+                int ki = s - ax.halo + t;
+                ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
+                phs = fmaf(ax.tap_c[(int64_t)ss * ax.ntap + t], in[base + ki], phs);
+            }
+            if (se >= 0) {
+                int ki = e - ax.halo + t;
+                ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
+                phe = fmaf(ax.tap_c[(int64_t)se * ax.ntap + t], in[base + ki], phe);
+            }
+        }
+        for (int d = G >> 1; d > 0; d >>= 1) {
+            phs += __shfl_xor(phs, d, G);
+            phe += __shfl_xor(phe, d, G);
+        }
+    }
+
     float y[C], P[C];
     float4 fac[C];
     float yv = 0.f, pv = 1.f;
@@ -260,7 +287,7 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
             fac[c] = make_float4(f.x, f.y, 1.f, 0.f);
             r = ax.s3 * (u[c + 2] - u[c]);
         } else {
-            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, fac[c]);
+            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, fac[c], phs);
         }
         yv = fmaf(-fac[c].x, yv, r);
         pv = -fac[c].x * pv;
@@ -286,7 +313,7 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
 #pragma unroll
         for (int c = 0; c < C; ++c)
             if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
-        we = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, 1);
+        we = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, 1, phe);
     }
     we = __shfl(we, kc, G);
 
@@ -581,9 +608,11 @@ __global__ void k_pad_copy(const float *__restrict__ src, float *__restrict__ ds
     else dst[idx] = src[p];
 }
 
+// Media times the time step, formed in double and rounded once:
+// acoustic dt K, dt b; elastic dt lambda, dt mu, dt (lambda + 2 mu), dt b.
 __global__ void k_media(const float *__restrict__ vp, const float *__restrict__ vs,
                         const float *__restrict__ rho, float *m0, float *m1, float *m2, float *m3,
-                        int physics, int nx, int64_t pitch, int64_t total)
+                        int physics, int nx, int64_t pitch, int64_t total, double dt)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
@@ -591,15 +620,15 @@ __global__ void k_media(const float *__restrict__ vp, const float *__restrict__ 
     const int64_t p = (idx / nx) * pitch + x;
     const double r = rho[idx], c = vp[idx];
     if (physics == 0) {
-        m0[p] = (float)(r * c * c);   // K
-        m1[p] = (float)(1.0 / r);     // b
+        m0[p] = (float)(dt * r * c * c);   // dt K
+        m1[p] = (float)(dt / r);           // dt b
     } else {
         const double cs = vs[idx];
         const double mu = r * cs * cs, lam = r * c * c - 2.0 * mu;
-        m0[p] = (float)lam;
-        m1[p] = (float)mu;
-        m2[p] = (float)(lam + 2.0 * mu);
-        m3[p] = (float)(1.0 / r);
+        m0[p] = (float)(dt * lam);
+        m1[p] = (float)(dt * mu);
+        m2[p] = (float)(dt * (lam + 2.0 * mu));
+        m3[p] = (float)(dt / r);
     }
 }
 
@@ -798,12 +827,12 @@ hipError_t launch_pad_copy(const float *src, float *dst, int nx, int rows, int64
 }
 
 hipError_t launch_media(const float *vp, const float *vs, const float *rho, float *const *media,
-                        int physics, int nx, int rows, int64_t pitch, hipStream_t st)
+                        int physics, int nx, int rows, int64_t pitch, double dt, hipStream_t st)
 {
     const int64_t total = (int64_t)rows * nx;
     hipLaunchKernelGGL(k_media, nblk(total, 256), 256, 0, st, vp, vs, rho, media[0], media[1],
                        physics ? media[2] : nullptr, physics ? media[3] : nullptr, physics, nx, pitch,
-                       total);
+                       total, dt);
     return hipGetLastError();
 }
 

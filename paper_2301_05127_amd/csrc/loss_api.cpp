@@ -65,7 +65,7 @@ struct loss_sim {
     int64_t pitch = 0, plane = 0, shot_stride = 0, nodes = 0;
     std::vector<void *> allocs;
     std::vector<float *> f;        // nf fields [S][nz][ny][pitch]
-    std::vector<float *> med;      // acoustic K, b; elastic lambda, mu, lambda+2mu, b
+    std::vector<float *> med;      // times dt: acoustic K, b; elastic lambda, mu, lambda+2mu, b
     float *tmp[3] = {nullptr, nullptr, nullptr};
     float **d_fields = nullptr;    // device copy of f
     float **d_tmpfields = nullptr; // device pointer table used for unfused velocity output
@@ -195,7 +195,10 @@ loss_status deriv_axpy(loss_sim *s, int kc, int axis, const float *in, float alp
 }
 
 // Let the epilogue of a line kernel add the sources whose fields are among out_field.
-void attach_sources(const loss_sim *s, LineArgs &a, int time_offset, const int *out_field, int nout)
+// Stress sources are added as dt * s(t) * weight; body forces as (dt b) * f(t) * weight
+// with dt b taken from the media array, so their scale is 1.
+void attach_sources(const loss_sim *s, LineArgs &a, int time_offset, const int *out_field, int nout,
+                    bool forces)
 {
     if (s->nsrc == 0) return;
     a.src = s->d_src;
@@ -205,7 +208,7 @@ void attach_sources(const loss_sim *s, LineArgs &a, int time_offset, const int *
     a.bcoef = s->med.back();
     a.d_step = s->d_step;
     a.src_time_offset = time_offset;
-    a.src_scale = (float)s->d.dt;
+    a.src_scale = forces ? 1.f : (float)s->d.dt;
     for (int j = 0; j < 3; ++j) a.out_field[j] = j < nout ? out_field[j] : -1;
 }
 
@@ -240,7 +243,7 @@ loss_status inject(loss_sim *s, float **fields_dev, int time_offset, float scale
     if (r) return r;
     const float *b = s->med.back();
     hipError_t e = launch_inject(s->d_src, s->nsrc, fields_dev, b, s->d_wpool, s->d_wavpool, s->shot_stride,
-                                 s->pitch, s->plane, s->d_step, time_offset, scale * (float)s->d.dt,
+                                 s->pitch, s->plane, s->d_step, time_offset, scale,
                                  want_force, s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("inject: ") + hipGetErrorString(e));
     return timed_end(s, KC_SOURCE);
@@ -259,11 +262,11 @@ loss_status record(loss_sim *s, const RecDev *rec0, int nrec0, float w0, int acc
     return timed_end(s, KC_RECEIVER);
 }
 
-// ---- velocity sub-flow (A) over alpha_dt with the stress frozen -------------
+// ---- velocity sub-flow (A) over frac * dt with the stress frozen -------------
 // acoustic: v1 -= a b dsigma/dx, v3 -= a b dsigma/dz ; elastic: v_i += a b d_j sigma_ij
 // `vel` are the velocity destinations (state or a temporary), `base` optional source
 // for EPI_BASE on the first pass of each component.
-loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const float *const *base,
+loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const float *const *base,
                            bool with_forces = false)
 {
     const float *b = s->med.back();
@@ -274,14 +277,14 @@ loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const flo
             const int axis = c == 0 ? 0 : 2;
             LineArgs a = base_args(s, axis);
             a.in = sig;
-            a.alpha = -a_dt;
+            a.alpha = -frac;
             a.out[0] = vel[c];
             a.coef[0] = b;
             int epi = EPI_AXPY;
             if (base) { a.aux = base[c]; epi = EPI_BASE; }
             if (with_forces) {
                 const int fid = c == 0 ? LOSS_F_V1 : LOSS_F_V3;
-                attach_sources(s, a, 0, &fid, 1);
+                attach_sources(s, a, 0, &fid, 1, true);
             }
             r = run_line(s, c == 0 ? KC_VEL_X : KC_VEL_Z, axis, SOLVE_D1, epi, a);
             if (r) return r;
@@ -296,14 +299,14 @@ loss_status velocity_stage(loss_sim *s, float a_dt, float *const *vel, const flo
         for (int j = 0; j < 3; ++j) {
             LineArgs a = base_args(s, j);
             a.in = s->f[sidx[i][j]];
-            a.alpha = a_dt;
+            a.alpha = frac;
             a.out[0] = vel[i];
             a.coef[0] = b;
             int epi = EPI_AXPY;
             if (base && j == 0) { a.aux = base[i]; epi = EPI_BASE; }
             if (with_forces && j == 2) {
                 const int fid = LOSS_F_EV1 + i;
-                attach_sources(s, a, 0, &fid, 1);
+                attach_sources(s, a, 0, &fid, 1, true);
             }
             r = run_line(s, KC_VEL_X + j, j, SOLVE_D1, epi, a);
             if (r) return r;
@@ -328,11 +331,11 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         c.out[0] = s->f[LOSS_F_SIGMA];
         c.coef[0] = s->med[0];
         c.aux = s->tmp[0];
-        c.alpha = -dt;
+        c.alpha = -1.f;
         c.div = div_store;
         c.div_shot_stride = div_shot_stride;
         const int fid = LOSS_F_SIGMA;
-        attach_sources(s, c, -1, &fid, 1);
+        attach_sources(s, c, -1, &fid, 1, false);
         return run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_AXPY_AUX, c);
     }
     float *const *F = s->f.data();
@@ -341,14 +344,14 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
     for (int i = 0; i < 3; ++i) {
         LineArgs a = base_args(s, i);
         a.in = F[LOSS_F_EV1 + i];
-        a.alpha = dt;
+        a.alpha = 1.f;
         a.nout = 3;
         a.out[0] = F[LOSS_F_S11]; a.out[1] = F[LOSS_F_S22]; a.out[2] = F[LOSS_F_S33];
         a.coef[0] = a.coef[1] = a.coef[2] = lam;
         a.coef[i] = l2m;
         if (i == 2) {
             const int fid[3] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33};
-            attach_sources(s, a, -1, fid, 3);
+            attach_sources(s, a, -1, fid, 3, false);
         }
         r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_AXPY, a);
         if (r) return r;
@@ -359,9 +362,9 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         const int sij = sh[k][0], i = sh[k][1], j = sh[k][2];
         float *out[1] = {F[sij]};
         const float *coef[1] = {mu};
-        r = deriv_axpy(s, KC_STRESS_X + i, i, F[LOSS_F_EV1 + j], dt, 1, out, coef);
+        r = deriv_axpy(s, KC_STRESS_X + i, i, F[LOSS_F_EV1 + j], 1.f, 1, out, coef);
         if (r) return r;
-        r = deriv_axpy(s, KC_STRESS_X + j, j, F[LOSS_F_EV1 + i], dt, 1, out, coef);
+        r = deriv_axpy(s, KC_STRESS_X + j, j, F[LOSS_F_EV1 + i], 1.f, 1, out, coef);
         if (r) return r;
     }
     return LOSS_OK;
@@ -509,7 +512,7 @@ void drop_graph(loss_sim *s)
 loss_status fuse(loss_sim *s)
 {
     if (s->fused) return LOSS_OK;
-    const float hdt = 0.5f * (float)s->d.dt;
+    const float hdt = 0.5f;
     std::vector<float *> vel;
     if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
     else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
@@ -532,7 +535,7 @@ loss_status unfused_velocity(loss_sim *s, std::vector<float *> &vout)
     const int nv = (int)vel.size();
     std::vector<float *> dst(s->tmp, s->tmp + nv);
     std::vector<const float *> base(vel.begin(), vel.end());
-    loss_status r = velocity_stage(s, -0.5f * (float)s->d.dt, dst.data(), base.data());
+    loss_status r = velocity_stage(s, -0.5f, dst.data(), base.data());
     if (r) return r;
     if (s->nsrc) {
         // forces: subtract the half-step force term, on a pointer table aimed at tmp
@@ -578,7 +581,7 @@ loss_status one_step(loss_sim *s, float *div_store, int64_t div_shot_stride)
     std::vector<float *> vel;
     if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
     else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
-    if ((r = velocity_stage(s, (float)s->d.dt, vel.data(), nullptr, true))) return r;
+    if ((r = velocity_stage(s, 1.0f, vel.data(), nullptr, true))) return r;
     if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 1))) return r;
     return LOSS_OK;
 }
@@ -711,6 +714,8 @@ loss_status upload_axis(loss_sim *s, int axis)
     AxisDev &d = s->axd[axis];
     d.N = h.N; d.M = h.M; d.p = h.p; d.ntap = 2 * h.halo + 1; d.h = (float)h.h;
     d.s3 = (float)(3.0 / h.h);
+    d.halo = h.halo;
+    d.periodic = h.end_mode == LOSS_END_PERIODIC;
     d.lum = dlum;
     d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
     d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc;
@@ -845,7 +850,7 @@ loss_status loss_set_media(loss_sim *s, const float *vp, const float *vs, const 
                               mem == LOSS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->st));
     }
     hipError_t e = launch_media(dv[0], dv[1], dv[2], s->med.data(), s->d.physics, s->nx, s->ny * s->nz,
-                                s->pitch, s->st);
+                                s->pitch, s->d.dt, s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
     // keep dense vp and rho for the gradient map
     if (s->d_vp) s->release(s->d_vp);
@@ -1104,17 +1109,17 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
             hipError_t e = launch_residual_inject(s->d_rec_str, s->nrec_str, lam, ss, s->res_dev, n, s->st);
             if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
             if ((r = timed_end(s, KC_RECEIVER))) return r;
-            // lambda^{n+1} += -dt (Dx^T(b mu1) + Dz^T(b mu3))
-            if ((r = adj_deriv(s, 0, mu1, b, lam, -dt, EPI_AXPY, Y, (int)S))) return r;
-            if ((r = adj_deriv(s, 2, mu3, b, lam, -dt, EPI_AXPY, Y, (int)S))) return r;
+            // lambda^{n+1} += -dt (Dx^T(b mu1) + Dz^T(b mu3))   (media hold dt b, dt K)
+            if ((r = adj_deriv(s, 0, mu1, b, lam, -1.f, EPI_AXPY, Y, (int)S))) return r;
+            if ((r = adj_deriv(s, 2, mu3, b, lam, -1.f, EPI_AXPY, Y, (int)S))) return r;
             // dJ/dK += -dt lambda^{n+1} div u^n
             if ((r = timed_begin(s))) return r;
             e = launch_grad_accum(s->grad_pad, lam, s->divstore + k * fe, -dt, (int)S, ss, ss, s->st);
             if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
             if ((r = timed_end(s, KC_GRAD))) return r;
             // mu^n = mu^{n+1} - dt D^T(K lambda^{n+1})
-            if ((r = adj_deriv(s, 0, lam, K, mu1, -dt, EPI_AXPY, Y, (int)S))) return r;
-            if ((r = adj_deriv(s, 2, lam, K, mu3, -dt, EPI_AXPY, Y, (int)S))) return r;
+            if ((r = adj_deriv(s, 0, lam, K, mu1, -1.f, EPI_AXPY, Y, (int)S))) return r;
+            if ((r = adj_deriv(s, 2, lam, K, mu3, -1.f, EPI_AXPY, Y, (int)S))) return r;
         }
     }
     hipError_t e = launch_grad_unpad(s->grad_pad, s->grad_dense, s->nx, s->ny * s->nz, s->pitch, s->d_vp,

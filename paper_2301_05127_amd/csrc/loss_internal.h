@@ -56,7 +56,7 @@ std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_m
 
 // Device copy of one axis (float32).
 struct AxisDev {
-    int N, M, p, ntap;
+    int N, M, p, ntap, halo, periodic;
     float h;
     float s3;              // 3/h, the stencil weight of interior rows of G
     const float2 *lum;     // {m, invd} of T (compact copy for interior rows)
@@ -150,7 +150,7 @@ hipError_t launch_set_step(int64_t *d_step, int64_t v, hipStream_t st);
 hipError_t launch_pad_copy(const float *src, float *dst, int nx, int rows, int64_t pitch, int to_padded,
                            hipStream_t st);
 hipError_t launch_media(const float *vp, const float *vs, const float *rho, float *const *media,
-                        int physics, int nx, int rows, int64_t pitch, hipStream_t st);
+                        int physics, int nx, int rows, int64_t pitch, double dt, hipStream_t st);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_axpby(float *y, const float *x, float a, float b, int64_t n, hipStream_t st);
 hipError_t launch_grad_accum(double *g, const float *lam, const float *div, float scale, int S,
