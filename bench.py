@@ -50,6 +50,7 @@ def parse():
     p.add_argument("--timing-steps", type=int, default=200)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-steps", type=int, default=40)
+    p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run one 1 GiB device copy (HBM counter calibration)")
     return p.parse_args()
@@ -102,6 +103,7 @@ def main():
     sim = loss.Simulation(g, w["physics"], w["dt"], nshots=S, trace_len=total)
     sim.setup_workload(w, shots=shots)
     nodes = sim.nodes
+    cw = sim.autotune(3) if not a.no_autotune else [0, 0, 0]
     # warmup (also builds the step graph)
     sim.step(a.warmup)
     sim.sync()
@@ -160,6 +162,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload_desc(w, S), "nodes": nodes, "shots": S,
+                   "columns_per_wave": cw,
                    "hbm_effective_GBs": round(eff, 1),
                    "hbm_effective_frac": round(eff / HBM_PEAK_GBS, 4),
                    "compulsory_bytes_per_cell_step": step_bytes, "finite": finite},

@@ -182,6 +182,16 @@ loss_status loss_forward_ckpt(loss_sim *sim, int64_t nsteps, int64_t ckpt_every)
 loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, double *grad,
                          int32_t mem);
 
+/* Autotune the launch shape of the line kernels: for every strided axis (y, z) the
+ * columns per wave (16, 32 or 64 x-columns; the rest of the wave's lanes take further
+ * chunks of the same lines) is timed over `trial_steps` steps each and the fastest
+ * kept.  The arithmetic does not depend on the shape (results are bitwise equal).
+ * Wavefields, traces and the step counter are restored afterwards. */
+loss_status loss_autotune(loss_sim *sim, int32_t trial_steps);
+
+/* The columns per wave in use along `axis` (0 = automatic choice). */
+loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
+
 /* Wait for all work queued on the sim stream. */
 loss_status loss_sync(loss_sim *sim);
 

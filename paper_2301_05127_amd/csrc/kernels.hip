@@ -369,11 +369,23 @@ constexpr int kMaxWaves = 16;
 // groups of a wave and the waves of the block holding consecutive chunks of C nodes
 // along the axis.  Chunk maps are composed through LDS.
 template <int C, int SOLVE, int EPI>
-__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW)
+__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, int gx_real)
 {
     __shared__ float sA[1024], sB[1024], sQ[1024], sW[1024];
     __shared__ float sWe[64];
     const AxisDev &ax = a.ax;
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD
+    // a contiguous range of column groups (neighbouring groups share cache lines and
+    // PMBC halo rows in that XCD's L2).  gridDim.x is padded to a multiple of 8.
+    int bx, by;
+    {
+        const int total = gridDim.x * gridDim.y;
+        const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+        const int logical = (lin & 7) * (total >> 3) + (lin >> 3);
+        bx = logical % gridDim.x;
+        by = logical / gridDim.x;
+    }
+    if (bx >= gx_real) return;   // padding block (uniform across the block)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int SUB = 64 / CW;
@@ -381,7 +393,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW)
     const int ci = lane % CW;
     const int chunk = wv * SUB + lane / CW;
     const int n_other = (axis == 1) ? a.nz : a.ny;
-    const int64_t fcol = (int64_t)blockIdx.x * CW + ci;
+    const int64_t fcol = (int64_t)bx * CW + ci;
     const int64_t per_shot = (int64_t)n_other * a.pitch;
     const int shot0 = (int)(fcol / per_shot);
     const int64_t rem = fcol - (int64_t)shot0 * per_shot;
@@ -389,7 +401,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW)
     const int col = (int)(rem - (int64_t)o * a.pitch);
     const bool cact = col < a.nx && shot0 < a.S;
     const int shot = min(shot0, a.S - 1);
-    const int l = blockIdx.y;
+    const int l = by;
     const int64_t stride = (axis == 1) ? a.pitch : a.plane;
     const int64_t obase = (axis == 1) ? (int64_t)o * a.plane : (int64_t)o * a.pitch;
     const int64_t mbase = obase + min(col, a.nx - 1);
@@ -400,6 +412,39 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW)
     const int e = min(s + M, N);
     const int q = s + chunk * C;
     const float *__restrict__ in = a.in;
+
+    // PMBC slopes of rows s and e for this column: the chunks of the unit share the
+    // taps (independent loads), partial sums meet in LDS
+    float phs = __builtin_nanf(""), phe = __builtin_nanf("");
+    if constexpr (SOLVE == SOLVE_D1 || SOLVE == SOLVE_D2) {
+        const int ss = (int)ax.rc[s].w, se = (int)ax.rc[e].w;
+        if (ss >= 0 || se >= 0) {
+            float ps = 0.f, pe = 0.f;
+            for (int t = chunk; t < ax.ntap; t += NCH) {
+                if (ss >= 0) {
+                    int ki = s - ax.halo + t;
+                    ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
+                    ps = fmaf(ax.tap_c[(int64_t)ss * ax.ntap + t], in[base + (int64_t)ki * stride], ps);
+                }
+                if (se >= 0) {
+                    int ki = e - ax.halo + t;
+                    ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
+                    pe = fmaf(ax.tap_c[(int64_t)se * ax.ntap + t], in[base + (int64_t)ki * stride], pe);
+                }
+            }
+            sA[chunk * CW + ci] = ps;
+            sB[chunk * CW + ci] = pe;
+            __syncthreads();
+            float sumS = 0.f, sumE = 0.f;
+            for (int j = 0; j < NCH; ++j) {
+                sumS += sA[j * CW + ci];
+                sumE += sB[j * CW + ci];
+            }
+            phs = sumS;
+            phe = sumE;
+            __syncthreads();
+        }
+    }
 
     float u[C + 2];
 #pragma unroll
@@ -414,7 +459,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW)
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int i = min(q + c, N);
-        const float r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, stride, fac[c]);
+        const float r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, stride, fac[c], phs);
         yv = fmaf(-fac[c].x, yv, r);
         pv = -fac[c].x * pv;
         y[c] = yv;
@@ -434,7 +479,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW)
 #pragma unroll
         for (int c = 0; c < C; ++c)
             if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
-        sWe[ci] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, stride);
+        sWe[ci] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, stride, phe);
     }
 
     float w[C], Q[C];
@@ -705,19 +750,25 @@ hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
     const int nch = (M + C - 1) / C;
     const int n_other = axis == 1 ? a.nz : a.ny;
     const int64_t F = (int64_t)a.S * n_other * a.pitch;
-    // columns per wave: the widest that still gives >= 2048 blocks (or 16)
-    int CW = 64;
-    while (CW > 16 && ((F + CW - 1) / CW) * a.ax.p < 2048) CW >>= 1;
+    // columns per wave: the caller's choice, else the widest that still gives
+    // >= 2048 workgroups (or 16)
+    int CW = a.cw;
+    if (CW != 16 && CW != 32 && CW != 64) {
+        CW = 64;
+        while (CW > 16 && ((F + CW - 1) / CW) * a.ax.p < 2048) CW >>= 1;
+    }
     const int sub = 64 / CW;
     const int W = (nch + sub - 1) / sub;
     if (W > kMaxWaves) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((F + CW - 1) / CW), a.ax.p, 1);
+    const int gx = (int)((F + CW - 1) / CW);
+    const int gxp = (gx + 7) / 8 * 8;
+    dim3 grid((unsigned)gxp, a.ax.p, 1);
     const int threads = 64 * W;
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, 0, st, a, axis, CW); break;
-    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, 0, st, a, axis, CW); break;
-    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, 0, st, a, axis, CW); break;
-    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, 0, st, a, axis, CW); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, 0, st, a, axis, CW, gx); break;
+    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, 0, st, a, axis, CW, gx); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, 0, st, a, axis, CW, gx); break;
+    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, 0, st, a, axis, CW, gx); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -78,6 +78,7 @@ struct loss_sim {
     bool src_dirty = true;
     SrcDev *d_src = nullptr;
     int *d_src_begin = nullptr;    // [S+1]
+    int cw[3] = {0, 0, 0};         // strided-kernel columns per wave per axis (0 = automatic)
     int nsrc = 0;
     bool pending_inc = false;      // next line kernel advances the step counter
     float *d_wpool = nullptr, *d_wavpool = nullptr;
@@ -144,6 +145,7 @@ LineArgs base_args(const loss_sim *s, int axis)
     a.pitch = s->pitch; a.plane = s->plane; a.shot_stride = s->shot_stride;
     a.ax = s->axd[axis];
     a.nout = 1;
+    a.cw = s->cw[axis];
     return a;
 }
 
@@ -1038,6 +1040,69 @@ loss_status loss_kernel_timing(loss_sim *s, int32_t id, double *ms, int64_t *lau
 }
 
 int64_t loss_current_step(const loss_sim *s) { return s ? s->step : -1; }
+
+loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
+{
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    if (trial_steps < 1) return fail(LOSS_EINVAL, "trial_steps must be >= 1");
+    loss_status r;
+    if ((r = ensure_ready(s))) return r;
+    // save the state
+    const int64_t fe = field_elems(s);
+    float *bk = nullptr;
+    double *tbk = nullptr;
+    if ((r = s->alloc(&bk, (size_t)(s->nf * fe)))) return r;
+    if ((r = s->alloc(&tbk, (size_t)std::max<int64_t>(1, s->trace_total)))) return r;
+    for (int f = 0; f < s->nf; ++f)
+        HIPCHK(hipMemcpyAsync(bk + f * fe, s->f[f], sizeof(float) * fe, hipMemcpyDeviceToDevice, s->st));
+    if (s->trace_total)
+        HIPCHK(hipMemcpyAsync(tbk, s->traces, sizeof(double) * s->trace_total, hipMemcpyDeviceToDevice, s->st));
+    const int64_t step0 = s->step;
+    const bool fused0 = s->fused;
+    const bool timing0 = s->timing;
+    s->timing = false;
+    if ((r = fuse(s))) return r;
+    const int cands[3] = {64, 32, 16};
+    for (int axis = 1; axis < 3; ++axis) {
+        if (axis == 1 && s->d.ndim == 2) continue;
+        float best = 1e30f;
+        int bestcw = 0;
+        for (int cw : cands) {
+            s->cw[axis] = cw;
+            if ((r = one_step(s, nullptr, 0))) return r;   // warm this shape up
+            HIPCHK(hipEventRecord(s->ev0, s->st));
+            for (int k = 0; k < trial_steps; ++k)
+                if ((r = one_step(s, nullptr, 0))) return r;
+            HIPCHK(hipEventRecord(s->ev1, s->st));
+            HIPCHK(hipEventSynchronize(s->ev1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+            if (ms < best) { best = ms; bestcw = cw; }
+        }
+        s->cw[axis] = bestcw;
+    }
+    // restore
+    for (int f = 0; f < s->nf; ++f)
+        HIPCHK(hipMemcpyAsync(s->f[f], bk + f * fe, sizeof(float) * fe, hipMemcpyDeviceToDevice, s->st));
+    if (s->trace_total)
+        HIPCHK(hipMemcpyAsync(s->traces, tbk, sizeof(double) * s->trace_total, hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(launch_set_step(s->d_step, step0, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->release(bk);
+    s->release(tbk);
+    s->step = step0;
+    s->fused = fused0;
+    s->timing = timing0;
+    drop_graph(s);
+    return LOSS_OK;
+}
+
+loss_status loss_autotune_choice(loss_sim *s, int32_t axis, int32_t *cw)
+{
+    if (!s || !cw || axis < 0 || axis > 2) return fail(LOSS_EINVAL, "bad argument");
+    *cw = s->cw[axis];
+    return LOSS_OK;
+}
 
 loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
 {

@@ -113,6 +113,7 @@ struct LineArgs {
     int src_time_offset;
     float src_scale;
     int out_field[3];
+    int cw;                // strided kernels: columns per wave (16, 32, 64; 0 = automatic)
 };
 
 // Launch helpers (kernels.hip).  axis: 0 = x (contiguous), 1 = y, 2 = z.

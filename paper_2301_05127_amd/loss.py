@@ -27,7 +27,8 @@ EXPORTS = [
     "loss_create", "loss_destroy", "loss_set_media", "loss_add_source", "loss_add_receivers",
     "loss_reset", "loss_step", "loss_get_field", "loss_set_field", "loss_get_traces", "loss_deriv",
     "loss_forward_ckpt", "loss_adjoint", "loss_sync", "loss_set_timing", "loss_kernel_timing",
-    "loss_current_step", "loss_status_str", "loss_last_error",
+    "loss_current_step", "loss_status_str", "loss_last_error", "loss_autotune",
+    "loss_autotune_choice",
 ]
 
 
@@ -78,6 +79,8 @@ def lib():
         "loss_kernel_timing": (I32, [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64),
                                      ctypes.POINTER(ctypes.c_char_p)]),
         "loss_current_step": (I64, [P]),
+        "loss_autotune": (I32, [P, I32]),
+        "loss_autotune_choice": (I32, [P, I32, ctypes.POINTER(I32)]),
         "loss_status_str": (ctypes.c_char_p, [I32]),
         "loss_last_error": (ctypes.c_char_p, []),
     }
@@ -256,6 +259,18 @@ class Simulation:
         _check(lib().loss_adjoint(self._h, r.ctypes.data_as(ctypes.c_void_p), param,
                                   g.ctypes.data_as(ctypes.c_void_p), MEM_HOST))
         return g
+
+    # ---- launch-shape autotuning ----------------------------------------------------
+    def autotune(self, trial_steps=5):
+        """Pick the fastest launch shape of the strided line kernels; returns the
+        columns-per-wave choice per axis."""
+        _check(lib().loss_autotune(self._h, int(trial_steps)))
+        out = []
+        for axis in range(3):
+            v = ctypes.c_int32()
+            _check(lib().loss_autotune_choice(self._h, axis, ctypes.byref(v)))
+            out.append(v.value)
+        return out
 
     # ---- timing ----------------------------------------------------------------
     def set_timing(self, on):

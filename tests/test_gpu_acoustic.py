@@ -180,3 +180,26 @@ def test_cfg2_full_size_few_steps(orc):
         assert rel_l2(sim.get_field(f), rf[f]) < 1e-5, f
     assert rel_l2(sim.get_traces(0), rt) < 1e-5
     sim.close()
+
+
+def test_autotune_restores_state_and_keeps_bits():
+    """The launch-shape autotuner restores the state and changes no result bit."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs
+    w = _f32(inputs.config("cfg1", nsteps=60))
+    announce("autotune")
+    from paper_2301_05127_amd import loss
+    a = loss.Simulation(w["grid"], 0, w["dt"], nshots=1, trace_len=60)
+    a.setup_workload(w)
+    a.step(20)
+    before = [a.get_field(f) for f in range(3)]
+    cw = a.autotune(2)
+    assert cw[2] in (16, 32, 64) and a.current_step == 20
+    for f in range(3):
+        assert np.array_equal(a.get_field(f), before[f])
+    a.step(40)
+    b = _gpu(w)
+    for f in range(3):
+        assert np.array_equal(a.get_field(f), b.get_field(f))
+    assert np.array_equal(a.get_traces(0), b.get_traces(0))
+    a.close(); b.close()
