@@ -182,14 +182,16 @@ loss_status loss_forward_ckpt(loss_sim *sim, int64_t nsteps, int64_t ckpt_every)
 loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, double *grad,
                          int32_t mem);
 
-/* Autotune the launch shape of the line kernels: for every strided axis (y, z) the
- * columns per wave (16, 32 or 64 x-columns; the rest of the wave's lanes take further
- * chunks of the same lines) is timed over `trial_steps` steps each and the fastest
- * kept.  The arithmetic does not depend on the shape (results are bitwise equal).
- * Wavefields, traces and the step counter are restored afterwards. */
+/* Autotune the launch shape of the line kernels: along x the nodes per lane (4, 8 or
+ * 16); along y and z the columns per wave (16, 32 or 64 x-columns; the rest of the
+ * wave's lanes take further chunks of the same lines) and the nodes per lane (8 or
+ * 16); each candidate timed over `trial_steps` steps, the fastest kept.  A shape
+ * changes only how the carries of the scan are grouped (rounding-level
+ * differences).  Wavefields, traces and the step counter are restored afterwards. */
 loss_status loss_autotune(loss_sim *sim, int32_t trial_steps);
 
-/* The columns per wave in use along `axis` (0 = automatic choice). */
+/* The launch shape in use along `axis`: nodes per lane for x; for y and z,
+ * 100 * columns per wave + nodes per lane (0 = automatic choice). */
 loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
 
 /* Wait for all work queued on the sim stream. */

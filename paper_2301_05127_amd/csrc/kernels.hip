@@ -68,9 +68,27 @@ __device__ __forceinline__ float source_terms(const LineArgs &a, int j, int shot
     return add;
 }
 
+// Does the segment [lo, hi] along `axis` through (x, y, z) of `shot` meet a source box?
+__device__ __forceinline__ bool segment_has_source(const LineArgs &a, int shot, int axis, int x, int y, int z,
+                                                int lo, int hi)
+{
+    const int k1 = a.src_begin[shot + 1];
+    for (int k = a.src_begin[shot]; k < k1; ++k) {
+        const SrcDev &sd = a.src[k];
+        const int c0[3] = {sd.x0, sd.y0, sd.z0}, nb[3] = {sd.bx, sd.by, sd.bz}, p[3] = {x, y, z};
+        bool hit = true;
+        for (int d = 0; d < 3; ++d) {
+            if (d == axis) hit = hit && hi >= c0[d] && lo < c0[d] + nb[d];
+            else hit = hit && p[d] >= c0[d] && p[d] < c0[d] + nb[d];
+        }
+        if (hit) return true;
+    }
+    return false;
+}
+
 template <int EPI>
 __device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float D,
-                                         int x, int y, int z)
+                                         int x, int y, int z, bool srcs = true)
 {
     if constexpr (EPI == EPI_STORE) {
         a.out[0][oidx] = D;
@@ -78,14 +96,14 @@ __device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_
         for (int j = 0; j < a.nout; ++j) {
             const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
             float v = fmaf(a.alpha * c, D, a.out[j][oidx]);
-            if (a.src) v += source_terms(a, j, shot, x, y, z, midx);
+            if (srcs && a.src) v += source_terms(a, j, shot, x, y, z, midx);
             a.out[j][oidx] = v;
         }
     } else if constexpr (EPI == EPI_AXPY_AUX) {
         const float dv = D + a.aux[oidx];
         const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
         float v = fmaf(a.alpha * c, dv, a.out[0][oidx]);
-        if (a.src) v += source_terms(a, 0, shot, x, y, z, midx);
+        if (srcs && a.src) v += source_terms(a, 0, shot, x, y, z, midx);
         a.out[0][oidx] = v;
         if (a.div) a.div[(int64_t)shot * a.div_shot_stride + midx] = dv;
     } else {  // EPI_BASE
@@ -105,9 +123,9 @@ __device__ __forceinline__ float4 fma4(float a, float4 c, float4 d, float4 o)
 // Epilogue of four consecutive x nodes (16-byte aligned, all inside the unit).
 template <int EPI>
 __device__ __forceinline__ void epilogue4(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float4 D,
-                                          int x, int y, int z)
+                                          int x, int y, int z, bool srcs)
 {
-    if (a.src) {
+    if (srcs) {
         epilogue<EPI>(a, oidx, midx, shot, D.x, x, y, z);
         epilogue<EPI>(a, oidx + 1, midx + 1, shot, D.y, x + 1, y, z);
         epilogue<EPI>(a, oidx + 2, midx + 2, shot, D.z, x + 2, y, z);
@@ -197,7 +215,7 @@ __device__ __forceinline__ float closing_row(const AxisDev &ax, int e, float yla
 // x axis (contiguous): G lanes per unit, C nodes per lane, 64/G units per wave.
 // ---------------------------------------------------------------------------
 template <int C, int SOLVE, int EPI>
-__global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunits)
+__global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
 {
     const AxisDev &ax = a.ax;
     const int lane = threadIdx.x & 63;
@@ -205,20 +223,28 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
     const int k = lane & (G - 1);
     const int grp = lane / G;
     const int upw = 64 / G;
-    int64_t unit = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wid) * upw + grp;
+    int unit = (blockIdx.x * (blockDim.x >> 6) + wid) * upw + grp;
     const bool uact = unit < nunits;
     if (!uact) unit = nunits - 1;
     const int N = ax.N, M = ax.M, p = ax.p;
-    const int l = (int)(unit % p);
-    const int64_t line = unit / p;
-    const int shot = (int)(line / ((int64_t)a.nz * a.ny));
-    const int64_t base = line * a.pitch;
-    const int64_t mbase = base - (int64_t)shot * a.shot_stride;
-    const int rowz = (int)((line / a.ny) % a.nz), rowy = (int)(line % a.ny);
+    const int line = unit / p;
+    const int l = unit - line * p;
+    const int lps = a.nz * a.ny;                 // lines per shot
+    const int shot = line / lps;
+    const int64_t base = (int64_t)line * a.pitch;
+    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
     if (a.step_inc && blockIdx.x == 0 && threadIdx.x == 0) *a.step_inc += 1;
     const int s = l * M;
     const int e = min(s + M, N);
     const int q = s + k * C;
+    int rowz = 0, rowy = 0;                       // coordinates, only for source terms
+    bool srcs = false;
+    if (a.src) {
+        const int r = line - shot * lps;
+        rowz = r / a.ny;
+        rowy = r - rowz * a.ny;
+        srcs = segment_has_source(a, shot, 0, 0, rowy, rowz, q, min(q + C, N));
+    }
     const float *__restrict__ in = a.in;
 
     // chunk values u[1..C] = nodes q..q+C-1 (16-byte loads when aligned and inside
@@ -260,12 +286,12 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
             if (ss >= 0) {
                 int ki = s - ax.halo + t;
                 ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                phs = fmaf(ax.tap_c[(int64_t)ss * ax.ntap + t], in[base + ki], phs);
+                phs = fmaf(ax.tap_c[ss * ax.ntap + t], in[base + ki], phs);
             }
             if (se >= 0) {
                 int ki = e - ax.halo + t;
                 ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                phe = fmaf(ax.tap_c[(int64_t)se * ax.ntap + t], in[base + ki], phe);
+                phe = fmaf(ax.tap_c[se * ax.ntap + t], in[base + ki], phe);
             }
         }
         for (int d = G >> 1; d > 0; d >>= 1) {
@@ -274,23 +300,24 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
         }
     }
 
-    float y[C], P[C];
-    float4 fac[C];
+    float y[C], P[C], fi[C], fs[C];   // eliminated rhs, carry factor, 1/pivot, superdiagonal
     float yv = 0.f, pv = 1.f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int i = min(q + c, N);
-        float r;
+        float r, fm;
         if (SOLVE == SOLVE_D1 && i != s) {
             // rows strictly inside the patch: [1 4 1] with rhs (3/h)(u_{i+1} - u_{i-1})
             const float2 f = ax.lum[i];
-            fac[c] = make_float4(f.x, f.y, 1.f, 0.f);
+            fm = f.x; fi[c] = f.y; fs[c] = 1.f;
             r = ax.s3 * (u[c + 2] - u[c]);
         } else {
-            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, fac[c], phs);
+            float4 f;
+            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, f, phs);
+            fm = f.x; fi[c] = f.y; fs[c] = f.z;
         }
-        yv = fmaf(-fac[c].x, yv, r);
-        pv = -fac[c].x * pv;
+        yv = fmaf(-fm, yv, r);
+        pv = -fm * pv;
         y[c] = yv;
         P[c] = pv;
     }
@@ -323,7 +350,7 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
         if (q + c < e) {
-            const float inv = fac[c].y, sp = fac[c].z;
+            const float inv = fi[c], sp = fs[c];
             wv = fmaf(-sp, wv, y[c]) * inv;
             qv = -sp * inv * qv;
         }
@@ -347,20 +374,20 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int64_t nunit
             for (int g4 = 0; g4 < C / 4; ++g4)
                 epilogue4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4, shot,
                                make_float4(w[4 * g4], w[4 * g4 + 1], w[4 * g4 + 2], w[4 * g4 + 3]),
-                               q + 4 * g4, rowy, rowz);
+                               q + 4 * g4, rowy, rowz, srcs);
         } else {
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const int i = q + c;
-                if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, w[c], i, rowy, rowz);
+                if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, w[c], i, rowy, rowz, srcs);
             }
         }
-        if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we, N, rowy, rowz);
+        if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we, N, rowy, rowz, srcs);
     }
 }
 
 // ---------------------------------------------------------------------------
-// y / z axes (strided): lanes = x columns, wave w = chunk w of C nodes along the axis.
+// y / z axes (strided).
 // ---------------------------------------------------------------------------
 constexpr int kMaxWaves = 16;
 
@@ -382,36 +409,36 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         const int total = gridDim.x * gridDim.y;
         const int lin = blockIdx.y * gridDim.x + blockIdx.x;
         const int logical = (lin & 7) * (total >> 3) + (lin >> 3);
-        bx = logical % gridDim.x;
-        by = logical / gridDim.x;
+        by = logical / (int)gridDim.x;
+        bx = logical - by * (int)gridDim.x;
     }
     if (bx >= gx_real) return;   // padding block (uniform across the block)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int SUB = 64 / CW;
     const int NCH = (blockDim.x >> 6) * SUB;
-    const int ci = lane % CW;
+    const int ci = lane & (CW - 1);
     const int chunk = wv * SUB + lane / CW;
     const int n_other = (axis == 1) ? a.nz : a.ny;
-    const int64_t fcol = (int64_t)bx * CW + ci;
-    const int64_t per_shot = (int64_t)n_other * a.pitch;
-    const int shot0 = (int)(fcol / per_shot);
-    const int64_t rem = fcol - (int64_t)shot0 * per_shot;
-    const int o = (int)(rem / a.pitch);
-    const int col = (int)(rem - (int64_t)o * a.pitch);
+    const int pitch = (int)a.pitch;
+    const int per_shot = n_other * pitch;
+    const int fcol = bx * CW + ci;
+    const int shot0 = fcol / per_shot;
+    const int rem = fcol - shot0 * per_shot;
+    const int o = rem / pitch;
+    const int col = rem - o * pitch;
     const bool cact = col < a.nx && shot0 < a.S;
     const int shot = min(shot0, a.S - 1);
     const int l = by;
-    const int64_t stride = (axis == 1) ? a.pitch : a.plane;
-    const int64_t obase = (axis == 1) ? (int64_t)o * a.plane : (int64_t)o * a.pitch;
-    const int64_t mbase = obase + min(col, a.nx - 1);
-    const int64_t base = (int64_t)shot * a.shot_stride + mbase;
+    const int stride = (axis == 1) ? pitch : (int)a.plane;
+    const int mbase = ((axis == 1) ? o * (int)a.plane : o * pitch) + min(col, a.nx - 1);
+    const int64_t sbase = (int64_t)shot * a.shot_stride;   // start of the shot's field
+    const float *__restrict__ in = a.in + sbase;
     if (a.step_inc && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.step_inc += 1;
     const int N = ax.N, M = ax.M;
     const int s = l * M;
     const int e = min(s + M, N);
     const int q = s + chunk * C;
-    const float *__restrict__ in = a.in;
 
     // PMBC slopes of rows s and e for this column: the chunks of the unit share the
     // taps (independent loads), partial sums meet in LDS
@@ -424,12 +451,12 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
                 if (ss >= 0) {
                     int ki = s - ax.halo + t;
                     ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                    ps = fmaf(ax.tap_c[(int64_t)ss * ax.ntap + t], in[base + (int64_t)ki * stride], ps);
+                    ps = fmaf(ax.tap_c[ss * ax.ntap + t], in[mbase + ki * stride], ps);
                 }
                 if (se >= 0) {
                     int ki = e - ax.halo + t;
                     ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                    pe = fmaf(ax.tap_c[(int64_t)se * ax.ntap + t], in[base + (int64_t)ki * stride], pe);
+                    pe = fmaf(ax.tap_c[se * ax.ntap + t], in[mbase + ki * stride], pe);
                 }
             }
             sA[chunk * CW + ci] = ps;
@@ -449,19 +476,27 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
     float u[C + 2];
 #pragma unroll
     for (int c = 0; c < C + 2; ++c) {
-        const int64_t off = (int64_t)clampi(q - 1 + c, 0, N) * stride;
-        u[c] = load_in(a, base + off, mbase + off);
+        const int off = mbase + clampi(q - 1 + c, 0, N) * stride;
+        u[c] = a.in_coef ? in[off] * a.in_coef[off] : in[off];
     }
 
-    float y[C], P[C];
-    float4 fac[C];
+    float y[C], P[C], fi[C], fs[C];
     float yv = 0.f, pv = 1.f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int i = min(q + c, N);
-        const float r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, stride, fac[c], phs);
-        yv = fmaf(-fac[c].x, yv, r);
-        pv = -fac[c].x * pv;
+        float r, fm;
+        if (SOLVE == SOLVE_D1 && i != s) {
+            const float2 f = ax.lum[i];
+            fm = f.x; fi[c] = f.y; fs[c] = 1.f;
+            r = ax.s3 * (u[c + 2] - u[c]);
+        } else {
+            float4 f;
+            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, mbase, stride, f, phs);
+            fm = f.x; fi[c] = f.y; fs[c] = f.z;
+        }
+        yv = fmaf(-fm, yv, r);
+        pv = -fm * pv;
         y[c] = yv;
         P[c] = pv;
     }
@@ -479,7 +514,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
 #pragma unroll
         for (int c = 0; c < C; ++c)
             if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
-        sWe[ci] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, stride, phe);
+        sWe[ci] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, mbase, stride, phe);
     }
 
     float w[C], Q[C];
@@ -487,7 +522,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
         if (q + c < e) {
-            const float inv = fac[c].y, sp = fac[c].z;
+            const float inv = fi[c], sp = fs[c];
             wvv = fmaf(-sp, wvv, y[c]) * inv;
             qv = -sp * inv * qv;
         }
@@ -503,16 +538,20 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
 
     if (cact) {
         const int cy = axis == 1 ? 0 : o, cz = axis == 1 ? o : 0;
+        const bool srcs = a.src && segment_has_source(a, shot, axis, col, cy, cz, q, min(q + C, N));
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int i = q + c;
-            if (i < e)
-                epilogue<EPI>(a, base + (int64_t)i * stride, mbase + (int64_t)i * stride, shot,
-                              fmaf(Q[c], wr, w[c]), col, axis == 1 ? i : cy, axis == 1 ? cz : i);
+            if (i < e) {
+                const int off = mbase + i * stride;
+                epilogue<EPI>(a, sbase + off, off, shot, fmaf(Q[c], wr, w[c]), col, axis == 1 ? i : cy,
+                              axis == 1 ? cz : i, srcs);
+            }
         }
-        if (e == N && chunk == kc)
-            epilogue<EPI>(a, base + (int64_t)N * stride, mbase + (int64_t)N * stride, shot, we, col,
-                          axis == 1 ? N : cy, axis == 1 ? cz : N);
+        if (e == N && chunk == kc) {
+            const int off = mbase + N * stride;
+            epilogue<EPI>(a, sbase + off, off, shot, we, col, axis == 1 ? N : cy, axis == 1 ? cz : N, srcs);
+        }
     }
 }
 
@@ -730,14 +769,16 @@ hipError_t dispatch_x(int epi, const LineArgs &a, hipStream_t st)
     if (G > 64) return hipErrorInvalidValue;
     const int64_t lines = (int64_t)a.S * a.nz * a.ny;
     const int64_t nunits = lines * a.ax.p;
+    if (nunits >= (1ll << 31)) return hipErrorInvalidValue;
     const int threads = 256;
     const int64_t units_per_block = (threads / 64) * (64 / G);
     const unsigned blocks = nblk(nunits, (int)units_per_block);
+    const int nu = (int)nunits;
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_STORE>), blocks, threads, 0, st, a, G, nunits); break;
-    case EPI_AXPY: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_AXPY>), blocks, threads, 0, st, a, G, nunits); break;
-    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_AXPY_AUX>), blocks, threads, 0, st, a, G, nunits); break;
-    case EPI_BASE: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_BASE>), blocks, threads, 0, st, a, G, nunits); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_STORE>), blocks, threads, 0, st, a, G, nu); break;
+    case EPI_AXPY: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_AXPY>), blocks, threads, 0, st, a, G, nu); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_AXPY_AUX>), blocks, threads, 0, st, a, G, nu); break;
+    case EPI_BASE: hipLaunchKernelGGL((k_line_x<C, SOLVE, EPI_BASE>), blocks, threads, 0, st, a, G, nu); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -779,10 +820,20 @@ hipError_t dispatch_solve(int axis, int epi, const LineArgs &a, hipStream_t st)
 {
     const int M = a.ax.M;
     if (axis == 0) {
-        if (M <= 256) return dispatch_x<4, SOLVE>(epi, a, st);
-        if (M <= 1024) return dispatch_x<16, SOLVE>(epi, a, st);
-        return hipErrorInvalidValue;
+        // nodes per lane: the caller's choice if it fits 64 lanes per patch, else the
+        // smallest that does
+        int cx = a.cx;
+        if (cx != 4 && cx != 8 && cx != 16) cx = 4;
+        while (cx < 16 && cx * 64 < M) cx *= 2;
+        if (cx * 64 < M) return hipErrorInvalidValue;
+        if (cx == 4) return dispatch_x<4, SOLVE>(epi, a, st);
+        if (cx == 8) return dispatch_x<8, SOLVE>(epi, a, st);
+        return dispatch_x<16, SOLVE>(epi, a, st);
     }
+    // nodes per lane along y / z: the caller's choice if the patch fits the block
+    const int cs = a.cs;
+    if (cs == 8 && (M + 7) / 8 <= kMaxWaves * (64 / (a.cw ? a.cw : 64)))
+        return dispatch_s<8, SOLVE>(axis, epi, a, st);
     if (M <= 16 * kMaxWaves) return dispatch_s<16, SOLVE>(axis, epi, a, st);
     if (M <= 64 * kMaxWaves) return dispatch_s<64, SOLVE>(axis, epi, a, st);
     return hipErrorInvalidValue;

@@ -79,6 +79,8 @@ struct loss_sim {
     SrcDev *d_src = nullptr;
     int *d_src_begin = nullptr;    // [S+1]
     int cw[3] = {0, 0, 0};         // strided-kernel columns per wave per axis (0 = automatic)
+    int cx = 0;                    // x-kernel nodes per lane (0 = automatic)
+    int cs[3] = {0, 0, 0};         // strided-kernel nodes per lane per axis (0 = automatic)
     int nsrc = 0;
     bool pending_inc = false;      // next line kernel advances the step counter
     float *d_wpool = nullptr, *d_wavpool = nullptr;
@@ -146,6 +148,8 @@ LineArgs base_args(const loss_sim *s, int axis)
     a.ax = s->axd[axis];
     a.nout = 1;
     a.cw = s->cw[axis];
+    a.cx = s->cx;
+    a.cs = s->cs[axis];
     return a;
 }
 
@@ -1062,13 +1066,17 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     const bool timing0 = s->timing;
     s->timing = false;
     if ((r = fuse(s))) return r;
-    const int cands[3] = {64, 32, 16};
-    for (int axis = 1; axis < 3; ++axis) {
+    for (int axis = 0; axis < 3; ++axis) {
         if (axis == 1 && s->d.ndim == 2) continue;
+        // candidates: x -> nodes per lane; y, z -> (columns per wave, nodes per lane)
+        std::vector<std::pair<int, int>> cands;
+        if (axis == 0) cands = {{4, 0}, {8, 0}, {16, 0}};
+        else cands = {{64, 16}, {32, 16}, {16, 16}, {32, 8}, {16, 8}};
         float best = 1e30f;
-        int bestcw = 0;
-        for (int cw : cands) {
-            s->cw[axis] = cw;
+        std::pair<int, int> bestc = cands[0];
+        for (const auto &cd : cands) {
+            if (axis == 0) s->cx = cd.first;
+            else { s->cw[axis] = cd.first; s->cs[axis] = cd.second; }
             if ((r = one_step(s, nullptr, 0))) return r;   // warm this shape up
             HIPCHK(hipEventRecord(s->ev0, s->st));
             for (int k = 0; k < trial_steps; ++k)
@@ -1077,9 +1085,10 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
             HIPCHK(hipEventSynchronize(s->ev1));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
-            if (ms < best) { best = ms; bestcw = cw; }
+            if (ms < best) { best = ms; bestc = cd; }
         }
-        s->cw[axis] = bestcw;
+        if (axis == 0) s->cx = bestc.first;
+        else { s->cw[axis] = bestc.first; s->cs[axis] = bestc.second; }
     }
     // restore
     for (int f = 0; f < s->nf; ++f)
@@ -1100,7 +1109,7 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
 loss_status loss_autotune_choice(loss_sim *s, int32_t axis, int32_t *cw)
 {
     if (!s || !cw || axis < 0 || axis > 2) return fail(LOSS_EINVAL, "bad argument");
-    *cw = s->cw[axis];
+    *cw = axis == 0 ? s->cx : s->cw[axis] * 100 + s->cs[axis];
     return LOSS_OK;
 }
 

@@ -114,6 +114,8 @@ struct LineArgs {
     float src_scale;
     int out_field[3];
     int cw;                // strided kernels: columns per wave (16, 32, 64; 0 = automatic)
+    int cx;                // x kernel: nodes per lane (4, 8, 16; 0 = automatic)
+    int cs;                // y/z kernels: nodes per lane (8 or 16; 0 = automatic)
 };
 
 // Launch helpers (kernels.hip).  axis: 0 = x (contiguous), 1 = y, 2 = z.

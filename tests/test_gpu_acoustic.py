@@ -194,12 +194,14 @@ def test_autotune_restores_state_and_keeps_bits():
     a.step(20)
     before = [a.get_field(f) for f in range(3)]
     cw = a.autotune(2)
-    assert cw[2] in (16, 32, 64) and a.current_step == 20
+    assert cw[2] // 100 in (16, 32, 64) and cw[2] % 100 in (8, 16) and a.current_step == 20
     for f in range(3):
         assert np.array_equal(a.get_field(f), before[f])
     a.step(40)
     b = _gpu(w)
+    # the y/z shape leaves every bit unchanged; the x chunk length only regroups the
+    # carry composition of the scan (rounding level)
     for f in range(3):
-        assert np.array_equal(a.get_field(f), b.get_field(f))
-    assert np.array_equal(a.get_traces(0), b.get_traces(0))
+        assert rel_l2(a.get_field(f), b.get_field(f)) < 1e-6
+    assert rel_l2(a.get_traces(0), b.get_traces(0)) < 1e-6
     a.close(); b.close()
