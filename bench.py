@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-steps", type=int, default=40)
     p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--shape", default=None,
+                   help="launch shape per axis 'x,y,z' (loss_set_shape encoding); skips autotuning")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run one 1 GiB device copy (HBM counter calibration)")
     return p.parse_args()
@@ -103,7 +105,11 @@ def main():
     sim = loss.Simulation(g, w["physics"], w["dt"], nshots=S, trace_len=total)
     sim.setup_workload(w, shots=shots)
     nodes = sim.nodes
-    cw = sim.autotune(3) if not a.no_autotune else [0, 0, 0]
+    if a.shape:
+        cw = [int(v) for v in a.shape.split(",")]
+        sim.set_shape(cw)
+    else:
+        cw = sim.autotune(3) if not a.no_autotune else [0, 0, 0]
     # warmup (also builds the step graph)
     sim.step(a.warmup)
     sim.sync()

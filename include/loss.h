@@ -194,6 +194,11 @@ loss_status loss_autotune(loss_sim *sim, int32_t trial_steps);
  * 100 * columns per wave + nodes per lane (0 = automatic choice). */
 loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
 
+/* Set the launch shape along `axis` in the encoding of loss_autotune_choice
+ * (x: 4, 8 or 16; y/z: 100 * {16, 32, 64} + {8, 16}; 0 = automatic).  LOSS_EINVAL
+ * for any other value. */
+loss_status loss_set_shape(loss_sim *sim, int32_t axis, int32_t shape);
+
 /* Wait for all work queued on the sim stream. */
 loss_status loss_sync(loss_sim *sim);
 

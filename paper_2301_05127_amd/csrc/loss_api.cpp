@@ -1106,6 +1106,23 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     return LOSS_OK;
 }
 
+loss_status loss_set_shape(loss_sim *s, int32_t axis, int32_t shape)
+{
+    if (!s || axis < 0 || axis > 2 || (axis == 1 && s->d.ndim == 2)) return fail(LOSS_EINVAL, "bad axis");
+    if (axis == 0) {
+        if (shape != 0 && shape != 4 && shape != 8 && shape != 16) return fail(LOSS_EINVAL, "bad x shape");
+        s->cx = shape;
+    } else {
+        const int cw = shape / 100, cs = shape % 100;
+        if (shape != 0 && !((cw == 16 || cw == 32 || cw == 64) && (cs == 8 || cs == 16)))
+            return fail(LOSS_EINVAL, "bad y/z shape");
+        s->cw[axis] = cw;
+        s->cs[axis] = cs;
+    }
+    drop_graph(s);
+    return LOSS_OK;
+}
+
 loss_status loss_autotune_choice(loss_sim *s, int32_t axis, int32_t *cw)
 {
     if (!s || !cw || axis < 0 || axis > 2) return fail(LOSS_EINVAL, "bad argument");

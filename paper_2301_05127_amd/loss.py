@@ -28,7 +28,7 @@ EXPORTS = [
     "loss_reset", "loss_step", "loss_get_field", "loss_set_field", "loss_get_traces", "loss_deriv",
     "loss_forward_ckpt", "loss_adjoint", "loss_sync", "loss_set_timing", "loss_kernel_timing",
     "loss_current_step", "loss_status_str", "loss_last_error", "loss_autotune",
-    "loss_autotune_choice",
+    "loss_autotune_choice", "loss_set_shape",
 ]
 
 
@@ -81,6 +81,7 @@ def lib():
         "loss_current_step": (I64, [P]),
         "loss_autotune": (I32, [P, I32]),
         "loss_autotune_choice": (I32, [P, I32, ctypes.POINTER(I32)]),
+        "loss_set_shape": (I32, [P, I32, I32]),
         "loss_status_str": (ctypes.c_char_p, [I32]),
         "loss_last_error": (ctypes.c_char_p, []),
     }
@@ -271,6 +272,13 @@ class Simulation:
             _check(lib().loss_autotune_choice(self._h, axis, ctypes.byref(v)))
             out.append(v.value)
         return out
+
+    def set_shape(self, shapes):
+        """Set the launch shape per axis (see loss_set_shape); None entries are skipped."""
+        for axis, v in enumerate(shapes):
+            if v is None or (axis == 1 and self.grid["ndim"] == 2):
+                continue
+            _check(lib().loss_set_shape(self._h, axis, int(v)))
 
     # ---- timing ----------------------------------------------------------------
     def set_timing(self, on):
