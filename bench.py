@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the LOSS hot path on one MI355X.
 
-Workload (default): 2-D acoustic, 2048x2048 intervals (2049^2 nodes), h = 10 m,
+Workload (default cfg2): 2-D acoustic, 2048x2048 intervals (2049^2 nodes), h = 10 m,
 dt = 1 ms, 8x8 patches of 256 intervals, PMBC halo 12, velocity = smooth Gaussian
 random field in [1500, 4500] m/s (seed 2301, correlation 200 m), 20 Hz Ricker at the
-centre, receivers on every node of row z = 20 m; synthetic inputs.
+centre, receivers on every node of row z = 20 m; synthetic inputs.  Other workloads
+(--workload): cfg1 (129^2 acoustic), cfg3 (257^3 elastic, two shots in one batch),
+cfg4 (513^3 layered elastic), cfg5 (1025^2 acoustic, 64 shots; --grad also times the
+checkpointed forward and the adjoint and reports the gradient/forward ratio).
 
 One step = one Strang step of the whole hot path: PMBC junction slopes, patch
-tridiagonal solves and derivative epilogues along x and z for the stress and the
+tridiagonal solves and derivative epilogues along every axis for the stress and the
 velocity sub-flows, source injection, receiver recording.  Inputs are resident in
 device memory before the timed region; the timed region replays the step graph.
 
@@ -36,20 +39,30 @@ ALGO_BYTES = {
         "velocity_line_x": 16,   # read sigma, v1, b; write v1
         "velocity_line_z": 16,   # read sigma, v3, b; write v3
     },
+    1: {  # elastic, per axis: one normal-stress pass (read v_i, 3 sigma, lambda, lambda+2mu;
+          # write 3 sigma: 36 B) and two shear passes (read v, sigma_ij, mu; write sigma_ij:
+          # 16 B) -> 68 B over 3 launches; velocity passes read sigma_ij, v_i, b, write v_i
+        "stress_line_x": 68 / 3, "stress_line_y": 68 / 3, "stress_line_z": 68 / 3,
+        "velocity_line_x": 16, "velocity_line_y": 16, "velocity_line_z": 16,
+    },
 }
 STEP_BYTES = {0: 44, 1: 120}   # compulsory bytes per cell-step (whole step)
+DEFAULT_STEPS = {"cfg1": 300, "cfg2": 2000, "cfg3": 1000, "cfg4": 1500, "cfg5": 3000}
+CPU_SAMPLE_STEPS = {"cfg1": 300, "cfg2": 40, "cfg3": 2, "cfg4": 1, "cfg5": 60}
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=2000)
+    p.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's length)")
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--workload", default="cfg2")
-    p.add_argument("--shots", type=int, default=1)
+    p.add_argument("--workload", default="cfg2", choices=sorted(DEFAULT_STEPS))
+    p.add_argument("--shots", type=int, default=None, help="shots per batch (default: the workload's)")
     p.add_argument("--timing-steps", type=int, default=200)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-steps", type=int, default=40)
+    p.add_argument("--cpu-sample-steps", type=int, default=None)
+    p.add_argument("--grad", action="store_true",
+                   help="also time the checkpointed forward and the adjoint (gradient/forward ratio)")
     p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--shape", default=None,
                    help="launch shape per axis 'x,y,z' (loss_set_shape encoding); skips autotuning")
@@ -75,14 +88,36 @@ def cpu_baseline(w, nsteps):
     oracle.run(w["grid"], w["physics"], w["dt"], nsteps, w["vp"], w["rho"], vs=w.get("vs"),
                sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh.get("rec_comp", 0))
     el = time.perf_counter() - t0
-    nodes = int(np.prod([v + 1 for v in w["grid"]["n"] if True]))
-    if w["grid"]["ndim"] == 2:
-        nodes = (w["grid"]["n"][0] + 1) * (w["grid"]["n"][2] + 1)
+    n = w["grid"]["n"]
+    nodes = (n[0] + 1) * (n[2] + 1) * (1 if w["grid"]["ndim"] == 2 else n[1] + 1)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": nodes * nsteps / el / 1e6, "unit": "Mcell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d steps of the same workload, one shot, FP64 C oracle (canonical unfused "
                       "Strang, OpenMP over lines), %.1f s wall" % (nsteps, el)}
+
+
+def gradient_ratio(sim, w, S, nsteps, t_fwd):
+    """Time forward-with-checkpoints + adjoint over the same steps as the plain forward
+    (t_fwd); the residual is the recorded traces themselves (J = sum d^2 / 2)."""
+    import torch
+    every = int(w.get("ckpt_every", 100))
+    sim.reset()
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.forward_ckpt(nsteps, every)
+    sim.sync()
+    torch.cuda.synchronize()
+    t_ck = time.perf_counter() - t0
+    res = np.stack([sim.get_traces(s) for s in range(S)])
+    t0 = time.perf_counter()
+    g = sim.adjoint(res)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    return {"steps": nsteps, "ckpt_every": every, "forward_s": round(t_fwd, 4),
+            "forward_ckpt_s": round(t_ck, 4), "adjoint_s": round(t_adj, 4),
+            "ratio": round((t_ck + t_adj) / t_fwd, 3), "finite": bool(np.isfinite(g).all()),
+            "note": "adjoint time includes the host residual upload and gradient download"}
 
 
 def main():
@@ -97,9 +132,11 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
     torch.cuda.init()
+    if a.steps is None:
+        a.steps = DEFAULT_STEPS[a.workload]
     total = a.warmup + a.steps
     w = inputs.config(a.workload, nsteps=total)
-    S = a.shots
+    S = a.shots if a.shots is not None else len(w["shots"])
     shots = (w["shots"] * S)[:S]
     g = w["grid"]
     sim = loss.Simulation(g, w["physics"], w["dt"], nshots=S, trace_len=total)
@@ -148,6 +185,10 @@ def main():
     step_bytes = STEP_BYTES[w["physics"]]
     eff = value * 1e6 * step_bytes / 1e9
 
+    grad = None
+    if a.grad:
+        grad = gradient_ratio(sim, w, S, a.steps, el)
+
     if a.copy_probe:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -175,9 +216,11 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if grad:
+        res["gradient"] = grad
     if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(inputs.config(a.workload, nsteps=a.cpu_sample_steps),
-                                           a.cpu_sample_steps)
+        cs = a.cpu_sample_steps or CPU_SAMPLE_STEPS[a.workload]
+        res["cpu_baseline"] = cpu_baseline(inputs.config(a.workload, nsteps=cs), cs)
     sim.close()
     print(json.dumps(res), flush=True)
 

@@ -12,9 +12,20 @@
 // then every lane adds A_local * carry_in.  The derivative is fused with the
 // field update (epilogue).
 //
-//   x axis: lanes own C = 4 or 16 consecutive x nodes; G lanes per unit (power of 2).
-//   y, z axes: lanes own one x column each (coalesced), wave w owns chunk w of the
-//             unit along the axis; up to 16 waves per unit.
+// Two properties of the factors keep the kernels short:
+//  * the junction value of a patch (the PMBC slope, or its Hermite moment row)
+//    enters the first row of the patch linearly, so it is the carry into the
+//    patch: the slope's halo sum is formed while the chunks eliminate;
+//  * the elimination factors of the [1 4 1] rows are at most about 0.29, so the
+//    carry into a chunk depends on chunks more than `reach` rows back only through
+//    a product below 2^-44 (the axis table computes reach from the factors): the
+//    kernels compose the maps of the chunks within reach only.
+// Every global load of a lane (its nodes, factor rows, PMBC taps and the epilogue
+// operands) is issued before the solve, so a wave waits on memory once.
+//
+//   x axis: lanes own C = 4, 8 or 16 consecutive x nodes; G lanes per unit (power of 2).
+//   y, z axes: lanes own one x column each (coalesced), lane groups of a block own
+//             consecutive chunks of the unit along the axis.
 #include <hip/hip_runtime.h>
 
 #include "loss_internal.h"
@@ -25,18 +36,23 @@ namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// PMBC junction slope (eq. PMBC): phi_J = sum_t c_t u[idx_t] along the line.
-__device__ __forceinline__ float pmbc_phi(const AxisDev &ax, int slot, const float *__restrict__ in,
-                                          int64_t base, int64_t stride)
+// Node of tap t of the PMBC row of junction J (eq. PMBC: taps J-halo .. J+halo),
+// wrapped on a periodic axis; taps outside a non-periodic line carry a zero
+// coefficient, so the clamped node stands in for them.
+__device__ __forceinline__ int tap_node(const AxisDev &ax, int J, int t)
 {
-    const int *ti = ax.tap_idx + (int64_t)slot * ax.ntap;
-    const float *tc = ax.tap_c + (int64_t)slot * ax.ntap;
-    float acc = 0.f;
-    for (int t = 0; t < ax.ntap; ++t) {
-        const int k = ti[t];
-        if (k >= 0) acc = fmaf(tc[t], in[base + (int64_t)k * stride], acc);
-    }
-    return acc;
+    int k = J - ax.halo + t;
+    if (ax.periodic) k = k < 0 ? k + ax.N : (k >= ax.N ? k - ax.N : k);
+    else k = clampi(k, 0, ax.N);
+    return k;
+}
+
+// PMBC slots of the junction rows s and e of patch l (-1 at a natural end): the
+// slots number the junction rows in node order.
+__device__ __forceinline__ int slot_first(const AxisDev &ax, int l) { return ax.ends == 0 ? l - 1 : l; }
+__device__ __forceinline__ int slot_last(const AxisDev &ax, int l, int e)
+{
+    return e == ax.N ? (ax.ends == 0 ? -1 : ax.p) : (ax.ends == 0 ? l : l + 1);
 }
 
 // value of the input at element `idx` (media element `midx`), times the optional factor
@@ -112,8 +128,66 @@ __device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_
     }
 }
 
+// Epilogue operands of one node read ahead of the solve: out0, coef0, aux.
+struct Pre {
+    float o, c, x;
+};
+
+template <int EPI>
+__device__ __forceinline__ Pre pre_load(const LineArgs &a, int64_t oidx, int64_t midx)
+{
+    Pre r{0.f, 1.f, 0.f};
+    if constexpr (EPI == EPI_AXPY || EPI == EPI_AXPY_AUX) r.o = a.out[0][oidx];
+    if constexpr (EPI != EPI_STORE) r.c = a.coef[0] ? a.coef[0][midx] : 1.f;
+    if constexpr (EPI == EPI_AXPY_AUX || EPI == EPI_BASE) r.x = a.aux[oidx];
+    return r;
+}
+
+// Epilogue with out0 / coef0 / aux taken from `pr` (outputs j >= 1 are read here).
+template <int EPI>
+__device__ __forceinline__ void epilogue_pre(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float D,
+                                             const Pre &pr, int x, int y, int z, bool srcs)
+{
+    if (srcs) {
+        epilogue<EPI>(a, oidx, midx, shot, D, x, y, z);
+        return;
+    }
+    if constexpr (EPI == EPI_STORE) {
+        a.out[0][oidx] = D;
+    } else if constexpr (EPI == EPI_AXPY) {
+        a.out[0][oidx] = fmaf(a.alpha * pr.c, D, pr.o);
+        for (int j = 1; j < a.nout; ++j) {
+            const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
+            a.out[j][oidx] = fmaf(a.alpha * c, D, a.out[j][oidx]);
+        }
+    } else if constexpr (EPI == EPI_AXPY_AUX) {
+        const float dv = D + pr.x;
+        a.out[0][oidx] = fmaf(a.alpha * pr.c, dv, pr.o);
+        if (a.div) a.div[(int64_t)shot * a.div_shot_stride + midx] = dv;
+    } else {
+        a.out[0][oidx] = fmaf(a.alpha * pr.c, D, pr.x);
+    }
+}
+
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 __device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+
+// Epilogue operands of four consecutive x nodes (16-byte aligned).
+struct Pre4 {
+    float4 o, c, x;
+};
+
+template <int EPI>
+__device__ __forceinline__ Pre4 pre_load4(const LineArgs &a, int64_t oidx, int64_t midx)
+{
+    const float4 one = make_float4(1.f, 1.f, 1.f, 1.f), zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    Pre4 r{zero, one, zero};
+    if constexpr (EPI == EPI_AXPY || EPI == EPI_AXPY_AUX) r.o = ld4(a.out[0] + oidx);
+    if constexpr (EPI != EPI_STORE) r.c = a.coef[0] ? ld4(a.coef[0] + midx) : one;
+    if constexpr (EPI == EPI_AXPY_AUX || EPI == EPI_BASE) r.x = ld4(a.aux + oidx);
+    return r;
+}
+
 __device__ __forceinline__ float4 fma4(float a, float4 c, float4 d, float4 o)
 {
     return make_float4(fmaf(a * c.x, d.x, o.x), fmaf(a * c.y, d.y, o.y), fmaf(a * c.z, d.z, o.z),
@@ -123,7 +197,7 @@ __device__ __forceinline__ float4 fma4(float a, float4 c, float4 d, float4 o)
 // Epilogue of four consecutive x nodes (16-byte aligned, all inside the unit).
 template <int EPI>
 __device__ __forceinline__ void epilogue4(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float4 D,
-                                          int x, int y, int z, bool srcs)
+                                          const Pre4 &pr, int x, int y, int z, bool srcs)
 {
     if (srcs) {
         epilogue<EPI>(a, oidx, midx, shot, D.x, x, y, z);
@@ -132,82 +206,127 @@ __device__ __forceinline__ void epilogue4(const LineArgs &a, int64_t oidx, int64
         epilogue<EPI>(a, oidx + 3, midx + 3, shot, D.w, x + 3, y, z);
         return;
     }
-    const float4 one = make_float4(1.f, 1.f, 1.f, 1.f);
     if constexpr (EPI == EPI_STORE) {
         st4(a.out[0] + oidx, D);
     } else if constexpr (EPI == EPI_AXPY) {
-        for (int j = 0; j < a.nout; ++j) {
+        st4(a.out[0] + oidx, fma4(a.alpha, pr.c, D, pr.o));
+        const float4 one = make_float4(1.f, 1.f, 1.f, 1.f);
+        for (int j = 1; j < a.nout; ++j) {
             const float4 c = a.coef[j] ? ld4(a.coef[j] + midx) : one;
             st4(a.out[j] + oidx, fma4(a.alpha, c, D, ld4(a.out[j] + oidx)));
         }
     } else if constexpr (EPI == EPI_AXPY_AUX) {
-        const float4 t = ld4(a.aux + oidx);
-        const float4 dv = make_float4(D.x + t.x, D.y + t.y, D.z + t.z, D.w + t.w);
-        const float4 c = a.coef[0] ? ld4(a.coef[0] + midx) : one;
-        st4(a.out[0] + oidx, fma4(a.alpha, c, dv, ld4(a.out[0] + oidx)));
+        const float4 dv = make_float4(D.x + pr.x.x, D.y + pr.x.y, D.z + pr.x.z, D.w + pr.x.w);
+        st4(a.out[0] + oidx, fma4(a.alpha, pr.c, dv, pr.o));
         if (a.div) st4(a.div + (int64_t)shot * a.div_shot_stride + midx, dv);
     } else {
-        const float4 c = a.coef[0] ? ld4(a.coef[0] + midx) : one;
-        st4(a.out[0] + oidx, fma4(a.alpha, c, D, ld4(a.aux + oidx)));
+        st4(a.out[0] + oidx, fma4(a.alpha, pr.c, D, pr.x));
     }
 }
 
-// Right-hand side of row i of the solved system for the chunk value layout
-// u[c] = node q-1+c (so node i = q+cc sits at u[cc+1]).
-// phi_s: the PMBC slope of row s when the caller has already formed it (NAN = form it here)
+// Factors of the special rows of a patch, read once per unit.
+struct EndRows {
+    float4 lus, rcs, lu2s;     // row s: LU of T, stencil of G, LU of the moment system
+    float4 lue, rce, luTe;     // row e: LU of T, stencil of G, LU of T^T
+    float2 lu2e;               // row e as the closing row of the moment system
+};
+
 template <int SOLVE>
-__device__ __forceinline__ float row_rhs(const AxisDev &ax, int i, int s, float um, float u0, float up,
-                                         const float *__restrict__ in, int64_t base, int64_t stride,
-                                         float4 &fac, float phi_s = __builtin_nanf(""))
+__device__ __forceinline__ EndRows end_rows(const AxisDev &ax, int s, int e)
 {
-    if constexpr (SOLVE == SOLVE_D1) {
-        fac = ax.lu[i];
-        const float4 rc = ax.rc[i];
-        float r = fmaf(rc.x, um, fmaf(rc.y, u0, rc.z * up));
-        if (rc.w >= 0.f) r = (i == s && phi_s == phi_s) ? phi_s : pmbc_phi(ax, (int)rc.w, in, base, stride);
-        return r;
-    } else if constexpr (SOLVE == SOLVE_T1) {
-        fac = ax.luT[i];
-        return u0;
-    } else {  // SOLVE_D2: moment system of the patch starting at s
-        fac = ax.lu2[i];
-        const float ih = 1.f / ax.h;
-        if (i == s) {
-            const float4 l = ax.lu[i];
-            if (l.w == (float)ROW_NATURAL_L) return 0.f;
-            const float phi = (phi_s == phi_s) ? phi_s : pmbc_phi(ax, (int)ax.rc[i].w, in, base, stride);
-            return 6.f * ih * fmaf(up - u0, ih, -phi);
-        }
-        return 6.f * ih * ih * (um - 2.f * u0 + up);
+    EndRows r;
+    if constexpr (SOLVE != SOLVE_T1) {
+        r.lus = ax.lu[s];
+        r.lue = ax.lu[e];
     }
+    if constexpr (SOLVE == SOLVE_D1) {
+        r.rcs = ax.rc[s];
+        r.rce = ax.rc[e];
+    }
+    if constexpr (SOLVE == SOLVE_D2) {
+        r.lu2s = ax.lu2[s];
+        r.lu2e = ax.lu2c[e];
+    }
+    if constexpr (SOLVE == SOLVE_T1) r.luTe = ax.luT[e];
+    return r;
 }
 
-// Closing row e of a unit: given the eliminated value at e-1, return the solution at e.
+// Row s as the first row of the forward elimination, y_s = r - fm * carry, where the
+// carry into the patch is the junction slope phi_s (zero at a natural end):
+//   D1 junction: w_s = phi_s                            -> r = 0, fm = -1;
+//   D2 junction: Hermite moment row, rhs (6/h)((u_{s+1}-u_s)/h - phi_s)
+//                                                       -> r = 6(u_{s+1}-u_s)/h^2, fm = 6/h;
+//   natural end: the end row of the system, independent of the carry (fm = 0).
 template <int SOLVE>
-__device__ __forceinline__ float closing_row(const AxisDev &ax, int e, float ylast, float ulast,
-                                             float ue, const float *__restrict__ in, int64_t base,
-                                             int64_t stride, float phi_e = __builtin_nanf(""))
+__device__ __forceinline__ float first_row(const AxisDev &ax, const EndRows &er, float u0, float up, float &fm,
+                                           float &fi, float &fs)
 {
+    const bool junc = er.lus.w == (float)ROW_JUNCTION;
     if constexpr (SOLVE == SOLVE_D1) {
-        const float4 lu = ax.lu[e];
-        const float4 rc = ax.rc[e];
-        const float r = (rc.w >= 0.f)
-                            ? ((phi_e == phi_e) ? phi_e : pmbc_phi(ax, (int)rc.w, in, base, stride))
-                            : fmaf(rc.x, ulast, rc.y * ue);
-        return (r - lu.x * ylast) * lu.y;
-    } else if constexpr (SOLVE == SOLVE_T1) {
-        const float4 lu = ax.luT[e];
-        return (ue - lu.x * ylast) * lu.y;
+        fi = er.lus.y;
+        fs = er.lus.z;
+        fm = junc ? -1.f : er.lus.x;
+        return junc ? 0.f : fmaf(er.rcs.y, u0, er.rcs.z * up);
     } else {
-        const float2 f = ax.lu2c[e];
-        const float4 l = ax.lu[e];
+        const float ih = 1.f / ax.h;
+        fi = er.lu2s.y;
+        fs = er.lu2s.z;
+        fm = junc ? 6.f * ih : er.lu2s.x;
+        return junc ? 6.f * ih * ih * (up - u0) : 0.f;
+    }
+}
+
+// Closing row e of a unit: given the eliminated value at e-1, the solution at e.
+template <int SOLVE>
+__device__ __forceinline__ float last_row(const AxisDev &ax, const EndRows &er, float ylast, float ulast,
+                                          float ue, float phe)
+{
+    if constexpr (SOLVE == SOLVE_D1) {
+        const float r = (er.lue.w == (float)ROW_JUNCTION) ? phe : fmaf(er.rce.x, ulast, er.rce.y * ue);
+        return (r - er.lue.x * ylast) * er.lue.y;
+    } else if constexpr (SOLVE == SOLVE_T1) {
+        return (ue - er.luTe.x * ylast) * er.luTe.y;
+    } else {
         float r = 0.f;
-        if (l.w != (float)ROW_NATURAL_R) {
+        if (er.lue.w != (float)ROW_NATURAL_R) {
             const float ih = 1.f / ax.h;
-            const float phi = (phi_e == phi_e) ? phi_e : pmbc_phi(ax, (int)ax.rc[e].w, in, base, stride);
-            r = 6.f * ih * fmaf(-(ue - ulast), ih, phi);
+            r = 6.f * ih * fmaf(-(ue - ulast), ih, phe);
         }
-        return (r - f.x * ylast) * f.y;
+        return (r - er.lu2e.x * ylast) * er.lu2e.y;
+    }
+}
+
+// Factors {m, 1/d, sup} of rows q..q+C-1 (rows past N read the tables' identity padding).
+template <int C, int SOLVE>
+__device__ __forceinline__ void row_factors(const AxisDev &ax, int q, float (&fm)[C], float (&fi)[C],
+                                            float (&fs)[C])
+{
+    const int qt = min(q, ax.N);
+    if constexpr (SOLVE == SOLVE_T1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float4 f = ax.luT[qt + c];
+            fm[c] = f.x; fi[c] = f.y; fs[c] = f.z;
+        }
+    } else {
+        const float2 *tab = (SOLVE == SOLVE_D1) ? ax.lum : ax.lum2;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float2 f = tab[qt + c];
+            fm[c] = f.x; fi[c] = f.y; fs[c] = 1.f;   // sup = 1 on patch-interior rows
+        }
+    }
+}
+
+// Right-hand side of a patch-interior row from the node values u_{i-1}, u_i, u_{i+1}.
+template <int SOLVE>
+__device__ __forceinline__ float interior_rhs(const AxisDev &ax, float um, float u0, float up)
+{
+    if constexpr (SOLVE == SOLVE_D1) return ax.s3 * (up - um);
+    else if constexpr (SOLVE == SOLVE_T1) return u0;
+    else {
+        const float ih = 1.f / ax.h;
+        return 6.f * ih * ih * (um - 2.f * u0 + up);
     }
 }
 
@@ -237,16 +356,9 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
     const int s = l * M;
     const int e = min(s + M, N);
     const int q = s + k * C;
-    int rowz = 0, rowy = 0;                       // coordinates, only for source terms
-    bool srcs = false;
-    if (a.src) {
-        const int r = line - shot * lps;
-        rowz = r / a.ny;
-        rowy = r - rowz * a.ny;
-        srcs = segment_has_source(a, shot, 0, 0, rowy, rowz, q, min(q + C, N));
-    }
     const float *__restrict__ in = a.in;
 
+    // ---- loads -------------------------------------------------------------
     // chunk values u[1..C] = nodes q..q+C-1 (16-byte loads when aligned and inside
     // the line); u[0], u[C+1] = the neighbouring lanes' edge nodes
     float u[C + 2];
@@ -263,72 +375,96 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
             u[c] = load_in(a, base + i, mbase + i);
         }
     }
+    const int ir = min(q + C, N);
+    const float uright = load_in(a, base + ir, mbase + ir);   // kept by the unit's last lane
+    float fm[C], fi[C], fs[C];
+    row_factors<C, SOLVE>(ax, q, fm, fi, fs);
+    const EndRows er = end_rows<SOLVE>(ax, s, e);
+    // PMBC taps of rows s and e, shared by the G lanes of the unit: taps k and k+G
+    // of this lane (loads without a wait in between; the products are selected later)
+    const int nt = ax.ntap;
+    const int ss = slot_first(ax, l), se = slot_last(ax, l, e);
+    float tcs[2] = {0.f, 0.f}, tvs[2] = {0.f, 0.f}, tce[2] = {0.f, 0.f}, tve[2] = {0.f, 0.f};
+    if constexpr (SOLVE != SOLVE_T1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 0 || G < nt) {
+                const int t = min(k + h * G, nt - 1);
+                tcs[h] = ax.tap_c[max(ss, 0) * nt + t];
+                tce[h] = ax.tap_c[max(se, 0) * nt + t];
+                tvs[h] = in[base + tap_node(ax, s, t)];
+                tve[h] = in[base + tap_node(ax, e, t)];
+            }
+        }
+    }
+    // epilogue operands of the aligned whole-chunk case
+    const bool vec = ((q & 3) == 0) && q + C <= e;
+    Pre4 pre[C / 4];
+    if (vec) {
+#pragma unroll
+        for (int g4 = 0; g4 < C / 4; ++g4) pre[g4] = pre_load4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4);
+    }
+    int rowz = 0, rowy = 0;                       // coordinates, only for source terms
+    bool srcs = false;
+    if (a.src) {
+        const int r = line - shot * lps;
+        rowz = r / a.ny;
+        rowy = r - rowz * a.ny;
+        srcs = segment_has_source(a, shot, 0, 0, rowy, rowz, q, min(q + C, N));
+    }
+    float phs = 0.f, phe = 0.f;
+    if constexpr (SOLVE != SOLVE_T1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool ok = k + h * G < nt;
+            if (ss >= 0 && ok) phs = fmaf(tcs[h], tvs[h], phs);
+            if (se >= 0 && ok) phe = fmaf(tce[h], tve[h], phe);
+        }
+        for (int t = k + 2 * G; t < nt; t += G) {   // halos wider than two taps per lane
+            if (ss >= 0) phs = fmaf(ax.tap_c[ss * nt + t], in[base + tap_node(ax, s, t)], phs);
+            if (se >= 0) phe = fmaf(ax.tap_c[se * nt + t], in[base + tap_node(ax, e, t)], phe);
+        }
+    }
+
+    // ---- solve -------------------------------------------------------------
     {
         const float left = __shfl_up(u[C], 1, G);
         const float right = __shfl_down(u[1], 1, G);
         u[0] = (k == 0) ? u[1] : left;   // row s never uses node s-1
-        if (k == G - 1) {
-            const int i = min(q + C, N);
-            u[C + 1] = load_in(a, base + i, mbase + i);
-        } else {
-            u[C + 1] = right;
-        }
+        u[C + 1] = (k == G - 1) ? uright : right;
     }
-
-    // PMBC slopes of rows s and e: the G lanes of the unit share the taps, then a
-    // butterfly sum over the group (no lane walks the halo alone)
-    float phs = 0.f, phe = 0.f;
-    if constexpr (SOLVE == SOLVE_D1 || SOLVE == SOLVE_D2) {
-        const int ss = (int)ax.rc[s].w, se = (int)ax.rc[e].w;
-        // tap t of the row at junction J sits at node J - halo + t (wrapped on a periodic
-        // axis; taps outside the line carry a zero coefficient)
-        for (int t = k; t < ax.ntap; t += G) {
-            if (ss >= 0) {
-                int ki = s - ax.halo + t;
-                ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                phs = fmaf(ax.tap_c[ss * ax.ntap + t], in[base + ki], phs);
-            }
-            if (se >= 0) {
-                int ki = e - ax.halo + t;
-                ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                phe = fmaf(ax.tap_c[se * ax.ntap + t], in[base + ki], phe);
-            }
-        }
+    if constexpr (SOLVE != SOLVE_T1) {
         for (int d = G >> 1; d > 0; d >>= 1) {
             phs += __shfl_xor(phs, d, G);
             phe += __shfl_xor(phe, d, G);
         }
     }
 
-    float y[C], P[C], fi[C], fs[C];   // eliminated rhs, carry factor, 1/pivot, superdiagonal
+    // forward elimination over the chunk from a zero carry
+    float y[C], P[C];   // eliminated rhs, carry factor
     float yv = 0.f, pv = 1.f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int i = min(q + c, N);
-        float r, fm;
-        if (SOLVE == SOLVE_D1 && i != s) {
-            // rows strictly inside the patch: [1 4 1] with rhs (3/h)(u_{i+1} - u_{i-1})
-            const float2 f = ax.lum[i];
-            fm = f.x; fi[c] = f.y; fs[c] = 1.f;
-            r = ax.s3 * (u[c + 2] - u[c]);
-        } else {
-            float4 f;
-            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, base, 1, f, phs);
-            fm = f.x; fi[c] = f.y; fs[c] = f.z;
+        float r = interior_rhs<SOLVE>(ax, u[c], u[c + 1], u[c + 2]);
+        if constexpr (SOLVE != SOLVE_T1) {
+            if (c == 0 && k == 0) r = first_row<SOLVE>(ax, er, u[1], u[2], fm[0], fi[0], fs[0]);
         }
-        yv = fmaf(-fm, yv, r);
-        pv = -fm * pv;
+        yv = fmaf(-fm[c], yv, r);
+        pv = -fm[c] * pv;
         y[c] = yv;
         P[c] = pv;
     }
-    // compose the forward carries over the unit (inclusive scan of affine maps)
+    // compose the forward carries of the lanes within reach (inclusive scan of
+    // affine maps); the first lane's carry is the junction slope
+    const int reach = ax.reach;
     float A = pv, B = yv;
-    for (int d = 1; d < G; d <<= 1) {
+    if (k == 0) { B = fmaf(A, phs, B); A = 0.f; }
+    for (int d = 1; d < G && d * C < reach; d <<= 1) {
         const float Ap = __shfl_up(A, d, G), Bp = __shfl_up(B, d, G);
         if (k >= d) { B = fmaf(A, Bp, B); A = A * Ap; }
     }
     float yin = __shfl_up(B, 1, G);
-    if (k == 0) yin = 0.f;
+    if (k == 0) yin = phs;
 #pragma unroll
     for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
 
@@ -340,7 +476,7 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
 #pragma unroll
         for (int c = 0; c < C; ++c)
             if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
-        we = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, base, 1, phe);
+        we = last_row<SOLVE>(ax, er, ylast, ulast, ue, phe);
     }
     we = __shfl(we, kc, G);
 
@@ -350,30 +486,31 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
         if (q + c < e) {
-            const float inv = fi[c], sp = fs[c];
-            wv = fmaf(-sp, wv, y[c]) * inv;
-            qv = -sp * inv * qv;
+            wv = fmaf(-fs[c], wv, y[c]) * fi[c];
+            qv = -fs[c] * fi[c] * qv;
         }
         w[c] = wv;
         Q[c] = qv;
     }
     float Qm = qv, Wm = wv;
-    for (int d = 1; d < G; d <<= 1) {
+    for (int d = 1; d < G && d * C < reach; d <<= 1) {
         const float Qn = __shfl_down(Qm, d, G), Wn = __shfl_down(Wm, d, G);
         if (k + d < G) { Wm = fmaf(Qm, Wn, Wm); Qm = Qm * Qn; }
     }
     float Qx = __shfl_down(Qm, 1, G), Wx = __shfl_down(Wm, 1, G);
     if (k == G - 1) { Qx = 1.f; Wx = 0.f; }
+    // lanes past the closing row hold identity maps, so the closing value enters
+    // exactly where the window reaches it (elsewhere its factor is below the tolerance)
     const float wr = fmaf(Qx, we, Wx);
 
     if (uact) {
 #pragma unroll
         for (int c = 0; c < C; ++c) w[c] = fmaf(Q[c], wr, w[c]);
-        if (((q & 3) == 0) && q + C <= e) {
+        if (vec) {
 #pragma unroll
             for (int g4 = 0; g4 < C / 4; ++g4)
                 epilogue4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4, shot,
-                               make_float4(w[4 * g4], w[4 * g4 + 1], w[4 * g4 + 2], w[4 * g4 + 3]),
+                               make_float4(w[4 * g4], w[4 * g4 + 1], w[4 * g4 + 2], w[4 * g4 + 3]), pre[g4],
                                q + 4 * g4, rowy, rowz, srcs);
         } else {
 #pragma unroll
@@ -390,16 +527,21 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
 // y / z axes (strided).
 // ---------------------------------------------------------------------------
 constexpr int kMaxWaves = 16;
+constexpr int kTapChunks = 8;      // chunks of a unit that share the PMBC taps
+constexpr int kTapsPerChunk = 4;   // taps per chunk loaded ahead of the solve
 
 // Columns are the flattened (shot, other coordinate, x) positions of the lines: one
 // lane per column, CW consecutive columns per wave (64, 32 or 16), the 64/CW lane
 // groups of a wave and the waves of the block holding consecutive chunks of C nodes
-// along the axis.  Chunk maps are composed through LDS.
+// along the axis.  Chunk maps and PMBC partial sums meet in LDS: two barriers.
+// Dynamic LDS: 6 * blockDim.x + 64 floats.
 template <int C, int SOLVE, int EPI>
 __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, int gx_real)
 {
-    __shared__ float sA[1024], sB[1024], sQ[1024], sW[1024];
-    __shared__ float sWe[64];
+    extern __shared__ float lds[];
+    const int nthr = blockDim.x;
+    float *sA = lds, *sB = lds + nthr, *sPs = lds + 2 * nthr, *sPe = lds + 3 * nthr;
+    float *sQ = lds + 4 * nthr, *sW = lds + 5 * nthr, *sWe = lds + 6 * nthr;
     const AxisDev &ax = a.ax;
     // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD
     // a contiguous range of column groups (neighbouring groups share cache lines and
@@ -416,9 +558,10 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int SUB = 64 / CW;
-    const int NCH = (blockDim.x >> 6) * SUB;
+    const int NCH = (nthr >> 6) * SUB;
     const int ci = lane & (CW - 1);
     const int chunk = wv * SUB + lane / CW;
+    const int me = chunk * CW + ci;
     const int n_other = (axis == 1) ? a.nz : a.ny;
     const int pitch = (int)a.pitch;
     const int per_shot = n_other * pitch;
@@ -440,71 +583,86 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
     const int e = min(s + M, N);
     const int q = s + chunk * C;
 
-    // PMBC slopes of rows s and e for this column: the chunks of the unit share the
-    // taps (independent loads), partial sums meet in LDS
-    float phs = __builtin_nanf(""), phe = __builtin_nanf("");
-    if constexpr (SOLVE == SOLVE_D1 || SOLVE == SOLVE_D2) {
-        const int ss = (int)ax.rc[s].w, se = (int)ax.rc[e].w;
-        if (ss >= 0 || se >= 0) {
-            float ps = 0.f, pe = 0.f;
-            for (int t = chunk; t < ax.ntap; t += NCH) {
-                if (ss >= 0) {
-                    int ki = s - ax.halo + t;
-                    ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                    ps = fmaf(ax.tap_c[ss * ax.ntap + t], in[mbase + ki * stride], ps);
-                }
-                if (se >= 0) {
-                    int ki = e - ax.halo + t;
-                    ki = ax.periodic ? (ki + 2 * N) % N : clampi(ki, 0, N);
-                    pe = fmaf(ax.tap_c[se * ax.ntap + t], in[mbase + ki * stride], pe);
-                }
-            }
-            sA[chunk * CW + ci] = ps;
-            sB[chunk * CW + ci] = pe;
-            __syncthreads();
-            float sumS = 0.f, sumE = 0.f;
-            for (int j = 0; j < NCH; ++j) {
-                sumS += sA[j * CW + ci];
-                sumE += sB[j * CW + ci];
-            }
-            phs = sumS;
-            phe = sumE;
-            __syncthreads();
-        }
-    }
-
+    // ---- loads -------------------------------------------------------------
     float u[C + 2];
 #pragma unroll
     for (int c = 0; c < C + 2; ++c) {
         const int off = mbase + clampi(q - 1 + c, 0, N) * stride;
         u[c] = a.in_coef ? in[off] * a.in_coef[off] : in[off];
     }
+    float fm[C], fi[C], fs[C];
+    row_factors<C, SOLVE>(ax, q, fm, fi, fs);
+    const EndRows er = end_rows<SOLVE>(ax, s, e);
+    // PMBC partial sums of rows s and e: the first T chunks share the taps, chunk j
+    // taking taps j, j+T, ... (kTapsPerChunk of them without a wait in between)
+    const int T = min(NCH, kTapChunks);
+    const int nt = ax.ntap;
+    const int ss = slot_first(ax, l), se = slot_last(ax, l, e);
+    float tcs[kTapsPerChunk] = {}, tvs[kTapsPerChunk] = {}, tce[kTapsPerChunk] = {}, tve[kTapsPerChunk] = {};
+    if (SOLVE != SOLVE_T1 && chunk < T) {
+#pragma unroll
+        for (int h = 0; h < kTapsPerChunk; ++h) {
+            const int t = min(chunk + h * T, nt - 1);
+            tcs[h] = ax.tap_c[max(ss, 0) * nt + t];
+            tce[h] = ax.tap_c[max(se, 0) * nt + t];
+            tvs[h] = in[mbase + tap_node(ax, s, t) * stride];
+            tve[h] = in[mbase + tap_node(ax, e, t) * stride];
+        }
+    }
+    // epilogue operands (small chunks only: they cost 3 registers per node)
+    constexpr bool kPre = C <= 8;
+    Pre pre[kPre ? C : 1];
+    if constexpr (kPre) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int off = mbase + min(q + c, N) * stride;
+            pre[c] = pre_load<EPI>(a, sbase + off, off);
+        }
+    }
+    float ps = 0.f, pe = 0.f;
+    if constexpr (SOLVE != SOLVE_T1) {
+        if (chunk < T) {
+#pragma unroll
+            for (int h = 0; h < kTapsPerChunk; ++h) {
+                const bool ok = chunk + h * T < nt;
+                if (ss >= 0 && ok) ps = fmaf(tcs[h], tvs[h], ps);
+                if (se >= 0 && ok) pe = fmaf(tce[h], tve[h], pe);
+            }
+            for (int t = chunk + kTapsPerChunk * T; t < nt; t += T) {   // wide halos
+                if (ss >= 0) ps = fmaf(ax.tap_c[ss * nt + t], in[mbase + tap_node(ax, s, t) * stride], ps);
+                if (se >= 0) pe = fmaf(ax.tap_c[se * nt + t], in[mbase + tap_node(ax, e, t) * stride], pe);
+            }
+        }
+    }
 
-    float y[C], P[C], fi[C], fs[C];
+    // ---- forward elimination, chunk maps -------------------------------------
+    float y[C], P[C];
     float yv = 0.f, pv = 1.f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int i = min(q + c, N);
-        float r, fm;
-        if (SOLVE == SOLVE_D1 && i != s) {
-            const float2 f = ax.lum[i];
-            fm = f.x; fi[c] = f.y; fs[c] = 1.f;
-            r = ax.s3 * (u[c + 2] - u[c]);
-        } else {
-            float4 f;
-            r = row_rhs<SOLVE>(ax, i, s, u[c], u[c + 1], u[c + 2], in, mbase, stride, f, phs);
-            fm = f.x; fi[c] = f.y; fs[c] = f.z;
+        float r = interior_rhs<SOLVE>(ax, u[c], u[c + 1], u[c + 2]);
+        if constexpr (SOLVE != SOLVE_T1) {
+            if (c == 0 && chunk == 0) r = first_row<SOLVE>(ax, er, u[1], u[2], fm[0], fi[0], fs[0]);
         }
-        yv = fmaf(-fm, yv, r);
-        pv = -fm * pv;
+        yv = fmaf(-fm[c], yv, r);
+        pv = -fm[c] * pv;
         y[c] = yv;
         P[c] = pv;
     }
-    sA[chunk * CW + ci] = pv;
-    sB[chunk * CW + ci] = yv;
+    sA[me] = pv;
+    sB[me] = yv;
+    sPs[me] = ps;
+    sPe[me] = pe;
     __syncthreads();
+    // carry: the maps of the chunks within reach, from the junction slope when the
+    // window starts at the unit's first chunk
+    const int Dc = (ax.reach + C - 1) / C;
+    const int j0 = max(0, chunk - Dc);
     float yin = 0.f;
-    for (int j = 0; j < chunk; ++j) yin = fmaf(sA[j * CW + ci], yin, sB[j * CW + ci]);
+    if (SOLVE != SOLVE_T1 && j0 == 0) {
+        for (int j = 0; j < T; ++j) yin += sPs[j * CW + ci];
+    }
+    for (int j = j0; j < chunk; ++j) yin = fmaf(sA[j * CW + ci], yin, sB[j * CW + ci]);
 #pragma unroll
     for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
 
@@ -514,27 +672,30 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
 #pragma unroll
         for (int c = 0; c < C; ++c)
             if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
-        sWe[ci] = closing_row<SOLVE>(ax, e, ylast, ulast, ue, in, mbase, stride, phe);
+        float phe = 0.f;
+        if (SOLVE != SOLVE_T1)
+            for (int j = 0; j < T; ++j) phe += sPe[j * CW + ci];
+        sWe[ci] = last_row<SOLVE>(ax, er, ylast, ulast, ue, phe);
     }
 
+    // ---- back substitution ---------------------------------------------------
     float w[C], Q[C];
     float wvv = 0.f, qv = 1.f;
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
         if (q + c < e) {
-            const float inv = fi[c], sp = fs[c];
-            wvv = fmaf(-sp, wvv, y[c]) * inv;
-            qv = -sp * inv * qv;
+            wvv = fmaf(-fs[c], wvv, y[c]) * fi[c];
+            qv = -fs[c] * fi[c] * qv;
         }
         w[c] = wvv;
         Q[c] = qv;
     }
-    sQ[chunk * CW + ci] = qv;
-    sW[chunk * CW + ci] = wvv;
+    sQ[me] = qv;
+    sW[me] = wvv;
     __syncthreads();
     const float we = sWe[ci];
-    float wr = we;
-    for (int j = NCH - 1; j > chunk; --j) wr = fmaf(sQ[j * CW + ci], wr, sW[j * CW + ci]);
+    float wr = we;   // chunks past kc hold identity maps
+    for (int j = min(NCH - 1, chunk + Dc); j > chunk; --j) wr = fmaf(sQ[j * CW + ci], wr, sW[j * CW + ci]);
 
     if (cact) {
         const int cy = axis == 1 ? 0 : o, cz = axis == 1 ? o : 0;
@@ -544,8 +705,13 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
             const int i = q + c;
             if (i < e) {
                 const int off = mbase + i * stride;
-                epilogue<EPI>(a, sbase + off, off, shot, fmaf(Q[c], wr, w[c]), col, axis == 1 ? i : cy,
-                              axis == 1 ? cz : i, srcs);
+                const float D = fmaf(Q[c], wr, w[c]);
+                if constexpr (kPre)
+                    epilogue_pre<EPI>(a, sbase + off, off, shot, D, pre[c], col, axis == 1 ? i : cy,
+                                      axis == 1 ? cz : i, srcs);
+                else
+                    epilogue<EPI>(a, sbase + off, off, shot, D, col, axis == 1 ? i : cy, axis == 1 ? cz : i,
+                                  srcs);
             }
         }
         if (e == N && chunk == kc) {
@@ -805,11 +971,12 @@ hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
     const int gxp = (gx + 7) / 8 * 8;
     dim3 grid((unsigned)gxp, a.ax.p, 1);
     const int threads = 64 * W;
+    const size_t shm = (6 * (size_t)threads + 64) * sizeof(float);
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, 0, st, a, axis, CW, gx); break;
-    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, 0, st, a, axis, CW, gx); break;
-    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, 0, st, a, axis, CW, gx); break;
-    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, 0, st, a, axis, CW, gx); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, shm, st, a, axis, CW, gx); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

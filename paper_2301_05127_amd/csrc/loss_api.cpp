@@ -106,6 +106,9 @@ struct loss_sim {
     double kms[KC_COUNT] = {0};
     int64_t kcount[KC_COUNT] = {0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // side stream for receiver recording that overlaps the velocity pass
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // adjoint
     float *ckpt = nullptr;         // [nseg][3 fields][S][shot_stride] fused states
     int64_t ck_every = 0, ck_steps = 0, ck_nseg = 0;
@@ -255,15 +258,17 @@ loss_status inject(loss_sim *s, float **fields_dev, int time_offset, float scale
     return timed_end(s, KC_SOURCE);
 }
 
-// record one or two receiver lists into trace sample (*d_step - 1) (inside a step)
+// record one or two receiver lists into trace sample (*d_step - 1) (inside a step),
+// on stream `st` (default: the simulation stream)
 loss_status record(loss_sim *s, const RecDev *rec0, int nrec0, float w0, int acc0,
-                   const RecDev *rec1 = nullptr, int nrec1 = 0, float w1 = 0.f, int acc1 = 0)
+                   const RecDev *rec1 = nullptr, int nrec1 = 0, float w1 = 0.f, int acc1 = 0,
+                   hipStream_t st = nullptr)
 {
     if (nrec0 + nrec1 == 0 || s->d.trace_len == 0) return LOSS_OK;
     loss_status r = timed_begin(s);
     if (r) return r;
     hipError_t e = launch_record2(rec0, nrec0, w0, acc0, rec1, nrec1, w1, acc1, s->d_fields, s->shot_stride,
-                                  s->traces, s->d_step, -1, s->d.trace_len, s->st);
+                                  s->traces, s->d_step, -1, s->d.trace_len, st ? st : s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("record: ") + hipGetErrorString(e));
     return timed_end(s, KC_RECEIVER);
 }
@@ -578,17 +583,31 @@ loss_status unfuse_in_place(loss_sim *s)
 // One fused step.  The first line kernel advances the step counter, so inside the
 // step *d_step = n + 1: stress sources use sample n (offset -1, added in the stress
 // epilogue), forces sample n + 1 (offset 0, velocity epilogue), traces slot n.
+//
+// Stress receivers read only sigma, which the velocity pass does not write: with no
+// velocity receivers (whose first half is read before the velocity pass) they are
+// recorded on the side stream while the velocity pass runs, joined before the step
+// ends (the next step advances the counter and rewrites sigma).
 loss_status one_step(loss_sim *s, float *div_store, int64_t div_shot_stride)
 {
     loss_status r;
     s->pending_inc = true;
     if ((r = stress_stage(s, div_store, div_shot_stride))) return r;
-    if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0, s->d_rec_vel, s->nrec_vel, 0.5f, 0))) return r;
+    const bool side = s->nrec_vel == 0 && s->nrec_str > 0 && s->d.trace_len > 0 && !s->timing;
+    if (side) {
+        HIPCHK(hipEventRecord(s->ev_fork, s->st));
+        HIPCHK(hipStreamWaitEvent(s->st2, s->ev_fork, 0));
+        if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0, nullptr, 0, 0.f, 0, s->st2))) return r;
+        HIPCHK(hipEventRecord(s->ev_join, s->st2));
+    } else if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0, s->d_rec_vel, s->nrec_vel, 0.5f, 0))) {
+        return r;
+    }
     std::vector<float *> vel;
     if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
     else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
     if ((r = velocity_stage(s, 1.0f, vel.data(), nullptr, true))) return r;
     if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 1))) return r;
+    if (side) HIPCHK(hipStreamWaitEvent(s->st, s->ev_join, 0));
     return LOSS_OK;
 }
 
@@ -682,9 +701,17 @@ loss_status copy_field_out(loss_sim *s, float *dst_dense, const float *src_padde
 loss_status upload_axis(loss_sim *s, int axis)
 {
     const AxisHost &h = s->axh[axis];
-    const int n = h.N + 1;
-    std::vector<float4> lu(n), rc(n), luT(n), lu2(n);
-    std::vector<float2> lu2c(n), lum(n);
+    const int n = h.N + 1, np = n + kTabPad;
+    // the line kernels derive the PMBC slots of a patch from its index
+    for (int l = 0; l < h.p; ++l) {
+        const int st = l * h.M, e = std::min(st + h.M, h.N);
+        const int ss = h.end_mode == LOSS_END_NATURAL ? l - 1 : l;
+        const int se = e == h.N ? (h.end_mode == LOSS_END_NATURAL ? -1 : h.p)
+                                : (h.end_mode == LOSS_END_NATURAL ? l : l + 1);
+        if (h.slot[st] != ss || h.slot[e] != se) return fail(LOSS_EINVAL, "internal: junction slot order");
+    }
+    std::vector<float4> lu(n), rc(n), luT(np, make_float4(0.f, 1.f, 0.f, 0.f)), lu2(n);
+    std::vector<float2> lu2c(n), lum(np, make_float2(0.f, 1.f)), lum2(np, make_float2(0.f, 1.f));
     for (int i = 0; i < n; ++i) {
         lu[i] = make_float4((float)h.m[i], (float)h.invd[i], (float)h.sup[i], (float)h.kind[i]);
         rc[i] = make_float4((float)h.cm[i], (float)h.c0[i], (float)h.cp[i], (float)h.slot[i]);
@@ -692,29 +719,33 @@ loss_status upload_axis(loss_sim *s, int axis)
         lu2[i] = make_float4((float)h.m2[i], (float)h.invd2[i], (float)h.sup2[i], 0.f);
         lu2c[i] = make_float2((float)h.m2c[i], (float)h.invd2c[i]);
         lum[i] = make_float2((float)h.m[i], (float)h.invd[i]);
+        lum2[i] = make_float2((float)h.m2[i], (float)h.invd2[i]);
     }
-    std::vector<float> tc(h.tap_c.begin(), h.tap_c.end()), gc(h.g_c.begin(), h.g_c.end());
+    // at least one slot of taps: the kernels read slot 0 even on a line without junctions
+    std::vector<float> tc(std::max<size_t>(h.tap_c.size(), 2 * h.halo + 1), 0.f), gc(h.g_c.begin(), h.g_c.end());
+    std::copy(h.tap_c.begin(), h.tap_c.end(), tc.begin());
     float4 *dlu, *drc, *dluT, *dlu2;
-    float2 *dlu2c, *dlum;
+    float2 *dlu2c, *dlum, *dlum2;
     int *dti, *dgn;
     float *dtc, *dgc;
     loss_status r;
-    if ((r = s->alloc(&dlu, n)) || (r = s->alloc(&drc, n)) || (r = s->alloc(&dluT, n)) ||
-        (r = s->alloc(&dlu2, n)) || (r = s->alloc(&dlu2c, n)) || (r = s->alloc(&dlum, n)) ||
+    if ((r = s->alloc(&dlu, n)) || (r = s->alloc(&drc, n)) || (r = s->alloc(&dluT, np)) ||
+        (r = s->alloc(&dlu2, n)) || (r = s->alloc(&dlu2c, n)) || (r = s->alloc(&dlum, np)) ||
+        (r = s->alloc(&dlum2, np)) ||
         (r = s->alloc(&dti, std::max<size_t>(1, h.tap_idx.size()))) ||
-        (r = s->alloc(&dtc, std::max<size_t>(1, tc.size()))) ||
+        (r = s->alloc(&dtc, tc.size())) ||
         (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())))
         return r;
     HIPCHK(hipMemcpy(dlu, lu.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(drc, rc.data(), n * sizeof(float4), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(dluT, luT.data(), n * sizeof(float4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dluT, luT.data(), np * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dlu2, lu2.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dlu2c, lu2c.data(), n * sizeof(float2), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(dlum, lum.data(), n * sizeof(float2), hipMemcpyHostToDevice));
-    if (!h.tap_idx.empty()) {
+    HIPCHK(hipMemcpy(dlum, lum.data(), np * sizeof(float2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dlum2, lum2.data(), np * sizeof(float2), hipMemcpyHostToDevice));
+    if (!h.tap_idx.empty())
         HIPCHK(hipMemcpy(dti, h.tap_idx.data(), h.tap_idx.size() * sizeof(int), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(dtc, tc.data(), tc.size() * sizeof(float), hipMemcpyHostToDevice));
-    }
+    HIPCHK(hipMemcpy(dtc, tc.data(), tc.size() * sizeof(float), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dgn, h.g_node.data(), h.g_node.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dgc, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice));
     AxisDev &d = s->axd[axis];
@@ -722,7 +753,9 @@ loss_status upload_axis(loss_sim *s, int axis)
     d.s3 = (float)(3.0 / h.h);
     d.halo = h.halo;
     d.periodic = h.end_mode == LOSS_END_PERIODIC;
-    d.lum = dlum;
+    d.ends = h.end_mode;
+    d.reach = h.reach;
+    d.lum = dlum; d.lum2 = dlum2;
     d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
     d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc;
     return LOSS_OK;
@@ -810,6 +843,10 @@ loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out)
         return bail(fail(LOSS_EHIP, "pointer table upload"));
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
         return bail(fail(LOSS_EHIP, "hipEventCreate"));
+    if (hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(LOSS_EHIP, "side stream"));
     s->src.assign(s->S, {});
     s->rec.assign(s->S, RecHost());
     // zero state (fill kernels, no memset nodes)
@@ -836,6 +873,9 @@ loss_status loss_destroy(loss_sim *s)
     s->allocs.clear();
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    if (s->st2) { (void)hipStreamSynchronize(s->st2); (void)hipStreamDestroy(s->st2); }
     if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
     delete s;
     return LOSS_OK;

@@ -25,6 +25,10 @@ namespace loss {
 
 constexpr int kMaxHalo = 64;
 constexpr int kMaxGatherTaps = 4;   // junction rows reaching one node (transposed PMBC)
+constexpr int kTabPad = 64;         // identity rows after row N of the per-row factor tables
+// The carry a chunk leaves out of its elimination when it composes only the maps of
+// the chunks within `reach` rows is at most kReachTol times the carry itself.
+constexpr double kReachTol = 0x1p-44;
 
 // Row kinds of the derivative system of one axis.
 enum RowKind : int { ROW_INTERIOR = 0, ROW_JUNCTION = 1, ROW_NATURAL_L = 2, ROW_NATURAL_R = 3 };
@@ -49,6 +53,7 @@ struct AxisHost {
     // second-derivative system (per patch, Hermite/natural end rows)
     std::vector<double> m2, invd2, sup2;    // factors for rows as the first/interior row of a patch
     std::vector<double> m2c, invd2c;        // factors of node i as the closing row of the patch ending at i
+    int reach = 0;                      // rows of carry composition (see kReachTol)
 };
 
 // Build the tables; returns an empty string on success, else the reason.
@@ -57,12 +62,15 @@ std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_m
 // Device copy of one axis (float32).
 struct AxisDev {
     int N, M, p, ntap, halo, periodic;
+    int ends;              // end mode (LOSS_END_*): junction slots of patch l are l-1, l (natural) or l, l+1
+    int reach;             // rows of carry composition across chunks (see kReachTol)
     float h;
     float s3;              // 3/h, the stencil weight of interior rows of G
-    const float2 *lum;     // {m, invd} of T (compact copy for interior rows)
+    const float2 *lum;     // {m, invd} of T (compact copy for interior rows; kTabPad rows past N)
+    const float2 *lum2;    // {m2, invd2} of the moment system (compact, padded like lum)
     const float4 *lu;      // {m, invd, sup, kind}
     const float4 *rc;      // {cm, c0, cp, slot}
-    const float4 *luT;     // {mT, invdT, supT, subT}
+    const float4 *luT;     // {mT, invdT, supT, subT} (padded like lum)
     const float4 *lu2;     // {m2, invd2, sup2, 0}
     const float2 *lu2c;    // {m2c, invd2c}
     const int *tap_idx;    // [nslot][ntap]

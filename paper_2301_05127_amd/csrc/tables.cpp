@@ -70,6 +70,37 @@ void periodic_inverse_col(int N, std::vector<double> &g)
     for (int k = 0; k < N; ++k) g[k] = alpha * (std::pow(r, k) + std::pow(r, N - k));
 }
 
+// Rows of composition a chunk boundary needs in one sweep direction.  Forward
+// elimination: y_r = rhs_r - f_r y_{r-1} on rows lo..hi-1 (the carry into row lo
+// is exact).  The carry into row q depends on the one W rows earlier through the
+// product f_{q-W} ... f_{q-1}; the window stops growing once it reaches row lo or
+// that product is below tol.
+int forward_reach(const std::vector<double> &f, int lo, int hi, double tol)
+{
+    int R = 0;
+    for (int q = lo + 1; q < hi; ++q) {
+        double prod = 1.0;
+        int W = 0;
+        while (q - W > lo && std::fabs(prod) > tol) { prod *= f[q - 1 - W]; ++W; }
+        R = std::max(R, W);
+    }
+    return R;
+}
+
+// Back substitution: w_r = (y_r - g_r w_{r+1}) / d_r on rows lo..hi-1 (the carry
+// into row hi-1 is the exact closing-row value).
+int backward_reach(const std::vector<double> &g, int lo, int hi, double tol)
+{
+    int R = 0;
+    for (int r = lo; r + 1 < hi; ++r) {
+        double prod = 1.0;
+        int W = 0;
+        while (r + W + 1 < hi && std::fabs(prod) > tol) { prod *= g[r + 1 + W]; ++W; }
+        R = std::max(R, W);
+    }
+    return R;
+}
+
 }  // namespace
 
 std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_mode)
@@ -209,6 +240,21 @@ std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_m
             ax.m2c[e] = mi;
             ax.invd2c[e] = 1.0 / (2.0 - mi * supprev);
         }
+    }
+    // ---- carry reach over the three systems, both sweeps ---------------------
+    std::vector<double> g1(n), gT(n), g2(n);
+    for (int i = 0; i < n; ++i) {
+        g1[i] = ax.sup[i] * ax.invd[i];
+        gT[i] = ax.supT[i] * ax.invdT[i];
+        g2[i] = ax.sup2[i] * ax.invd2[i];
+    }
+    ax.reach = 1;
+    for (int l = 0; l < ax.p; ++l) {
+        int s = l * M, e = std::min(s + M, N);
+        for (const std::vector<double> *f : {&ax.m, &ax.mT, &ax.m2})
+            ax.reach = std::max(ax.reach, forward_reach(*f, s, e, kReachTol));
+        for (const std::vector<double> *g : {&g1, &gT, &g2})
+            ax.reach = std::max(ax.reach, backward_reach(*g, s, e, kReachTol));
     }
     return std::string();
 }
