@@ -97,6 +97,28 @@ def cpu_baseline(w, nsteps):
                       "Strang, OpenMP over lines), %.1f s wall" % (nsteps, el)}
 
 
+def measured_traffic(workload_key, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary of this
+    workload (profiles/line_kernels_<key>.md, FETCH_SIZE and WRITE_SIZE passes scaled by
+    a 1 GiB copy), or None when the summary was taken on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "line_kernels_%s.md" % workload_key)
+    src = os.path.join(ROOT, "paper_2301_05127_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for line in open(path):
+        if line.startswith("bench-traffic "):
+            _, h, js = line.split(" ", 2)
+            if h == sha:
+                return json.loads(js).get(kernel)
+    return None
+
+
+PROFILE_KEYS = {"cfg1": "acoustic_129x129", "cfg2": "acoustic_2049x2049", "cfg3": "elastic_257cube_2shots",
+                "cfg4": "elastic_513cube", "cfg5": "acoustic_1025x1025_64shots"}
+
+
 def gradient_ratio(sim, w, S, nsteps, t_fwd):
     """Time forward-with-checkpoints + adjoint over the same steps as the plain forward
     (t_fwd); the residual is the recorded traces themselves (J = sum d^2 / 2)."""
@@ -176,9 +198,10 @@ def main():
         bytes_per_launch = algo[dom[0]] * nodes * S
         avg_s = dom[1] / dom[2] / 1e3
         ach = bytes_per_launch / avg_s / 1e9
+        tr = measured_traffic(PROFILE_KEYS[a.workload], dom[0]) if S == len(w["shots"]) else None
         roof = {"bound": "hbm", "kernel": dom[0], "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_node": algo[dom[0]]}
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
+                "bytes_per_node": round(algo[dom[0]], 3), "algorithmic_bytes": round(bytes_per_launch)}
     for n, d in kernels.items():
         if n in algo:
             d["algo_GBs"] = round(algo[n] * nodes * S / (d["avg_us"] * 1e-6) / 1e9, 1)
