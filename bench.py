@@ -38,6 +38,7 @@ ALGO_BYTES = {
         "stress_line_z": 20,     # read v3, T, sigma, K; write sigma
         "velocity_line_x": 16,   # read sigma, v1, b; write v1
         "velocity_line_z": 16,   # read sigma, v3, b; write v3
+        "velocity_stress_x": 20,  # read sigma, v1, b; write v1 and T = d(v1 new)/dx
     },
     1: {  # elastic, per axis: one normal-stress pass (read v_i, 3 sigma, lambda, lambda+2mu;
           # write 3 sigma: 36 B) and two shear passes (read v, sigma_ij, mu; write sigma_ij:

@@ -88,6 +88,10 @@ typedef int32_t loss_status;
 
 /* desc.flags */
 #define LOSS_FLAG_NO_GRAPH 1   /* launch every step eagerly instead of replaying a hipGraph */
+#define LOSS_FLAG_NO_FUSE_X 2  /* acoustic: keep the x velocity pass and the next step's x
+                                  stress pass in separate kernels (by default one kernel
+                                  runs both when a whole x line fits one workgroup and
+                                  there are no body forces or velocity receivers) */
 
 typedef struct {
     int32_t physics;      /* LOSS_ACOUSTIC (ndim 2) or LOSS_ELASTIC (ndim 3) */

@@ -102,19 +102,24 @@ __device__ __forceinline__ bool segment_has_source(const LineArgs &a, int shot, 
     return false;
 }
 
+// Epilogue of one node; returns the value written to out[0].
 template <int EPI>
-__device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float D,
-                                         int x, int y, int z, bool srcs = true)
+__device__ __forceinline__ float epilogue(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float D,
+                                          int x, int y, int z, bool srcs = true)
 {
     if constexpr (EPI == EPI_STORE) {
         a.out[0][oidx] = D;
+        return D;
     } else if constexpr (EPI == EPI_AXPY) {
+        float v0 = 0.f;
         for (int j = 0; j < a.nout; ++j) {
             const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
             float v = fmaf(a.alpha * c, D, a.out[j][oidx]);
             if (srcs && a.src) v += source_terms(a, j, shot, x, y, z, midx);
             a.out[j][oidx] = v;
+            if (j == 0) v0 = v;
         }
+        return v0;
     } else if constexpr (EPI == EPI_AXPY_AUX) {
         const float dv = D + a.aux[oidx];
         const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
@@ -122,9 +127,12 @@ __device__ __forceinline__ void epilogue(const LineArgs &a, int64_t oidx, int64_
         if (srcs && a.src) v += source_terms(a, 0, shot, x, y, z, midx);
         a.out[0][oidx] = v;
         if (a.div) a.div[(int64_t)shot * a.div_shot_stride + midx] = dv;
+        return v;
     } else {  // EPI_BASE
         const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
-        a.out[0][oidx] = fmaf(a.alpha * c, D, a.aux[oidx]);
+        const float v = fmaf(a.alpha * c, D, a.aux[oidx]);
+        a.out[0][oidx] = v;
+        return v;
     }
 }
 
@@ -143,30 +151,36 @@ __device__ __forceinline__ Pre pre_load(const LineArgs &a, int64_t oidx, int64_t
     return r;
 }
 
-// Epilogue with out0 / coef0 / aux taken from `pr` (outputs j >= 1 are read here).
+// Epilogue with out0 / coef0 / aux taken from `pr` (outputs j >= 1 are read here);
+// returns the value written to out[0].
 template <int EPI>
-__device__ __forceinline__ void epilogue_pre(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float D,
-                                             const Pre &pr, int x, int y, int z, bool srcs)
+__device__ __forceinline__ float epilogue_pre(const LineArgs &a, int64_t oidx, int64_t midx, int shot, float D,
+                                              const Pre &pr, int x, int y, int z, bool srcs)
 {
-    if (srcs) {
-        epilogue<EPI>(a, oidx, midx, shot, D, x, y, z);
-        return;
-    }
-    if constexpr (EPI == EPI_STORE) {
-        a.out[0][oidx] = D;
-    } else if constexpr (EPI == EPI_AXPY) {
-        a.out[0][oidx] = fmaf(a.alpha * pr.c, D, pr.o);
+    if (srcs) return epilogue<EPI>(a, oidx, midx, shot, D, x, y, z);
+    float v = D;
+    if constexpr (EPI == EPI_AXPY) {
+        v = fmaf(a.alpha * pr.c, D, pr.o);
         for (int j = 1; j < a.nout; ++j) {
             const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
             a.out[j][oidx] = fmaf(a.alpha * c, D, a.out[j][oidx]);
         }
     } else if constexpr (EPI == EPI_AXPY_AUX) {
         const float dv = D + pr.x;
-        a.out[0][oidx] = fmaf(a.alpha * pr.c, dv, pr.o);
+        v = fmaf(a.alpha * pr.c, dv, pr.o);
         if (a.div) a.div[(int64_t)shot * a.div_shot_stride + midx] = dv;
-    } else {
-        a.out[0][oidx] = fmaf(a.alpha * pr.c, D, pr.x);
+    } else if constexpr (EPI == EPI_BASE) {
+        v = fmaf(a.alpha * pr.c, D, pr.x);
     }
+    a.out[0][oidx] = v;
+    return v;
+}
+
+// Trace samples of the receivers at row `r` of a strided column ({first, count} in ri).
+__device__ __forceinline__ void record_row(const LineArgs &a, const int4 &ri, int r, float v, int64_t n)
+{
+    for (int k = ri.x; k < ri.x + ri.y; ++k)
+        if (a.rrow[k] == r) a.traces[a.rtoff[k] + n] = (double)v;
 }
 
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
@@ -333,50 +347,37 @@ __device__ __forceinline__ float interior_rhs(const AxisDev &ax, float um, float
 // ---------------------------------------------------------------------------
 // x axis (contiguous): G lanes per unit, C nodes per lane, 64/G units per wave.
 // ---------------------------------------------------------------------------
-template <int C, int SOLVE, int EPI>
-__global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
+
+// Solve of one unit (patch l) of an x line by its G lanes (lane k owns nodes
+// q = s + kC .. q + C - 1).  `val(i)` reads node i of the line and `val4(i)` nodes
+// i..i+3 (i 16-byte aligned, i + 3 <= N; used when `vec_in`).  `issue()` runs once
+// the unit's loads are issued (the caller's epilogue prefetch goes there).  On return
+// w[c] holds the derivative at node q + c for q + c < e; the function returns the
+// derivative at the closing row e (the same value in every lane of the unit).
+template <int C, int SOLVE, typename Val, typename Val4, typename Issue>
+__device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, bool vec_in, Val val, Val4 val4,
+                                        Issue issue, float (&w)[C])
 {
-    const AxisDev &ax = a.ax;
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int k = lane & (G - 1);
-    const int grp = lane / G;
-    const int upw = 64 / G;
-    int unit = (blockIdx.x * (blockDim.x >> 6) + wid) * upw + grp;
-    const bool uact = unit < nunits;
-    if (!uact) unit = nunits - 1;
-    const int N = ax.N, M = ax.M, p = ax.p;
-    const int line = unit / p;
-    const int l = unit - line * p;
-    const int lps = a.nz * a.ny;                 // lines per shot
-    const int shot = line / lps;
-    const int64_t base = (int64_t)line * a.pitch;
-    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
-    if (a.step_inc && blockIdx.x == 0 && threadIdx.x == 0) *a.step_inc += 1;
+    const int N = ax.N, M = ax.M;
     const int s = l * M;
     const int e = min(s + M, N);
     const int q = s + k * C;
-    const float *__restrict__ in = a.in;
 
     // ---- loads -------------------------------------------------------------
-    // chunk values u[1..C] = nodes q..q+C-1 (16-byte loads when aligned and inside
-    // the line); u[0], u[C+1] = the neighbouring lanes' edge nodes
+    // chunk values u[1..C] = nodes q..q+C-1; u[0], u[C+1] = the neighbouring lanes'
+    // edge nodes
     float u[C + 2];
-    if (!a.in_coef && ((q & 3) == 0) && q + C - 1 <= N) {
+    if (vec_in && ((q & 3) == 0) && q + C - 1 <= N) {
 #pragma unroll
         for (int g4 = 0; g4 < C / 4; ++g4) {
-            const float4 v = ld4(in + base + q + 4 * g4);
+            const float4 v = val4(q + 4 * g4);
             u[1 + 4 * g4] = v.x; u[2 + 4 * g4] = v.y; u[3 + 4 * g4] = v.z; u[4 + 4 * g4] = v.w;
         }
     } else {
 #pragma unroll
-        for (int c = 1; c <= C; ++c) {
-            const int i = min(q - 1 + c, N);
-            u[c] = load_in(a, base + i, mbase + i);
-        }
+        for (int c = 1; c <= C; ++c) u[c] = val(min(q - 1 + c, N));
     }
-    const int ir = min(q + C, N);
-    const float uright = load_in(a, base + ir, mbase + ir);   // kept by the unit's last lane
+    const float uright = val(min(q + C, N));   // kept by the unit's last lane
     float fm[C], fi[C], fs[C];
     row_factors<C, SOLVE>(ax, q, fm, fi, fs);
     const EndRows er = end_rows<SOLVE>(ax, s, e);
@@ -392,26 +393,12 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
                 const int t = min(k + h * G, nt - 1);
                 tcs[h] = ax.tap_c[max(ss, 0) * nt + t];
                 tce[h] = ax.tap_c[max(se, 0) * nt + t];
-                tvs[h] = in[base + tap_node(ax, s, t)];
-                tve[h] = in[base + tap_node(ax, e, t)];
+                tvs[h] = val(tap_node(ax, s, t));
+                tve[h] = val(tap_node(ax, e, t));
             }
         }
     }
-    // epilogue operands of the aligned whole-chunk case
-    const bool vec = ((q & 3) == 0) && q + C <= e;
-    Pre4 pre[C / 4];
-    if (vec) {
-#pragma unroll
-        for (int g4 = 0; g4 < C / 4; ++g4) pre[g4] = pre_load4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4);
-    }
-    int rowz = 0, rowy = 0;                       // coordinates, only for source terms
-    bool srcs = false;
-    if (a.src) {
-        const int r = line - shot * lps;
-        rowz = r / a.ny;
-        rowy = r - rowz * a.ny;
-        srcs = segment_has_source(a, shot, 0, 0, rowy, rowz, q, min(q + C, N));
-    }
+    issue();
     float phs = 0.f, phe = 0.f;
     if constexpr (SOLVE != SOLVE_T1) {
 #pragma unroll
@@ -421,8 +408,8 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
             if (se >= 0 && ok) phe = fmaf(tce[h], tve[h], phe);
         }
         for (int t = k + 2 * G; t < nt; t += G) {   // halos wider than two taps per lane
-            if (ss >= 0) phs = fmaf(ax.tap_c[ss * nt + t], in[base + tap_node(ax, s, t)], phs);
-            if (se >= 0) phe = fmaf(ax.tap_c[se * nt + t], in[base + tap_node(ax, e, t)], phe);
+            if (ss >= 0) phs = fmaf(ax.tap_c[ss * nt + t], val(tap_node(ax, s, t)), phs);
+            if (se >= 0) phe = fmaf(ax.tap_c[se * nt + t], val(tap_node(ax, e, t)), phe);
         }
     }
 
@@ -481,7 +468,7 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
     we = __shfl(we, kc, G);
 
     // back substitution
-    float w[C], Q[C];
+    float Q[C];
     float wv = 0.f, qv = 1.f;
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
@@ -502,10 +489,60 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
     // lanes past the closing row hold identity maps, so the closing value enters
     // exactly where the window reaches it (elsewhere its factor is below the tolerance)
     const float wr = fmaf(Qx, we, Wx);
+#pragma unroll
+    for (int c = 0; c < C; ++c) w[c] = fmaf(Q[c], wr, w[c]);
+    return we;
+}
+
+template <int C, int SOLVE, int EPI>
+__global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
+{
+    const AxisDev &ax = a.ax;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const int k = lane & (G - 1);
+    const int grp = lane / G;
+    const int upw = 64 / G;
+    int unit = (blockIdx.x * (blockDim.x >> 6) + wid) * upw + grp;
+    const bool uact = unit < nunits;
+    if (!uact) unit = nunits - 1;
+    const int N = ax.N, M = ax.M, p = ax.p;
+    const int line = unit / p;
+    const int l = unit - line * p;
+    const int lps = a.nz * a.ny;                 // lines per shot
+    const int shot = line / lps;
+    const int64_t base = (int64_t)line * a.pitch;
+    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
+    if (a.step_inc && blockIdx.x == 0 && threadIdx.x == 0) *a.step_inc += 1;
+    const int s = l * M;
+    const int e = min(s + M, N);
+    const int q = s + k * C;
+    const float *__restrict__ in = a.in + base;
+
+    // epilogue operands of the aligned whole-chunk case, source flag
+    const bool vec = ((q & 3) == 0) && q + C <= e;
+    Pre4 pre[C / 4];
+    int rowz = 0, rowy = 0;                       // coordinates, only for source terms
+    bool srcs = false;
+    auto issue = [&]() {
+        if (vec) {
+#pragma unroll
+            for (int g4 = 0; g4 < C / 4; ++g4) pre[g4] = pre_load4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4);
+        }
+        if (a.src) {
+            const int r = line - shot * lps;
+            rowz = r / a.ny;
+            rowy = r - rowz * a.ny;
+            srcs = segment_has_source(a, shot, 0, 0, rowy, rowz, q, min(q + C, N));
+        }
+    };
+    float w[C];
+    const float we = x_unit<C, SOLVE>(
+        ax, k, G, l, a.in_coef == nullptr,
+        [&](int i) { return a.in_coef ? in[i] * a.in_coef[mbase + i] : in[i]; },
+        [&](int i) { return ld4(in + i); }, issue, w);
 
     if (uact) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) w[c] = fmaf(Q[c], wr, w[c]);
         if (vec) {
 #pragma unroll
             for (int g4 = 0; g4 < C / 4; ++g4)
@@ -519,7 +556,97 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
                 if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, w[c], i, rowy, rowz, srcs);
             }
         }
+        const int kc = (e - 1 - s) / C;
         if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we, N, rowy, rowz, srcs);
+    }
+}
+
+// Velocity pass along x of one step fused with the stress pass along x of the next
+// (acoustic, no body forces): v1 += alpha * coef0 * d(in)/dx, then Tout = d v1/dx of
+// the updated v1.  One block holds every patch of one line (p*G lanes), so the
+// updated line stays in LDS between the two solves and the stress pass reads its
+// PMBC halos there.  Dynamic LDS: N + 1 floats.
+template <int C>
+__global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__ Tout, int G)
+{
+    extern __shared__ float4 lds4[];
+    float *line_s = reinterpret_cast<float *>(lds4);
+    const AxisDev &ax = a.ax;
+    const int N = ax.N, M = ax.M, p = ax.p;
+    const int k = threadIdx.x & (G - 1);
+    const int lraw = threadIdx.x / G;
+    const bool uact = lraw < p;
+    const int l = min(lraw, p - 1);
+    const int line = blockIdx.x;
+    const int lps = a.nz * a.ny;
+    const int shot = line / lps;
+    const int64_t base = (int64_t)line * a.pitch;
+    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
+    // the stress pass opens the next step (the velocity pass reads no step counter)
+    if (a.step_inc && blockIdx.x == 0 && threadIdx.x == 0) *a.step_inc += 1;
+    const int s = l * M;
+    const int e = min(s + M, N);
+    const int q = s + k * C;
+    const int kc = (e - 1 - s) / C;
+    const float *__restrict__ in = a.in + base;
+    float *__restrict__ v1 = a.out[0] + base;
+    const float *__restrict__ cf = a.coef[0] ? a.coef[0] + mbase : nullptr;
+
+    // ---- velocity pass -------------------------------------------------------
+    const bool vec = ((q & 3) == 0) && q + C <= e;
+    Pre4 pre[C / 4];
+    auto issue = [&]() {
+        if (vec) {
+#pragma unroll
+            for (int g4 = 0; g4 < C / 4; ++g4) pre[g4] = pre_load4<EPI_AXPY>(a, base + q + 4 * g4, mbase + q + 4 * g4);
+        }
+    };
+    float w[C];
+    float we = x_unit<C, SOLVE_D1>(
+        ax, k, G, l, true, [&](int i) { return in[i]; }, [&](int i) { return ld4(in + i); }, issue, w);
+    if (uact) {
+        if (vec) {
+#pragma unroll
+            for (int g4 = 0; g4 < C / 4; ++g4) {
+                const float4 v = fma4(a.alpha, pre[g4].c, make_float4(w[4 * g4], w[4 * g4 + 1], w[4 * g4 + 2],
+                                                                      w[4 * g4 + 3]), pre[g4].o);
+                st4(v1 + q + 4 * g4, v);
+                lds4[(q >> 2) + g4] = v;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int i = q + c;
+                if (i < e) {
+                    const float v = fmaf(a.alpha * (cf ? cf[i] : 1.f), w[c], v1[i]);
+                    v1[i] = v;
+                    line_s[i] = v;
+                }
+            }
+        }
+        if (e == N && k == kc) {
+            const float v = fmaf(a.alpha * (cf ? cf[N] : 1.f), we, v1[N]);
+            v1[N] = v;
+            line_s[N] = v;
+        }
+    }
+    __syncthreads();
+
+    // ---- stress pass: T = d v1 / dx from the line in LDS ------------------------
+    we = x_unit<C, SOLVE_D1>(
+        ax, k, G, l, true, [&](int i) { return line_s[i]; }, [&](int i) { return lds4[i >> 2]; }, [] {}, w);
+    if (uact) {
+        float *__restrict__ T = Tout + base;
+        if (vec) {
+#pragma unroll
+            for (int g4 = 0; g4 < C / 4; ++g4)
+                st4(T + q + 4 * g4, make_float4(w[4 * g4], w[4 * g4 + 1], w[4 * g4 + 2], w[4 * g4 + 3]));
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (q + c < e) T[q + c] = w[c];
+        }
+        if (e == N && k == kc) T[N] = we;
     }
 }
 
@@ -590,6 +717,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         const int off = mbase + clampi(q - 1 + c, 0, N) * stride;
         u[c] = a.in_coef ? in[off] * a.in_coef[off] : in[off];
     }
+    const int4 rinfo = (a.rcol && cact) ? a.rcol[fcol] : make_int4(0, 0, 0, -1);
     float fm[C], fi[C], fs[C];
     row_factors<C, SOLVE>(ax, q, fm, fi, fs);
     const EndRows er = end_rows<SOLVE>(ax, s, e);
@@ -700,23 +828,36 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
     if (cact) {
         const int cy = axis == 1 ? 0 : o, cz = axis == 1 ? o : 0;
         const bool srcs = a.src && segment_has_source(a, shot, axis, col, cy, cz, q, min(q + C, N));
+        // receivers of this column among the rows this lane updates: trace sample n
+        int64_t n = -1;
+        if (rinfo.y > 0 && rinfo.w >= q && rinfo.z < q + C) {
+            n = *a.d_step - 1;
+            if (n >= a.trace_len) n = -1;
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int i = q + c;
             if (i < e) {
                 const int off = mbase + i * stride;
                 const float D = fmaf(Q[c], wr, w[c]);
+                float v;
                 if constexpr (kPre)
-                    epilogue_pre<EPI>(a, sbase + off, off, shot, D, pre[c], col, axis == 1 ? i : cy,
-                                      axis == 1 ? cz : i, srcs);
+                    v = epilogue_pre<EPI>(a, sbase + off, off, shot, D, pre[c], col, axis == 1 ? i : cy,
+                                          axis == 1 ? cz : i, srcs);
                 else
-                    epilogue<EPI>(a, sbase + off, off, shot, D, col, axis == 1 ? i : cy, axis == 1 ? cz : i,
-                                  srcs);
+                    v = epilogue<EPI>(a, sbase + off, off, shot, D, col, axis == 1 ? i : cy, axis == 1 ? cz : i,
+                                      srcs);
+                if (n >= 0 && i >= rinfo.z && i <= rinfo.w) record_row(a, rinfo, i, v, n);
             }
         }
         if (e == N && chunk == kc) {
             const int off = mbase + N * stride;
-            epilogue<EPI>(a, sbase + off, off, shot, we, col, axis == 1 ? N : cy, axis == 1 ? cz : N, srcs);
+            const float v = epilogue<EPI>(a, sbase + off, off, shot, we, col, axis == 1 ? N : cy,
+                                          axis == 1 ? cz : N, srcs);
+            if (rinfo.y > 0 && rinfo.w == N) {
+                const int64_t nn = *a.d_step - 1;
+                if (nn >= 0 && nn < a.trace_len) record_row(a, rinfo, N, v, nn);
+            }
         }
     }
 }
@@ -926,6 +1067,16 @@ __global__ void k_nonfinite(const float *p, int64_t n, int *flag)
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// nodes per lane of the x kernels: the caller's choice if it fits 64 lanes per patch,
+// else the smallest that does (0 = none fits)
+int x_chunk(const LineArgs &a)
+{
+    int cx = a.cx;
+    if (cx != 4 && cx != 8 && cx != 16) cx = 4;
+    while (cx < 16 && cx * 64 < a.ax.M) cx *= 2;
+    return cx * 64 < a.ax.M ? 0 : cx;
+}
+
 template <int C, int SOLVE>
 hipError_t dispatch_x(int epi, const LineArgs &a, hipStream_t st)
 {
@@ -987,12 +1138,8 @@ hipError_t dispatch_solve(int axis, int epi, const LineArgs &a, hipStream_t st)
 {
     const int M = a.ax.M;
     if (axis == 0) {
-        // nodes per lane: the caller's choice if it fits 64 lanes per patch, else the
-        // smallest that does
-        int cx = a.cx;
-        if (cx != 4 && cx != 8 && cx != 16) cx = 4;
-        while (cx < 16 && cx * 64 < M) cx *= 2;
-        if (cx * 64 < M) return hipErrorInvalidValue;
+        const int cx = x_chunk(a);
+        if (!cx) return hipErrorInvalidValue;
         if (cx == 4) return dispatch_x<4, SOLVE>(epi, a, st);
         if (cx == 8) return dispatch_x<8, SOLVE>(epi, a, st);
         return dispatch_x<16, SOLVE>(epi, a, st);
@@ -1016,6 +1163,36 @@ hipError_t launch_line(int axis, int solve, int epi, const LineArgs &a, hipStrea
     case SOLVE_T1: return dispatch_solve<SOLVE_T1>(axis, epi, a, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+int line_xx_threads(const LineArgs &a)
+{
+    const int cx = x_chunk(a);
+    if (!cx) return 0;
+    int G = 1;
+    while (G * cx < a.ax.M) G <<= 1;
+    const int threads = (a.ax.p * G + 63) / 64 * 64;
+    const size_t shm = (size_t)(a.ax.N + 4) / 4 * 16;
+    if (threads > 512 || shm > 65536) return 0;
+    return threads;
+}
+
+hipError_t launch_line_xx(const LineArgs &a, float *Tout, hipStream_t st)
+{
+    const int threads = line_xx_threads(a);
+    if (!threads) return hipErrorInvalidValue;
+    const int cx = x_chunk(a);
+    int G = 1;
+    while (G * cx < a.ax.M) G <<= 1;
+    const size_t shm = (size_t)(a.ax.N + 4) / 4 * 16;
+    const int64_t lines = (int64_t)a.S * a.nz * a.ny;
+    if (lines >= (1ll << 31)) return hipErrorInvalidValue;
+    switch (cx) {
+    case 4: hipLaunchKernelGGL(k_line_xx<4>, (unsigned)lines, threads, shm, st, a, Tout, G); break;
+    case 8: hipLaunchKernelGGL(k_line_xx<8>, (unsigned)lines, threads, shm, st, a, Tout, G); break;
+    default: hipLaunchKernelGGL(k_line_xx<16>, (unsigned)lines, threads, shm, st, a, Tout, G); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st)

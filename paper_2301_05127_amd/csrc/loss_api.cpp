@@ -46,12 +46,12 @@ struct RecHost {
 // Kernel classes reported by loss_kernel_timing.
 enum KClass {
     KC_STRESS_X, KC_STRESS_Y, KC_STRESS_Z, KC_VEL_X, KC_VEL_Y, KC_VEL_Z, KC_SOURCE, KC_RECEIVER,
-    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_COUNT
+    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_VEL_STRESS_X, KC_COUNT
 };
 const char *kKClassName[KC_COUNT] = {
     "stress_line_x", "stress_line_y", "stress_line_z", "velocity_line_x", "velocity_line_y",
     "velocity_line_z", "source_inject", "receiver_record", "step_advance", "adjoint_line_solve",
-    "adjoint_gather", "gradient_accumulate"};
+    "adjoint_gather", "gradient_accumulate", "velocity_stress_x"};
 
 }  // namespace
 
@@ -106,9 +106,11 @@ struct loss_sim {
     double kms[KC_COUNT] = {0};
     int64_t kcount[KC_COUNT] = {0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    // side stream for receiver recording that overlaps the velocity pass
-    hipStream_t st2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // acoustic pressure receivers recorded by the z stress kernel: per flattened z
+    // column {first, count, min row, max row}, then rows and trace offsets
+    int4 *d_rcol = nullptr;
+    int *d_rrow = nullptr;
+    int64_t *d_rtoff = nullptr;
     // adjoint
     float *ckpt = nullptr;         // [nseg][3 fields][S][shot_stride] fused states
     int64_t ck_every = 0, ck_steps = 0, ck_nseg = 0;
@@ -258,17 +260,15 @@ loss_status inject(loss_sim *s, float **fields_dev, int time_offset, float scale
     return timed_end(s, KC_SOURCE);
 }
 
-// record one or two receiver lists into trace sample (*d_step - 1) (inside a step),
-// on stream `st` (default: the simulation stream)
+// record one or two receiver lists into trace sample (*d_step - 1) (inside a step)
 loss_status record(loss_sim *s, const RecDev *rec0, int nrec0, float w0, int acc0,
-                   const RecDev *rec1 = nullptr, int nrec1 = 0, float w1 = 0.f, int acc1 = 0,
-                   hipStream_t st = nullptr)
+                   const RecDev *rec1 = nullptr, int nrec1 = 0, float w1 = 0.f, int acc1 = 0)
 {
     if (nrec0 + nrec1 == 0 || s->d.trace_len == 0) return LOSS_OK;
     loss_status r = timed_begin(s);
     if (r) return r;
     hipError_t e = launch_record2(rec0, nrec0, w0, acc0, rec1, nrec1, w1, acc1, s->d_fields, s->shot_stride,
-                                  s->traces, s->d_step, -1, s->d.trace_len, st ? st : s->st);
+                                  s->traces, s->d_step, -1, s->d.trace_len, s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("record: ") + hipGetErrorString(e));
     return timed_end(s, KC_RECEIVER);
 }
@@ -325,6 +325,81 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
     return LOSS_OK;
 }
 
+// ---- acoustic passes -----------------------------------------------------------
+// T = d v1/dx into tmp[0]
+loss_status acoustic_stress_x(loss_sim *s)
+{
+    LineArgs a = base_args(s, 0);
+    a.in = s->f[LOSS_F_V1];
+    a.out[0] = s->tmp[0];
+    return run_line(s, KC_STRESS_X, 0, SOLVE_D1, EPI_STORE, a);
+}
+
+// sigma -= dt K (T + d v3/dz) (+ pressure sources); optional store of T + d v3/dz
+loss_status acoustic_stress_z(loss_sim *s, float *div_store, int64_t div_shot_stride)
+{
+    LineArgs c = base_args(s, 2);
+    c.in = s->f[LOSS_F_V3];
+    c.out[0] = s->f[LOSS_F_SIGMA];
+    c.coef[0] = s->med[0];
+    c.aux = s->tmp[0];
+    c.alpha = -1.f;
+    c.div = div_store;
+    c.div_shot_stride = div_shot_stride;
+    const int fid = LOSS_F_SIGMA;
+    attach_sources(s, c, -1, &fid, 1, false);
+    if (s->d_rcol && s->d.trace_len > 0) {
+        c.rcol = s->d_rcol;
+        c.rrow = s->d_rrow;
+        c.rtoff = s->d_rtoff;
+        c.traces = s->traces;
+        c.trace_len = s->d.trace_len;
+    }
+    return run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_AXPY_AUX, c);
+}
+
+// full velocity pass of component c (0: v1 along x, 1: v3 along z), no forces
+loss_status acoustic_velocity(loss_sim *s, int c)
+{
+    const int axis = c == 0 ? 0 : 2;
+    LineArgs a = base_args(s, axis);
+    a.in = s->f[LOSS_F_SIGMA];
+    a.alpha = -1.f;
+    a.out[0] = s->f[c == 0 ? LOSS_F_V1 : LOSS_F_V3];
+    a.coef[0] = s->med.back();
+    return run_line(s, c == 0 ? KC_VEL_X : KC_VEL_Z, axis, SOLVE_D1, EPI_AXPY, a);
+}
+
+// velocity pass along x of this step fused with the stress pass along x of the next
+// one (which it opens: it advances the step counter)
+loss_status acoustic_velocity_stress_x(loss_sim *s)
+{
+    LineArgs a = base_args(s, 0);
+    a.in = s->f[LOSS_F_SIGMA];
+    a.alpha = -1.f;
+    a.out[0] = s->f[LOSS_F_V1];
+    a.coef[0] = s->med.back();
+    a.step_inc = s->d_step;
+    s->pending_inc = false;
+    loss_status r = timed_begin(s);
+    if (r) return r;
+    hipError_t e = launch_line_xx(a, s->tmp[0], s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("fused x kernel launch: ") + hipGetErrorString(e));
+    return timed_end(s, KC_VEL_STRESS_X);
+}
+
+// The fused x schedule applies: acoustic, no body forces (the fused kernel's velocity
+// half must not read the step counter it advances), no velocity receivers, a whole x
+// line fits one block.
+bool fused_x_ok(loss_sim *s)
+{
+    if (s->d.physics != LOSS_ACOUSTIC || s->nrec_vel > 0 || (s->d.flags & LOSS_FLAG_NO_FUSE_X)) return false;
+    for (const auto &shot : s->src)
+        for (const SrcHost &h : shot)
+            if (h.kind >= LOSS_SRC_FORCE_X) return false;
+    return line_xx_threads(base_args(s, 0)) > 0;
+}
+
 // ---- stress sub-flow (B) over dt with the velocity frozen --------------------
 loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
 {
@@ -332,22 +407,8 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
     loss_status r;
     if (s->d.physics == LOSS_ACOUSTIC) {
         // T = d v1/dx ; sigma -= dt K (T + d v3/dz)
-        LineArgs a = base_args(s, 0);
-        a.in = s->f[LOSS_F_V1];
-        a.out[0] = s->tmp[0];
-        r = run_line(s, KC_STRESS_X, 0, SOLVE_D1, EPI_STORE, a);
-        if (r) return r;
-        LineArgs c = base_args(s, 2);
-        c.in = s->f[LOSS_F_V3];
-        c.out[0] = s->f[LOSS_F_SIGMA];
-        c.coef[0] = s->med[0];
-        c.aux = s->tmp[0];
-        c.alpha = -1.f;
-        c.div = div_store;
-        c.div_shot_stride = div_shot_stride;
-        const int fid = LOSS_F_SIGMA;
-        attach_sources(s, c, -1, &fid, 1, false);
-        return run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_AXPY_AUX, c);
+        if ((r = acoustic_stress_x(s))) return r;
+        return acoustic_stress_z(s, div_store, div_shot_stride);
     }
     float *const *F = s->f.data();
     const float *lam = s->med[0], *mu = s->med[1], *l2m = s->med[2];
@@ -493,6 +554,9 @@ loss_status upload_receivers(loss_sim *s)
     }
     if (s->d_rec_vel) { s->release(s->d_rec_vel); s->d_rec_vel = nullptr; }
     if (s->d_rec_str) { s->release(s->d_rec_str); s->d_rec_str = nullptr; }
+    if (s->d_rcol) { s->release(s->d_rcol); s->d_rcol = nullptr; }
+    if (s->d_rrow) { s->release(s->d_rrow); s->d_rrow = nullptr; }
+    if (s->d_rtoff) { s->release(s->d_rtoff); s->d_rtoff = nullptr; }
     if (s->traces) { s->release(s->traces); s->traces = nullptr; }
     loss_status r;
     s->nrec_vel = (int)vel.size();
@@ -504,6 +568,32 @@ loss_status upload_receivers(loss_sim *s)
     if (s->nrec_str) {
         if ((r = s->alloc(&s->d_rec_str, str.size()))) return r;
         HIPCHK(hipMemcpy(s->d_rec_str, str.data(), str.size() * sizeof(RecDev), hipMemcpyHostToDevice));
+    }
+    // acoustic: the pressure receivers go to the z stress kernel, keyed by the
+    // flattened z column (shot, y, x) of that kernel
+    if (s->d.physics == LOSS_ACOUSTIC && !str.empty()) {
+        const int64_t ncol = (int64_t)s->S * s->ny * s->pitch;
+        std::vector<std::vector<std::pair<int, int64_t>>> bycol(ncol);
+        for (const RecDev &d : str) {
+            const int64_t z = d.node / s->plane, rem = d.node - z * s->plane;
+            bycol[(int64_t)d.shot * s->ny * s->pitch + rem].push_back({(int)z, d.trace_off});
+        }
+        std::vector<int4> rcol(ncol, make_int4(0, 0, 0, -1));
+        std::vector<int> rrow;
+        std::vector<int64_t> rtoff;
+        for (int64_t c = 0; c < ncol; ++c) {
+            auto &v = bycol[c];
+            if (v.empty()) continue;
+            std::sort(v.begin(), v.end());
+            rcol[c] = make_int4((int)rrow.size(), (int)v.size(), v.front().first, v.back().first);
+            for (const auto &p : v) { rrow.push_back(p.first); rtoff.push_back(p.second); }
+        }
+        if ((r = s->alloc(&s->d_rcol, rcol.size())) || (r = s->alloc(&s->d_rrow, rrow.size())) ||
+            (r = s->alloc(&s->d_rtoff, rtoff.size())))
+            return r;
+        HIPCHK(hipMemcpy(s->d_rcol, rcol.data(), rcol.size() * sizeof(int4), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s->d_rrow, rrow.data(), rrow.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s->d_rtoff, rtoff.data(), rtoff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     }
     s->trace_total = off;
     if ((r = s->alloc(&s->traces, std::max<int64_t>(off, 1)))) return r;
@@ -583,31 +673,52 @@ loss_status unfuse_in_place(loss_sim *s)
 // One fused step.  The first line kernel advances the step counter, so inside the
 // step *d_step = n + 1: stress sources use sample n (offset -1, added in the stress
 // epilogue), forces sample n + 1 (offset 0, velocity epilogue), traces slot n.
-//
-// Stress receivers read only sigma, which the velocity pass does not write: with no
-// velocity receivers (whose first half is read before the velocity pass) they are
-// recorded on the side stream while the velocity pass runs, joined before the step
-// ends (the next step advances the counter and rewrites sigma).
+// Acoustic pressure receivers are recorded by the z stress kernel itself.
 loss_status one_step(loss_sim *s, float *div_store, int64_t div_shot_stride)
 {
     loss_status r;
     s->pending_inc = true;
     if ((r = stress_stage(s, div_store, div_shot_stride))) return r;
-    const bool side = s->nrec_vel == 0 && s->nrec_str > 0 && s->d.trace_len > 0 && !s->timing;
-    if (side) {
-        HIPCHK(hipEventRecord(s->ev_fork, s->st));
-        HIPCHK(hipStreamWaitEvent(s->st2, s->ev_fork, 0));
-        if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0, nullptr, 0, 0.f, 0, s->st2))) return r;
-        HIPCHK(hipEventRecord(s->ev_join, s->st2));
-    } else if ((r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0, s->d_rec_vel, s->nrec_vel, 0.5f, 0))) {
-        return r;
-    }
+    // stress receivers not recorded by the stress kernel, and the first half of the
+    // velocity receivers
+    const int nstr = s->d_rcol ? 0 : s->nrec_str;
+    if ((r = record(s, s->d_rec_str, nstr, 1.0f, 0, s->d_rec_vel, s->nrec_vel, 0.5f, 0))) return r;
     std::vector<float *> vel;
     if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
     else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
     if ((r = velocity_stage(s, 1.0f, vel.data(), nullptr, true))) return r;
     if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 1))) return r;
-    if (side) HIPCHK(hipStreamWaitEvent(s->st, s->ev_join, 0));
+    return LOSS_OK;
+}
+
+// K acoustic steps with the x passes of consecutive steps fused (fused_x_ok):
+//   stress_x(1); for n = 1..K: stress_z(n) (records the pressure receivers), vel_z(n),
+//   then vel_x(n) + stress_x(n+1) fused (n < K) or vel_x(K).
+// Each step's first kernel advances the step counter (stress_x or the fused kernel).
+loss_status steps_fused_x(loss_sim *s, int64_t K)
+{
+    loss_status r;
+    s->pending_inc = true;
+    if ((r = acoustic_stress_x(s))) return r;
+    for (int64_t n = 0; n < K; ++n) {
+        if ((r = acoustic_stress_z(s, nullptr, 0))) return r;
+        if (!s->d_rcol && (r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0))) return r;
+        if ((r = acoustic_velocity(s, 1))) return r;
+        r = (n + 1 < K) ? acoustic_velocity_stress_x(s) : acoustic_velocity(s, 0);
+        if (r) return r;
+    }
+    return LOSS_OK;
+}
+
+// K steps on the stream, eagerly (no graph)
+loss_status steps_eager(loss_sim *s, int64_t K, float *div_store = nullptr, int64_t div_shot_stride = 0)
+{
+    loss_status r;
+    if (div_store == nullptr && K > 0 && fused_x_ok(s)) return steps_fused_x(s, K);
+    for (int64_t done = 0; done < K; ++done) {
+        float *ds = div_store ? div_store + done * s->S * div_shot_stride : nullptr;
+        if ((r = one_step(s, ds, div_shot_stride))) return r;
+    }
     return LOSS_OK;
 }
 
@@ -620,7 +731,7 @@ loss_status ensure_ready(loss_sim *s)
     return LOSS_OK;
 }
 
-constexpr int kGraphSteps = 10;
+constexpr int kGraphSteps = 32;
 
 loss_status build_graph(loss_sim *s)
 {
@@ -628,7 +739,7 @@ loss_status build_graph(loss_sim *s)
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
     loss_status r = LOSS_OK;
-    for (int i = 0; i < kGraphSteps && r == LOSS_OK; ++i) r = one_step(s, nullptr, 0);
+    r = steps_eager(s, kGraphSteps);
     hipError_t e = hipStreamEndCapture(s->st, &g);
     if (r) { if (g) (void)hipGraphDestroy(g); return r; }
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -653,10 +764,7 @@ loss_status run_steps(loss_sim *s, int64_t nsteps, float *div_store, int64_t div
             done += s->gsteps;
         }
     }
-    for (; done < nsteps; ++done) {
-        float *ds = div_store ? div_store + done * s->S * div_shot_stride : nullptr;
-        if ((r = one_step(s, ds, div_shot_stride))) return r;
-    }
+    if ((r = steps_eager(s, nsteps - done, div_store, div_shot_stride))) return r;
     s->step += nsteps;
     return LOSS_OK;
 }
@@ -843,10 +951,6 @@ loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out)
         return bail(fail(LOSS_EHIP, "pointer table upload"));
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
         return bail(fail(LOSS_EHIP, "hipEventCreate"));
-    if (hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess)
-        return bail(fail(LOSS_EHIP, "side stream"));
     s->src.assign(s->S, {});
     s->rec.assign(s->S, RecHost());
     // zero state (fill kernels, no memset nodes)
@@ -873,9 +977,6 @@ loss_status loss_destroy(loss_sim *s)
     s->allocs.clear();
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
-    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
-    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
-    if (s->st2) { (void)hipStreamSynchronize(s->st2); (void)hipStreamDestroy(s->st2); }
     if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
     delete s;
     return LOSS_OK;
@@ -1117,10 +1218,9 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
         for (const auto &cd : cands) {
             if (axis == 0) s->cx = cd.first;
             else { s->cw[axis] = cd.first; s->cs[axis] = cd.second; }
-            if ((r = one_step(s, nullptr, 0))) return r;   // warm this shape up
+            if ((r = steps_eager(s, 2))) return r;   // warm this shape up
             HIPCHK(hipEventRecord(s->ev0, s->st));
-            for (int k = 0; k < trial_steps; ++k)
-                if ((r = one_step(s, nullptr, 0))) return r;
+            if ((r = steps_eager(s, trial_steps))) return r;
             HIPCHK(hipEventRecord(s->ev1, s->st));
             HIPCHK(hipEventSynchronize(s->ev1));
             float ms = 0.f;

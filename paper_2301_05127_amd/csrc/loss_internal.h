@@ -124,11 +124,23 @@ struct LineArgs {
     int cw;                // strided kernels: columns per wave (16, 32, 64; 0 = automatic)
     int cx;                // x kernel: nodes per lane (4, 8, 16; 0 = automatic)
     int cs;                // y/z kernels: nodes per lane (8 or 16; 0 = automatic)
+    // receivers of out[0] recorded by the strided kernel as its update lands (trace
+    // sample *d_step - 1): per flattened column {first, count, min row, max row} into
+    // rrow / rtoff (row along the axis, trace offset), sorted by column
+    const int4 *rcol;
+    const int *rrow;
+    const int64_t *rtoff;
+    double *traces;
+    int64_t trace_len;
 };
 
 // Launch helpers (kernels.hip).  axis: 0 = x (contiguous), 1 = y, 2 = z.
 hipError_t launch_line(int axis, int solve, int epi, const LineArgs &a, hipStream_t st);
 hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st);
+// Fused x passes of the acoustic step (velocity along x, then T = d v1/dx of the
+// updated v1 into Tout): threads per block, 0 when a line does not fit one block.
+int line_xx_threads(const LineArgs &a);
+hipError_t launch_line_xx(const LineArgs &a, float *Tout, hipStream_t st);
 
 struct SrcDev {
     int shot, kind, field0, nfield;   // fields field0 .. field0+nfield-1 (consecutive ids)

@@ -21,6 +21,7 @@ F_SIGMA, F_V1, F_V3 = 0, 1, 2
 F_EV1, F_EV2, F_EV3, F_S11, F_S22, F_S33, F_S12, F_S13, F_S23 = range(9)
 SRC_PRESSURE, SRC_EXPLOSIVE, SRC_FORCE_X, SRC_FORCE_Y, SRC_FORCE_Z = range(5)
 FLAG_NO_GRAPH = 1
+FLAG_NO_FUSE_X = 2
 GRAD_K, GRAD_VP = 0, 1
 
 EXPORTS = [
