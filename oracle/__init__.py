@@ -46,6 +46,11 @@ class _Grid(ctypes.Structure):
                 ("M", ctypes.c_int * 3), ("halo", ctypes.c_int), ("end_mode", ctypes.c_int)]
 
 
+class _Pml(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("R", ctypes.c_double), ("kmax", ctypes.c_double),
+                ("f0", ctypes.c_double), ("cmax", ctypes.c_double)]
+
+
 class _Source(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("pos", ctypes.c_double * 3), ("spread", ctypes.c_double),
                 ("wavelet", ctypes.POINTER(ctypes.c_double)), ("nt", ctypes.c_int)]
@@ -76,6 +81,9 @@ def lib():
                                     c_int, D, D, D]),
             "or_acoustic_adjoint": (c_int, [G, c_double, c_int, D, D, c_int, S, c_int, I, D, D]),
             "or_num_fields": (c_int, [c_int]),
+            "or_pml_flow": (None, [c_double, c_double, c_double, c_double, c_double, c_double, D, D]),
+            "or_run_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, c_int, S, c_int,
+                                   I, D, D, D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -212,6 +220,36 @@ def run(g, physics, dt, nsteps, vp, rho, vs=None, sources=(), receivers=None, re
                            _dp(fin), _dp(fields), _dp(traces))
     if rc != 0:
         raise ValueError("oracle or_run_from rejected its arguments (rc=%d)" % rc)
+    return fields, traces
+
+
+def pml_flow(d, k, alpha, tau, D, psi):
+    """Exact flow of one ADE-PML memory variable and its field over tau with the
+    derivative D frozen (Sec. 3.3); returns (psi(tau), (v(tau) - v(0)) / b)."""
+    po, dv = ctypes.c_double(), ctypes.c_double()
+    lib().or_pml_flow(float(d), float(k), float(alpha), float(tau), float(D), float(psi),
+                      ctypes.byref(po), ctypes.byref(dv))
+    return po.value, dv.value
+
+
+def run_pml(g, pml, dt, nsteps, vp, rho, sources=(), receivers=None, fields_in=None, step0=0):
+    """Acoustic 2-D run with the ADE-PML layer (Sec. 3.3).  pml: dict(width, R, kmax, f0,
+    cmax).  Returns (fields (7, *shape): sigma, v1, v3, psi_x, psi_z, phi_x, phi_z,
+    traces (nrec, nsteps) of sigma)."""
+    shape = field_shape(g)
+    vp = _f64(vp)
+    rho = _f64(rho)
+    src, keep = _sources(list(sources))
+    rec = np.zeros((0, 3), dtype=np.int32) if receivers is None else np.ascontiguousarray(receivers, dtype=np.int32)
+    fields = np.zeros((7,) + shape)
+    traces = np.zeros((rec.shape[0], nsteps))
+    fin = _f64(fields_in) if fields_in is not None else None
+    p = _Pml(int(pml["width"]), float(pml["R"]), float(pml["kmax"]), float(pml["f0"]), float(pml["cmax"]))
+    gs = _grid(g)
+    rc = lib().or_run_pml(ctypes.byref(gs), ctypes.byref(p), float(dt), int(step0), int(nsteps), _dp(vp), _dp(rho),
+                          len(keep), src, rec.shape[0], _ip(rec), _dp(fin), _dp(fields), _dp(traces))
+    if rc != 0:
+        raise ValueError("oracle or_run_pml rejected its arguments (rc=%d)" % rc)
     return fields, traces
 
 

@@ -18,7 +18,9 @@
  *      (eq. derivative_approximation); the second derivative is the second
  *      difference of the coefficients divided by h^2 (second derivative of B_i);
  *   5. time: Strang splitting, half step of the velocity sub-flow, full step of the
- *      stress sub-flow, half step of the velocity sub-flow (Sec. 3.3, no PML).
+ *      stress sub-flow, half step of the velocity sub-flow (Sec. 3.3);
+ *   6. optional absorbing layer (acoustic 2-D): the ADE-PML memory variables, each
+ *      sub-flow solved exactly with the driving derivative frozen (Sec. 3.3).
  */
 #include "loss_oracle.h"
 
@@ -618,6 +620,158 @@ int or_run(const or_grid *g, int physics, double dt, int nsteps,
 {
     return or_run_from(g, physics, dt, 0, nsteps, vp, vs, rho, nsrc, src, nrec, rec_idx,
                        rec_comp, NULL, fields, traces);
+}
+
+/* ------------------------------------------------------------------------ */
+/* ADE-PML (Sec. 3.3)                                                        */
+/* ------------------------------------------------------------------------ */
+void or_pml_flow(double d, double k, double alpha, double tau, double D, double psi,
+                 double *psi_out, double *dv_over_b)
+{
+    /* With D frozen, psi' = -beta psi - (d/k^2) D (beta = d/k + alpha) has the exact
+     * solution psi(t) = e^{-beta t} psi0 - (d/k^2) t phi1(beta t) D, and
+     * int_0^tau psi = tau phi1(x) psi0 - (d/k^2) tau^2 phi2(x) D  (x = beta tau) with
+     * the exponential-integrator functions phi1(x) = (1 - e^{-x}) / x and
+     * phi2(x) = (x - 1 + e^{-x}) / x^2 (Taylor series near x = 0, where the closed
+     * forms cancel).  Then v(tau) - v(0) = -b (tau D / k + int psi). */
+    double beta = d / k + alpha, x = beta * tau, phi1, phi2;
+    if (fabs(x) < 1e-3) {
+        phi1 = 1.0 - x / 2.0 + x * x / 6.0 - x * x * x / 24.0 + x * x * x * x / 120.0;
+        phi2 = 0.5 - x / 6.0 + x * x / 24.0 - x * x * x / 120.0 + x * x * x * x / 720.0;
+    } else {
+        phi1 = -expm1(-x) / x;
+        phi2 = (x + expm1(-x)) / (x * x);
+    }
+    double dk2 = d / (k * k);
+    *psi_out = exp(-x) * psi - dk2 * tau * phi1 * D;
+    *dv_over_b = -(tau * D / k + tau * phi1 * psi - dk2 * tau * tau * phi2 * D);
+}
+
+/* depth fraction into the layer of node j of an axis with N intervals */
+static double pml_delta(int j, int N, int width)
+{
+    int dist = 0;
+    if (j < width) dist = width - j;
+    if (j > N - width && j - (N - width) > dist) dist = j - (N - width);
+    return (double)dist / (double)width;
+}
+
+int or_run_pml(const or_grid *g, const or_pml *pml, double dt, int step0, int nsteps,
+               const double *vp, const double *rho, int nsrc, const or_source *src,
+               int nrec, const int *rec_idx, const double *fields_in, double *fields, double *traces)
+{
+    stepper S;
+    long nn[3], tot, i;
+    int a, k, n, r;
+    const int nf = 7;
+    double *F, *K, *b, *dx, *dz, **W, *pd[3], *pk[3], *pa[3];
+    if (check_grid(g, OR_ACOUSTIC) || pml->width < 1 || pml->width > g->n[0] / 2 ||
+        pml->width > g->n[2] / 2 || !(pml->R > 0.0 && pml->R < 1.0) || pml->kmax < 1.0 || pml->f0 <= 0.0)
+        return -1;
+    grid_nodes(g, nn);
+    tot = grid_total(g);
+    S.g = g; S.tot = tot;
+    for (a = 0; a < 3; ++a) {
+        if (a == 1) { memset(&S.T[a], 0, sizeof(axis_tab)); continue; }
+        tab_for_axis(g, a, &S.T[a]);
+        S.c[a].T = &S.T[a];
+        S.c[a].order = 1;
+    }
+    /* profiles d, k, alpha per node of the x and z axes */
+    for (a = 0; a < 3; a += 2) {
+        int j, N = g->n[a];
+        double d0 = -3.0 * pml->cmax * log(pml->R) / (2.0 * pml->width * g->h[a]);
+        pd[a] = (double *)malloc(sizeof(double) * 3 * (N + 1));
+        pk[a] = pd[a] + N + 1;
+        pa[a] = pk[a] + N + 1;
+        for (j = 0; j <= N; ++j) {
+            double del = pml_delta(j, N, pml->width);
+            pd[a][j] = d0 * del * del;
+            pk[a][j] = 1.0 + (pml->kmax - 1.0) * del;
+            pa[a][j] = 3.14159265358979323846 * pml->f0 * (1.0 - del);
+        }
+    }
+    F = (double *)calloc((size_t)tot * (nf + 4), sizeof(double));
+    K = F + (size_t)tot * nf;
+    b = K + tot;
+    dx = b + tot;
+    dz = dx + tot;
+    if (fields_in) memcpy(F, fields_in, sizeof(double) * (size_t)tot * nf);
+    for (i = 0; i < tot; ++i) {
+        b[i] = 1.0 / rho[i];
+        K[i] = rho[i] * vp[i] * vp[i];
+    }
+    W = (double **)malloc(sizeof(double *) * (nsrc > 0 ? nsrc : 1));
+    for (k = 0; k < nsrc; ++k) {
+        W[k] = (double *)malloc(sizeof(double) * tot);
+        or_source_weights(g, src[k].pos, src[k].spread, W[k]);
+    }
+    double *sig = F, *v1 = F + tot, *v3 = F + 2 * tot;
+    double *psx = F + 3 * tot, *psz = F + 4 * tot, *phx = F + 5 * tot, *phz = F + 6 * tot;
+    for (n = 0; n < nsteps; ++n) {
+        long sn = (long)step0 + n;
+        int half;
+        for (half = 0; half < 3; ++half) {
+            if (half != 1) {
+                /* (A) over dt/2 with sigma frozen (eq. ADE_PML_A) */
+                long fk = half == 0 ? sn : sn + 1;
+                double tau = 0.5 * dt;
+                deriv_into(&S, 0, sig, dx);
+                deriv_into(&S, 2, sig, dz);
+                for (i = 0; i < tot; ++i) {
+                    int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
+                    double p1, dvb;
+                    or_pml_flow(pd[0][x], pk[0][x], pa[0][x], tau, dx[i], psx[i], &p1, &dvb);
+                    psx[i] = p1;
+                    v1[i] += b[i] * dvb;
+                    or_pml_flow(pd[2][z], pk[2][z], pa[2][z], tau, dz[i], psz[i], &p1, &dvb);
+                    psz[i] = p1;
+                    v3[i] += b[i] * dvb;
+                }
+                for (k = 0; k < nsrc; ++k) {
+                    int fld = src[k].kind == OR_SRC_FORCE_X ? OR_A_V1
+                            : src[k].kind == OR_SRC_FORCE_Z ? OR_A_V3 : -1;
+                    double s = sample(&src[k], fk);
+                    if (fld < 0) continue;
+                    for (i = 0; i < tot; ++i) F[fld * tot + i] += tau * b[i] * s * W[k][i];
+                }
+            } else {
+                /* (B) over dt with the velocities frozen (eq. ADE_PML_B): the same
+                 * exact flow, with K in place of b */
+                deriv_into(&S, 0, v1, dx);
+                deriv_into(&S, 2, v3, dz);
+                for (i = 0; i < tot; ++i) {
+                    int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
+                    double p1, dsk;
+                    or_pml_flow(pd[0][x], pk[0][x], pa[0][x], dt, dx[i], phx[i], &p1, &dsk);
+                    phx[i] = p1;
+                    sig[i] += K[i] * dsk;
+                    or_pml_flow(pd[2][z], pk[2][z], pa[2][z], dt, dz[i], phz[i], &p1, &dsk);
+                    phz[i] = p1;
+                    sig[i] += K[i] * dsk;
+                }
+                for (k = 0; k < nsrc; ++k) {
+                    double s = sample(&src[k], sn);
+                    if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                    for (i = 0; i < tot; ++i) sig[i] += dt * s * W[k][i];
+                }
+            }
+        }
+        if (traces)
+            for (r = 0; r < nrec; ++r) {
+                long ix = rec_idx[3 * r], iz = rec_idx[3 * r + 2];
+                traces[(size_t)r * nsteps + n] = sig[iz * nn[0] + ix];
+            }
+    }
+    if (fields) memcpy(fields, F, sizeof(double) * (size_t)tot * nf);
+    for (k = 0; k < nsrc; ++k) free(W[k]);
+    free(W);
+    free(F);
+    for (a = 0; a < 3; a += 2) {
+        free(pd[a]);
+        axis_tab_free(&S.T[a]);
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

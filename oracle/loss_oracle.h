@@ -111,6 +111,37 @@ int or_run_from(const or_grid *g, int physics, double dt, int step0, int nsteps,
                 int nrec, const int *rec_idx, int rec_comp,
                 const double *fields_in, double *fields, double *traces);
 
+/* ---- absorbing layer (paper, Sec. 3.3: ADE-PML with exponential splitting) -- */
+
+/* Layer of `width` nodes at both ends of every axis.  At a node whose distance into
+ * the layer is delta * width nodes (delta in (0, 1]; 0 outside the layer):
+ *   d = d0 delta^2, k = 1 + (kmax - 1) delta, alpha = amax (1 - delta),
+ *   d0 = -3 cmax ln(R) / (2 width h), amax = pi f0
+ * (reading of the profile formulas after eq. ADE_PML_1: the exponent m = p = 1 applies
+ * to delta, and L is the layer thickness in metres). */
+typedef struct {
+    int width;       /* nodes */
+    double R;        /* target reflection coefficient */
+    double kmax;     /* coordinate stretching at the outer edge */
+    double f0;       /* dominant source frequency [Hz] */
+    double cmax;     /* largest P velocity [m/s] */
+} or_pml;
+
+/* Exact flow over tau of one memory variable and its field with the driving
+ * derivative D frozen (the sub-flow solutions of Sec. 3.3):
+ *   psi' = -(d/k + alpha) psi - (d/k^2) D,   v' = -b (D/k + psi)
+ * psi_out = psi(tau); dv_over_b = (v(tau) - v(0)) / b. */
+void or_pml_flow(double d, double k, double alpha, double tau, double D, double psi,
+                 double *psi_out, double *dv_over_b);
+
+/* Acoustic 2-D run with the layer on both axes: like or_run_from, with the state
+ * extended by the memory variables, fields (7 x nodes) = sigma, v1, v3, psi_x, psi_z,
+ * phi_x, phi_z (psi: velocity sub-flow, phi: stress sub-flow; zero outside the layer).
+ * Receivers record sigma.  Returns 0 on success. */
+int or_run_pml(const or_grid *g, const or_pml *pml, double dt, int step0, int nsteps,
+               const double *vp, const double *rho, int nsrc, const or_source *src,
+               int nrec, const int *rec_idx, const double *fields_in, double *fields, double *traces);
+
 /* Gradient of J = 1/2 sum_n sum_r (trace - obs)^2 of one acoustic 2-D shot with
  * respect to the bulk modulus K = rho c^2 at every node, given the residual
  * res[r*nsteps+n] = trace - obs.  Exact transpose of the discrete canonical Strang

@@ -1,0 +1,101 @@
+"""Pins of the oracle's absorbing layer (ADE-PML, Sec. 3.3).
+
+* the exact sub-flow of a memory variable and its field (the closed form after
+  eq. ADE_PML_1 and the velocity formula that follows it) against a fine Runge-Kutta
+  integration of the two ODEs;
+* with no damping (R -> 1, kmax = 1) the layer leaves the textbook Strang scheme;
+* energy that leaves the physical region is absorbed (natural ends keep it);
+* the solution inside the physical region matches a run on a domain three times as
+  wide, whose ends are too far to reflect within the window.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_05127_amd import inputs
+
+
+def rk4_flow(d, k, alpha, tau, D, psi0, n=20000):
+    beta = d / k + alpha
+    f = lambda y: np.array([-beta * y[0] - d / (k * k) * D, -(D / k + y[0])])   # (psi, v / b)
+    y = np.array([psi0, 0.0])
+    h = tau / n
+    for _ in range(n):
+        k1 = f(y); k2 = f(y + 0.5 * h * k1); k3 = f(y + 0.5 * h * k2); k4 = f(y + h * k3)
+        y = y + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return y
+
+
+@pytest.mark.parametrize("d,k,alpha,tau,D,psi0", [
+    (186.0, 1.0, 47.0, 5e-4, 1.3, 0.2),
+    (50.0, 2.5, 10.0, 1e-3, -0.7, -0.05),
+    (186.0, 1.2, 5.0, -5e-4, 0.4, 0.3),      # backward flow (recovering the integer time)
+    (0.0, 1.0, 47.0, 1e-3, 2.0, 0.0),         # inner edge of the layer: plain update
+    (3000.0, 1.0, 0.0, 1e-3, 1.0, 0.5),       # stiff outer edge, x = beta tau = 3
+])
+def test_pml_flow_matches_ode_integration(d, k, alpha, tau, D, psi0):
+    psi, dv = oracle.pml_flow(d, k, alpha, tau, D, psi0)
+    ref = rk4_flow(d, k, alpha, tau, D, psi0)
+    assert abs(psi - ref[0]) <= 1e-12 * max(1.0, abs(ref[0]))
+    assert abs(dv - ref[1]) <= 1e-12 * max(1e-3, abs(ref[1]))
+
+
+def _setup(N, M, halo=8, centre=None):
+    g = inputs.grid(2, (N, 0, N), (10.0, 10.0, 10.0), (M, M, M), halo)
+    shape = (N + 1, N + 1)
+    vp = np.full(shape, 2000.0)
+    rho = np.full(shape, 1000.0)
+    c = centre if centre is not None else 5.0 * N
+    src = [inputs._src(0, (c, 0.0, c), 20.0, 15.0, 1.2 / 15.0, 1e-3, 1000)]
+    return g, vp, rho, src
+
+
+def test_pml_without_damping_is_the_plain_scheme():
+    g, vp, rho, src = _setup(64, 32)
+    pml = dict(width=12, R=1.0 - 1e-12, kmax=1.0, f0=15.0, cmax=2000.0)
+    fp, tp = oracle.run_pml(g, pml, 1e-3, 200, vp, rho, sources=src, receivers=[[20, 0, 30]])
+    fn, tn = oracle.run(g, 0, 1e-3, 200, vp, rho, sources=src, receivers=[[20, 0, 30]])
+    for f in range(3):
+        assert oracle.rel_l2(fp[f], fn[f]) < 1e-10
+    assert oracle.rel_l2(tp, tn) < 1e-10
+
+
+def _energy(F, vp, rho, W):
+    s = (slice(W, -W), slice(W, -W))
+    K = rho * vp * vp
+    return 0.5 * float(np.sum(F[0][s] ** 2 / K[s] + rho[s] * (F[1][s] ** 2 + F[2][s] ** 2)))
+
+
+def test_pml_absorbs_outgoing_energy():
+    g, vp, rho, src = _setup(64, 32)
+    W = 12
+    pml = dict(width=W, R=1e-6, kmax=1.0, f0=15.0, cmax=2000.0)
+    ep, en, fp, fn = [], [], None, None
+    for n0 in range(0, 500, 100):
+        fp, _ = oracle.run_pml(g, pml, 1e-3, 100, vp, rho, sources=src, fields_in=fp, step0=n0)
+        fn, _ = oracle.run(g, 0, 1e-3, 100, vp, rho, sources=src, fields_in=fn, step0=n0)
+        ep.append(_energy(fp, vp, rho, W))
+        en.append(_energy(fn, vp, rho, W))
+    # the pulse has left the physical region by step 500
+    assert ep[-1] < 1e-6 * max(ep)
+    assert en[-1] > 1e-2 * max(en)
+
+
+def test_pml_matches_wider_domain():
+    N, W, off = 64, 12, 64
+    g, vp, rho, src = _setup(N, 32)
+    g3, vp3, rho3, src3 = _setup(3 * N, 32, centre=5.0 * N + 10.0 * off)
+    pml = dict(width=W, R=1e-6, kmax=1.0, f0=15.0, cmax=2000.0)
+    phys = slice(W, N + 1 - W)
+    wide = slice(off + W, off + N + 1 - W)
+    scale = None
+    for ns in (100, 260):
+        fp, _ = oracle.run_pml(g, pml, 1e-3, ns, vp, rho, sources=src)
+        fw, _ = oracle.run(g3, 0, 1e-3, ns, vp3, rho3, sources=src3)
+        a, b = fp[0][phys, phys], fw[0][wide, wide]
+        if scale is None:
+            scale = np.linalg.norm(b)          # the pulse inside the physical region
+        err = np.linalg.norm(a - b) / scale
+        # 100: the pulse has not reached the layer; 260: it has crossed it (what is left
+        # inside the physical region is mostly reflection from the 12-node layer)
+        assert err < (1e-6 if ns == 100 else 2e-3), (ns, err)
