@@ -68,7 +68,7 @@ def parse():
     p.add_argument("--shape", default=None,
                    help="launch shape per axis 'x,y,z' (loss_set_shape encoding); skips autotuning")
     p.add_argument("--copy-probe", action="store_true",
-                   help="also run one 1 GiB device copy (HBM counter calibration)")
+                   help="accepted for compatibility: the 1 GiB copy probe always runs")
     return p.parse_args()
 
 
@@ -213,11 +213,19 @@ def main():
     if a.grad:
         grad = gradient_ratio(sim, w, S, a.steps, el)
 
-    if a.copy_probe:
-        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
+    # device-to-device copy of 1 GiB: the bandwidth a plain streaming kernel reaches here
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
         y.copy_(x)
-        torch.cuda.synchronize()
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 5 * 2 * x.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
 
     res = {
         "metric": "Mcell-updates/s",
@@ -236,7 +244,8 @@ def main():
                    "columns_per_wave": cw,
                    "hbm_effective_GBs": round(eff, 1),
                    "hbm_effective_frac": round(eff / HBM_PEAK_GBS, 4),
-                   "compulsory_bytes_per_cell_step": step_bytes, "finite": finite},
+                   "compulsory_bytes_per_cell_step": step_bytes, "finite": finite,
+                   "copy_1GiB_GBs": round(copy_gbs, 1)},
         "roofline": roof,
         "kernels": kernels,
     }

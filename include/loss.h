@@ -145,6 +145,21 @@ loss_status loss_add_receivers(loss_sim *sim, int32_t shot, int64_t nrec, const 
 /* Zero every wavefield, trace and the step counter (media and sources are kept). */
 loss_status loss_reset(loss_sim *sim);
 
+/* Absorbing layer (paper Sec. 3.3: ADE-PML with the exponential operator splitting),
+ * acoustic only: the outermost `width` nodes at both ends of x and z carry memory
+ * variables (psi for the velocity sub-flow, phi for the stress sub-flow) that damp
+ * outgoing waves.  At depth fraction delta in (0, 1] into the layer:
+ *   d = d0 delta^2, k = 1 + (kmax - 1) delta, alpha = pi f0 (1 - delta),
+ *   d0 = -3 cmax ln(reflection) / (2 width h), cmax = the largest velocity of the
+ * media set (call after loss_set_media; setting media again does not update d0).
+ * Each sub-flow is solved exactly with its driving derivative frozen.  width = 0
+ * removes the layer.  The memory variables start at zero (and return to zero on
+ * loss_reset); loss_forward_ckpt / loss_adjoint refuse a simulation with a layer
+ * (LOSS_EUNSUPPORTED).  Errors: LOSS_EINVAL (width < 0 or > n/2 on an axis,
+ * reflection outside (0, 1), kmax < 1, f0 <= 0), LOSS_EUNSUPPORTED (elastic),
+ * LOSS_ESTATE (no media yet). */
+loss_status loss_set_pml(loss_sim *sim, int32_t width, double reflection, double kmax, double f0);
+
 /* Advance all shots by nsteps Strang steps, asynchronously on the sim stream.
  * Per step: stress sub-flow B(dt) then the velocity sub-flow, the two velocity half
  * steps of consecutive steps fused into one (the state holds the velocity half a

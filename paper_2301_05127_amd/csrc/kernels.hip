@@ -332,6 +332,14 @@ __device__ __forceinline__ void row_factors(const AxisDev &ax, int q, float (&fm
     }
 }
 
+// Hides a value from common-subexpression elimination, so that an expression of it
+// is recomputed instead of being kept in a register (emits no instruction).
+__device__ __forceinline__ float opaque(float v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Right-hand side of a patch-interior row from the node values u_{i-1}, u_i, u_{i+1}.
 template <int SOLVE>
 __device__ __forceinline__ float interior_rhs(const AxisDev &ax, float um, float u0, float up)
@@ -342,6 +350,36 @@ __device__ __forceinline__ float interior_rhs(const AxisDev &ax, float um, float
         const float ih = 1.f / ax.h;
         return 6.f * ih * ih * (um - 2.f * u0 + up);
     }
+}
+
+// Absorbing layer (ADE-PML, Sec. 3.3, exponential splitting).  With the derivative D
+// of this pass frozen over tau, the memory variable psi of node j evolves exactly as
+//   psi(tau) = e^{-x} psi0 - (d/k^2) tau phi1(x) D          (x = beta tau)
+// and the field moves by -tau * coef * (D/k + phi1(x) psi0 - (d/k^2) tau phi2(x) D),
+// phi1(x) = (1 - e^{-x})/x, phi2(x) = (x - 1 + e^{-x})/x^2 (series near 0).  Returns that
+// effective derivative, so the epilogue keeps its plain form; stores psi(tau) if asked.
+__device__ __forceinline__ bool in_pml(const AxisDev &ax, int j)
+{
+    return j < ax.pml_w || j > ax.N - ax.pml_w;
+}
+
+__device__ __forceinline__ float pml_adjust(const AxisDev &ax, float *__restrict__ mem, float tau, int store,
+                                            int j, int64_t idx, float D)
+{
+    const float4 t = ax.pml[j];
+    const float x = t.x * tau;
+    float phi1, phi2;
+    if (fabsf(x) < 0.1f) {
+        phi1 = 1.f - x * (0.5f - x * (1.f / 6.f - x * (1.f / 24.f - x * (1.f / 120.f - x * (1.f / 720.f)))));
+        phi2 = 0.5f - x * (1.f / 6.f - x * (1.f / 24.f - x * (1.f / 120.f - x * (1.f / 720.f - x * (1.f / 5040.f)))));
+    } else {
+        const float em = expm1f(-x);
+        phi1 = -em / x;
+        phi2 = (x + em) / (x * x);
+    }
+    const float psi0 = mem[idx];
+    if (store) mem[idx] = fmaf(expf(-x), psi0, -t.y * tau * phi1 * D);
+    return fmaf(t.z - t.y * tau * phi2, D, phi1 * psi0);
 }
 
 // ---------------------------------------------------------------------------
@@ -537,12 +575,20 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
         }
     };
     float w[C];
-    const float we = x_unit<C, SOLVE>(
+    float we = x_unit<C, SOLVE>(
         ax, k, G, l, a.in_coef == nullptr,
         [&](int i) { return a.in_coef ? in[i] * a.in_coef[mbase + i] : in[i]; },
         [&](int i) { return ld4(in + i); }, issue, w);
 
     if (uact) {
+        const int kc = (e - 1 - s) / C;
+        if (a.pml_mem) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (q + c < e && in_pml(ax, q + c))
+                    w[c] = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, q + c, base + q + c, w[c]);
+            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, N, base + N, we);
+        }
         if (vec) {
 #pragma unroll
             for (int g4 = 0; g4 < C / 4; ++g4)
@@ -556,7 +602,6 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
                 if (i < e) epilogue<EPI>(a, base + i, mbase + i, shot, w[c], i, rowy, rowz, srcs);
             }
         }
-        const int kc = (e - 1 - s) / C;
         if (e == N && k == kc) epilogue<EPI>(a, base + N, mbase + N, shot, we, N, rowy, rowz, srcs);
     }
 }
@@ -567,7 +612,8 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
 // updated line stays in LDS between the two solves and the stress pass reads its
 // PMBC halos there.  Dynamic LDS: N + 1 floats.
 template <int C>
-__global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__ Tout, int G)
+__global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__ Tout, float *__restrict__ pml_t,
+                                                 int G)
 {
     extern __shared__ float4 lds4[];
     float *line_s = reinterpret_cast<float *>(lds4);
@@ -605,6 +651,13 @@ __global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__
     float we = x_unit<C, SOLVE_D1>(
         ax, k, G, l, true, [&](int i) { return in[i]; }, [&](int i) { return ld4(in + i); }, issue, w);
     if (uact) {
+        if (a.pml_mem) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (q + c < e && in_pml(ax, q + c))
+                    w[c] = pml_adjust(ax, a.pml_mem, a.pml_tau, 1, q + c, base + q + c, w[c]);
+            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(ax, a.pml_mem, a.pml_tau, 1, N, base + N, we);
+        }
         if (vec) {
 #pragma unroll
             for (int g4 = 0; g4 < C / 4; ++g4) {
@@ -637,6 +690,13 @@ __global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__
         ax, k, G, l, true, [&](int i) { return line_s[i]; }, [&](int i) { return lds4[i >> 2]; }, [] {}, w);
     if (uact) {
         float *__restrict__ T = Tout + base;
+        if (pml_t) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (q + c < e && in_pml(ax, q + c))
+                    w[c] = pml_adjust(ax, pml_t, a.pml_tau, 1, q + c, base + q + c, w[c]);
+            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(ax, pml_t, a.pml_tau, 1, N, base + N, we);
+        }
         if (vec) {
 #pragma unroll
             for (int g4 = 0; g4 < C / 4; ++g4)
@@ -654,16 +714,19 @@ __global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__
 // y / z axes (strided).
 // ---------------------------------------------------------------------------
 constexpr int kMaxWaves = 16;
-constexpr int kTapChunks = 8;      // chunks of a unit that share the PMBC taps
-constexpr int kTapsPerChunk = 4;   // taps per chunk loaded ahead of the solve
+constexpr int kTapChunks = 16;     // chunks of a unit that share the PMBC taps
+constexpr int kTapsPerChunk = 2;   // taps per chunk loaded ahead of the solve
 
 // Columns are the flattened (shot, other coordinate, x) positions of the lines: one
 // lane per column, CW consecutive columns per wave (64, 32 or 16), the 64/CW lane
 // groups of a wave and the waves of the block holding consecutive chunks of C nodes
 // along the axis.  Chunk maps and PMBC partial sums meet in LDS: two barriers.
+// WIDE (CW = 64, one chunk per wave): the chunk index and so the factor rows are
+// wave-uniform (scalar loads, no vector registers for the factors), and the column
+// decomposition is done once per wave.
 // Dynamic LDS: 6 * blockDim.x + 64 floats.
-template <int C, int SOLVE, int EPI>
-__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, int gx_real)
+template <int C, int SOLVE, int EPI, bool WIDE>
+__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, int gx_real)
 {
     extern __shared__ float lds[];
     const int nthr = blockDim.x;
@@ -682,21 +745,36 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         bx = logical - by * (int)gridDim.x;
     }
     if (bx >= gx_real) return;   // padding block (uniform across the block)
+    const int CW = WIDE ? 64 : CW_;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int SUB = 64 / CW;
+    const int SUB = WIDE ? 1 : 64 / CW;
     const int NCH = (nthr >> 6) * SUB;
     const int ci = lane & (CW - 1);
-    const int chunk = wv * SUB + lane / CW;
+    const int chunk = WIDE ? __builtin_amdgcn_readfirstlane(wv) : wv * SUB + lane / CW;
     const int me = chunk * CW + ci;
     const int n_other = (axis == 1) ? a.nz : a.ny;
     const int pitch = (int)a.pitch;
     const int per_shot = n_other * pitch;
     const int fcol = bx * CW + ci;
-    const int shot0 = fcol / per_shot;
-    const int rem = fcol - shot0 * per_shot;
-    const int o = rem / pitch;
-    const int col = rem - o * pitch;
+    int shot0, o, col;
+    if constexpr (WIDE) {
+        // first column of the wave, then step this lane's column across row ends
+        const int f0 = bx * 64;
+        shot0 = f0 / per_shot;
+        const int r0 = f0 - shot0 * per_shot;
+        o = r0 / pitch;
+        col = r0 - o * pitch + lane;
+        while (col >= pitch) {
+            col -= pitch;
+            if (++o == n_other) { o = 0; ++shot0; }
+        }
+    } else {
+        shot0 = fcol / per_shot;
+        const int rem = fcol - shot0 * per_shot;
+        o = rem / pitch;
+        col = rem - o * pitch;
+    }
     const bool cact = col < a.nx && shot0 < a.S;
     const int shot = min(shot0, a.S - 1);
     const int l = by;
@@ -763,8 +841,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         }
     }
 
-    // ---- forward elimination, chunk maps -------------------------------------
-    float y[C], P[C];
+    // ---- forward elimination: chunk maps (values recomputed from the carry) ------
     float yv = 0.f, pv = 1.f;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -774,8 +851,6 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         }
         yv = fmaf(-fm[c], yv, r);
         pv = -fm[c] * pv;
-        y[c] = yv;
-        P[c] = pv;
     }
     sA[me] = pv;
     sB[me] = yv;
@@ -791,8 +866,17 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         for (int j = 0; j < T; ++j) yin += sPs[j * CW + ci];
     }
     for (int j = j0; j < chunk; ++j) yin = fmaf(sA[j * CW + ci], yin, sB[j * CW + ci]);
+    float y[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
+    for (int c = 0; c < C; ++c) {
+        float r = interior_rhs<SOLVE>(ax, opaque(u[c]), opaque(u[c + 1]), opaque(u[c + 2]));
+        if constexpr (SOLVE != SOLVE_T1) {
+            if (c == 0 && chunk == 0)
+                r = first_row<SOLVE>(ax, er, opaque(u[1]), opaque(u[2]), fm[0], fi[0], fs[0]);
+        }
+        yin = fmaf(-fm[c], yin, r);
+        y[c] = yin;
+    }
 
     const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
     if (chunk == kc) {
@@ -806,8 +890,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         sWe[ci] = last_row<SOLVE>(ax, er, ylast, ulast, ue, phe);
     }
 
-    // ---- back substitution ---------------------------------------------------
-    float w[C], Q[C];
+    // ---- back substitution: chunk maps, composition, values (into y) -------------
     float wvv = 0.f, qv = 1.f;
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
@@ -815,8 +898,6 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
             wvv = fmaf(-fs[c], wvv, y[c]) * fi[c];
             qv = -fs[c] * fi[c] * qv;
         }
-        w[c] = wvv;
-        Q[c] = qv;
     }
     sQ[me] = qv;
     sW[me] = wvv;
@@ -824,6 +905,11 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
     const float we = sWe[ci];
     float wr = we;   // chunks past kc hold identity maps
     for (int j = min(NCH - 1, chunk + Dc); j > chunk; --j) wr = fmaf(sQ[j * CW + ci], wr, sW[j * CW + ci]);
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        if (q + c < e) wr = fmaf(-fs[c], wr, y[c]) * fi[c];
+        y[c] = wr;
+    }
 
     if (cact) {
         const int cy = axis == 1 ? 0 : o, cz = axis == 1 ? o : 0;
@@ -839,7 +925,8 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
             const int i = q + c;
             if (i < e) {
                 const int off = mbase + i * stride;
-                const float D = fmaf(Q[c], wr, w[c]);
+                float D = y[c];
+                if (a.pml_mem && in_pml(ax, i)) D = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, i, sbase + off, D);
                 float v;
                 if constexpr (kPre)
                     v = epilogue_pre<EPI>(a, sbase + off, off, shot, D, pre[c], col, axis == 1 ? i : cy,
@@ -852,7 +939,9 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
         }
         if (e == N && chunk == kc) {
             const int off = mbase + N * stride;
-            const float v = epilogue<EPI>(a, sbase + off, off, shot, we, col, axis == 1 ? N : cy,
+            float D = we;
+            if (a.pml_mem && in_pml(ax, N)) D = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, N, sbase + off, D);
+            const float v = epilogue<EPI>(a, sbase + off, off, shot, D, col, axis == 1 ? N : cy,
                                           axis == 1 ? cz : N, srcs);
             if (rinfo.y > 0 && rinfo.w == N) {
                 const int64_t nn = *a.d_step - 1;
@@ -863,51 +952,82 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW, i
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint phase 2: out_j = (G^T y)_j, with y at junction rows recovered from the
-// junction row of T^T:  y_J = z_J - subT_J y_{J-1} - supT_J y_{J+1}.
+// Adjoint phase 2.  The patch-interior solve of T^T y = z leaves y undefined at the
+// junction rows; the junction row of T^T gives it:  y_J = z_J - subT_J y_{J-1} -
+// supT_J y_{J+1}  (neighbours are patch-interior rows).  Then (G^T y)_j = the stencil
+// column j of G (junction rows of G are zero) plus the transposed PMBC rows.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float adj_y(const AxisDev &ax, const float *__restrict__ Y,
-                                       const LineArgs &a, int64_t lb, int64_t mlb, int64_t stride, int i)
-{
-    const float4 lu = ax.lu[i];
-    if (lu.w != (float)ROW_JUNCTION) return Y[lb + (int64_t)i * stride];
-    const float4 t = ax.luT[i];
-    float v = load_in(a, lb + (int64_t)i * stride, mlb + (int64_t)i * stride);
-    if (i > 0) v = fmaf(-t.w, Y[lb + (int64_t)(i - 1) * stride], v);
-    if (i < ax.N) v = fmaf(-t.z, Y[lb + (int64_t)(i + 1) * stride], v);
-    return v;
-}
 
-template <int EPI>
-__global__ void __launch_bounds__(256) k_adj_gather(LineArgs a, const float *__restrict__ Y, int axis,
-                                                    int64_t total)
+// One thread per (line, junction).  Junction slot k sits at node (k+1)M (natural
+// ends: slots 0..p-2) or min(kM, N) (junction ends: slots 0..p).
+__global__ void __launch_bounds__(256) k_adj_junctions(LineArgs a, float *__restrict__ Y, int axis, int nj,
+                                                       int64_t total)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const AxisDev &ax = a.ax;
-    const int x = (int)(idx % a.nx);
-    int64_t r = idx / a.nx;
-    const int yy = (int)(r % a.ny);
-    r /= a.ny;
-    const int z = (int)(r % a.nz);
-    const int shot = (int)(r / a.nz);
+    int slot, x, yy, z, shot;
+    if (axis == 0) {
+        slot = (int)(idx % nj);
+        int64_t row = idx / nj;
+        const int rps = a.nz * a.ny;
+        shot = (int)(row / rps);
+        const int r2 = (int)(row - (int64_t)shot * rps);
+        z = r2 / a.ny;
+        yy = r2 - z * a.ny;
+        x = 0;
+    } else {
+        x = (int)(idx % a.nx);
+        int64_t t = idx / a.nx;
+        const int n_other = axis == 1 ? a.nz : a.ny;
+        const int so = (int)(t % ((int64_t)a.S * n_other));
+        slot = (int)(t / ((int64_t)a.S * n_other));
+        shot = so / n_other;
+        const int o = so - shot * n_other;
+        if (axis == 1) { z = o; yy = 0; } else { yy = o; z = 0; }
+    }
+    const int J = ax.ends == 0 ? (slot + 1) * ax.M : min(slot * ax.M, ax.N);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? a.pitch : a.plane);
+    const int64_t midx0 = (int64_t)z * a.plane + (int64_t)yy * a.pitch + x;   // node 0 of the line
+    const int64_t lb = (int64_t)shot * a.shot_stride + midx0;
+    const float4 t = ax.luT[J];
+    float v = a.in[lb + J * stride];
+    if (a.in_coef) v *= a.in_coef[midx0 + J * stride];
+    if (J > 0) v = fmaf(-t.w, Y[lb + (J - 1) * stride], v);
+    if (J < ax.N) v = fmaf(-t.z, Y[lb + (J + 1) * stride], v);
+    Y[lb + J * stride] = v;
+}
+
+// One thread per node; blocks tile the rows of x (the grid is rows x blocks per row,
+// so the row decomposition is per block).  Along x the node index varies across the
+// lanes; along y or z it is uniform per block (table reads are scalar).
+template <int EPI>
+__global__ void __launch_bounds__(256) k_adj_gather(LineArgs a, const float *__restrict__ Y, int axis, int bpr)
+{
+    const int row = blockIdx.x / bpr;                 // (shot, z, y) row of the padded layout
+    const int x = (blockIdx.x - row * bpr) * blockDim.x + threadIdx.x;
+    if (x >= a.nx) return;
+    const AxisDev &ax = a.ax;
+    const int rps = a.nz * a.ny;
+    const int shot = row / rps;
+    const int r2 = row - shot * rps;
+    const int z = r2 / a.ny;
+    const int yy = r2 - z * a.ny;
     const int64_t midx = (int64_t)z * a.plane + (int64_t)yy * a.pitch + x;
     const int64_t oidx = (int64_t)shot * a.shot_stride + midx;
     const int j = axis == 0 ? x : (axis == 1 ? yy : z);
     const int64_t stride = axis == 0 ? 1 : (axis == 1 ? a.pitch : a.plane);
-    const int64_t lb = oidx - (int64_t)j * stride;
-    const int64_t mlb = midx - (int64_t)j * stride;
-    float out = 0.f;
-    const float4 rc = ax.rc[j];
-    out = rc.y * adj_y(ax, Y, a, lb, mlb, stride, j);
-    if (j > 0) out = fmaf(ax.rc[j - 1].z, adj_y(ax, Y, a, lb, mlb, stride, j - 1), out);
-    if (j < ax.N) out = fmaf(ax.rc[j + 1].x, adj_y(ax, Y, a, lb, mlb, stride, j + 1), out);
+    const float *__restrict__ yl = Y + (oidx - j * stride);   // node 0 of the line
+    const float4 w = ax.adjw[j];
+    float out = w.y * yl[j * stride];
+    out = fmaf(w.x, yl[max(j - 1, 0) * stride], out);
+    out = fmaf(w.z, yl[min(j + 1, ax.N) * stride], out);
     const int *gn = ax.g_node + (int64_t)j * kMaxGatherTaps;
     const float *gc = ax.g_c + (int64_t)j * kMaxGatherTaps;
 #pragma unroll
     for (int t = 0; t < kMaxGatherTaps; ++t) {
         const int J = gn[t];
-        if (J >= 0) out = fmaf(gc[t], adj_y(ax, Y, a, lb, mlb, stride, J), out);
+        if (J >= 0) out = fmaf(gc[t], yl[J * stride], out);
     }
     epilogue<EPI>(a, oidx, midx, shot, out, x, yy, z);
 }
@@ -1123,11 +1243,23 @@ hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
     dim3 grid((unsigned)gxp, a.ax.p, 1);
     const int threads = 64 * W;
     const size_t shm = (6 * (size_t)threads + 64) * sizeof(float);
+    if constexpr (C != 8) {
+        if (CW == 64) {
+            switch (epi) {
+            case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE, true>), grid, threads, shm, st, a, axis, CW, gx); break;
+            case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY, true>), grid, threads, shm, st, a, axis, CW, gx); break;
+            case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX, true>), grid, threads, shm, st, a, axis, CW, gx); break;
+            case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE, true>), grid, threads, shm, st, a, axis, CW, gx); break;
+            default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
+    }
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE>), grid, threads, shm, st, a, axis, CW, gx); break;
-    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY>), grid, threads, shm, st, a, axis, CW, gx); break;
-    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX>), grid, threads, shm, st, a, axis, CW, gx); break;
-    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE, false>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY, false>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX, false>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE, false>), grid, threads, shm, st, a, axis, CW, gx); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1177,7 +1309,7 @@ int line_xx_threads(const LineArgs &a)
     return threads;
 }
 
-hipError_t launch_line_xx(const LineArgs &a, float *Tout, hipStream_t st)
+hipError_t launch_line_xx(const LineArgs &a, float *Tout, float *pml_mem_t, hipStream_t st)
 {
     const int threads = line_xx_threads(a);
     if (!threads) return hipErrorInvalidValue;
@@ -1188,22 +1320,35 @@ hipError_t launch_line_xx(const LineArgs &a, float *Tout, hipStream_t st)
     const int64_t lines = (int64_t)a.S * a.nz * a.ny;
     if (lines >= (1ll << 31)) return hipErrorInvalidValue;
     switch (cx) {
-    case 4: hipLaunchKernelGGL(k_line_xx<4>, (unsigned)lines, threads, shm, st, a, Tout, G); break;
-    case 8: hipLaunchKernelGGL(k_line_xx<8>, (unsigned)lines, threads, shm, st, a, Tout, G); break;
-    default: hipLaunchKernelGGL(k_line_xx<16>, (unsigned)lines, threads, shm, st, a, Tout, G); break;
+    case 4: hipLaunchKernelGGL(k_line_xx<4>, (unsigned)lines, threads, shm, st, a, Tout, pml_mem_t, G); break;
+    case 8: hipLaunchKernelGGL(k_line_xx<8>, (unsigned)lines, threads, shm, st, a, Tout, pml_mem_t, G); break;
+    default: hipLaunchKernelGGL(k_line_xx<16>, (unsigned)lines, threads, shm, st, a, Tout, pml_mem_t, G); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_junctions(int axis, const LineArgs &a, float *Y, hipStream_t st)
+{
+    const int nj = a.ax.ends == 0 ? a.ax.p - 1 : a.ax.p + 1;
+    if (nj <= 0) return hipSuccess;
+    const int64_t lines = axis == 0 ? (int64_t)a.S * a.nz * a.ny
+                                    : (int64_t)a.S * (axis == 1 ? a.nz : a.ny) * a.nx;
+    const int64_t total = lines * nj;
+    hipLaunchKernelGGL(k_adj_junctions, nblk(total, 256), 256, 0, st, a, Y, axis, nj, total);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st)
 {
-    const int64_t total = (int64_t)a.S * a.nz * a.ny * a.nx;
-    const unsigned blocks = nblk(total, 256);
+    const int bpr = (a.nx + 255) / 256;
+    const int64_t rows = (int64_t)a.S * a.nz * a.ny;
+    if (rows * bpr >= (1ll << 31) || a.shot_stride * a.S >= (1ll << 40)) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)(rows * bpr);
     switch (epi) {
-    case EPI_STORE: hipLaunchKernelGGL(k_adj_gather<EPI_STORE>, blocks, 256, 0, st, a, Y, axis, total); break;
-    case EPI_AXPY: hipLaunchKernelGGL(k_adj_gather<EPI_AXPY>, blocks, 256, 0, st, a, Y, axis, total); break;
-    case EPI_AXPY_AUX: hipLaunchKernelGGL(k_adj_gather<EPI_AXPY_AUX>, blocks, 256, 0, st, a, Y, axis, total); break;
-    case EPI_BASE: hipLaunchKernelGGL(k_adj_gather<EPI_BASE>, blocks, 256, 0, st, a, Y, axis, total); break;
+    case EPI_STORE: hipLaunchKernelGGL(k_adj_gather<EPI_STORE>, blocks, 256, 0, st, a, Y, axis, bpr); break;
+    case EPI_AXPY: hipLaunchKernelGGL(k_adj_gather<EPI_AXPY>, blocks, 256, 0, st, a, Y, axis, bpr); break;
+    case EPI_AXPY_AUX: hipLaunchKernelGGL(k_adj_gather<EPI_AXPY_AUX>, blocks, 256, 0, st, a, Y, axis, bpr); break;
+    case EPI_BASE: hipLaunchKernelGGL(k_adj_gather<EPI_BASE>, blocks, 256, 0, st, a, Y, axis, bpr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

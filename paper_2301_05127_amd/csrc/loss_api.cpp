@@ -118,6 +118,12 @@ struct loss_sim {
     float *adj[4] = {nullptr, nullptr, nullptr, nullptr};   // lambda, mu1, mu3, Y scratch
     double *grad_pad = nullptr, *grad_dense = nullptr, *res_dev = nullptr;
     float *d_vp = nullptr, *d_rho = nullptr;   // dense copies of the media for the gradient map
+    double cmax = 0.0;                         // largest velocity of the media
+    // absorbing layer: memory variables psi_x, psi_z (velocity sub-flow), phi_x, phi_z
+    // (stress sub-flow), each laid out like a field; per-axis coefficient tables
+    float *pml_mem = nullptr;
+    float4 *pml_tab[3] = {nullptr, nullptr, nullptr};
+    int pml_w = 0;
 
     template <class T>
     loss_status alloc(T **p, size_t count)
@@ -156,6 +162,20 @@ LineArgs base_args(const loss_sim *s, int axis)
     a.cx = s->cx;
     a.cs = s->cs[axis];
     return a;
+}
+
+// Memory variables of the absorbing layer: 0 psi_x, 1 psi_z (velocity sub-flow),
+// 2 phi_x, 3 phi_z (stress sub-flow).
+float *pml_var(const loss_sim *s, int k)
+{
+    return s->pml_mem ? s->pml_mem + (size_t)k * field_elems(s) : nullptr;
+}
+
+void set_pml(const loss_sim *s, LineArgs &a, int k, double tau, bool store)
+{
+    a.pml_mem = pml_var(s, k);
+    a.pml_tau = (float)tau;
+    a.pml_store = store ? 1 : 0;
 }
 
 // 3-D axis index of the grid axis for a 2-D acoustic grid: (x, z) -> (0, 2).
@@ -242,7 +262,8 @@ loss_status adj_deriv(loss_sim *s, int axis, const float *in, const float *in_co
     g.out[0] = out;
     g.alpha = alpha;
     if ((r = timed_begin(s))) return r;
-    hipError_t e = launch_adj_gather(axis, epi, g, Y, s->st);
+    hipError_t e = launch_adj_junctions(axis, g, Y, s->st);
+    if (e == hipSuccess) e = launch_adj_gather(axis, epi, g, Y, s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("adjoint gather: ") + hipGetErrorString(e));
     return timed_end(s, KC_ADJ_GATHER);
 }
@@ -293,6 +314,9 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             a.coef[0] = b;
             int epi = EPI_AXPY;
             if (base) { a.aux = base[c]; epi = EPI_BASE; }
+            // the layer's memory variable advances with the state (an evaluation at
+            // another time into a temporary leaves it unchanged)
+            set_pml(s, a, c, frac * s->d.dt, base == nullptr);
             if (with_forces) {
                 const int fid = c == 0 ? LOSS_F_V1 : LOSS_F_V3;
                 attach_sources(s, a, 0, &fid, 1, true);
@@ -332,6 +356,7 @@ loss_status acoustic_stress_x(loss_sim *s)
     LineArgs a = base_args(s, 0);
     a.in = s->f[LOSS_F_V1];
     a.out[0] = s->tmp[0];
+    set_pml(s, a, 2, s->d.dt, true);
     return run_line(s, KC_STRESS_X, 0, SOLVE_D1, EPI_STORE, a);
 }
 
@@ -346,6 +371,7 @@ loss_status acoustic_stress_z(loss_sim *s, float *div_store, int64_t div_shot_st
     c.alpha = -1.f;
     c.div = div_store;
     c.div_shot_stride = div_shot_stride;
+    set_pml(s, c, 3, s->d.dt, true);
     const int fid = LOSS_F_SIGMA;
     attach_sources(s, c, -1, &fid, 1, false);
     if (s->d_rcol && s->d.trace_len > 0) {
@@ -367,6 +393,7 @@ loss_status acoustic_velocity(loss_sim *s, int c)
     a.alpha = -1.f;
     a.out[0] = s->f[c == 0 ? LOSS_F_V1 : LOSS_F_V3];
     a.coef[0] = s->med.back();
+    set_pml(s, a, c, s->d.dt, true);
     return run_line(s, c == 0 ? KC_VEL_X : KC_VEL_Z, axis, SOLVE_D1, EPI_AXPY, a);
 }
 
@@ -380,10 +407,11 @@ loss_status acoustic_velocity_stress_x(loss_sim *s)
     a.out[0] = s->f[LOSS_F_V1];
     a.coef[0] = s->med.back();
     a.step_inc = s->d_step;
+    set_pml(s, a, 0, s->d.dt, true);
     s->pending_inc = false;
     loss_status r = timed_begin(s);
     if (r) return r;
-    hipError_t e = launch_line_xx(a, s->tmp[0], s->st);
+    hipError_t e = launch_line_xx(a, s->tmp[0], pml_var(s, 2), s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("fused x kernel launch: ") + hipGetErrorString(e));
     return timed_end(s, KC_VEL_STRESS_X);
 }
@@ -657,6 +685,17 @@ loss_status unfused_velocity(loss_sim *s, std::vector<float *> &vout)
 loss_status unfuse_in_place(loss_sim *s)
 {
     if (!s->fused) return LOSS_OK;
+    if (s->pml_mem) {
+        // the layer's memory variables go back with the velocity: the exact velocity
+        // sub-flow over -dt/2, in place
+        std::vector<float *> vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
+        loss_status r = velocity_stage(s, -0.5f, vel.data(), nullptr);
+        if (r) return r;
+        if ((r = inject(s, s->d_fields, 0, -0.5f, 1))) return r;
+        s->fused = false;
+        drop_graph(s);
+        return LOSS_OK;
+    }
     std::vector<float *> v;
     loss_status r = unfused_velocity(s, v);
     if (r) return r;
@@ -831,6 +870,11 @@ loss_status upload_axis(loss_sim *s, int axis)
     }
     // at least one slot of taps: the kernels read slot 0 even on a line without junctions
     std::vector<float> tc(std::max<size_t>(h.tap_c.size(), 2 * h.halo + 1), 0.f), gc(h.g_c.begin(), h.g_c.end());
+    // column j of the stencil part of G (junction rows of G are zero)
+    std::vector<float4> adjw(n);
+    for (int j = 0; j < n; ++j)
+        adjw[j] = make_float4(j > 0 ? (float)h.cp[j - 1] : 0.f, (float)h.c0[j], j < h.N ? (float)h.cm[j + 1] : 0.f, 0.f);
+    float4 *dadjw;
     std::copy(h.tap_c.begin(), h.tap_c.end(), tc.begin());
     float4 *dlu, *drc, *dluT, *dlu2;
     float2 *dlu2c, *dlum, *dlum2;
@@ -842,7 +886,7 @@ loss_status upload_axis(loss_sim *s, int axis)
         (r = s->alloc(&dlum2, np)) ||
         (r = s->alloc(&dti, std::max<size_t>(1, h.tap_idx.size()))) ||
         (r = s->alloc(&dtc, tc.size())) ||
-        (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())))
+        (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())) || (r = s->alloc(&dadjw, n)))
         return r;
     HIPCHK(hipMemcpy(dlu, lu.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(drc, rc.data(), n * sizeof(float4), hipMemcpyHostToDevice));
@@ -855,6 +899,7 @@ loss_status upload_axis(loss_sim *s, int axis)
         HIPCHK(hipMemcpy(dti, h.tap_idx.data(), h.tap_idx.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dtc, tc.data(), tc.size() * sizeof(float), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dgn, h.g_node.data(), h.g_node.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dadjw, adjw.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dgc, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice));
     AxisDev &d = s->axd[axis];
     d.N = h.N; d.M = h.M; d.p = h.p; d.ntap = 2 * h.halo + 1; d.h = (float)h.h;
@@ -865,7 +910,7 @@ loss_status upload_axis(loss_sim *s, int axis)
     d.reach = h.reach;
     d.lum = dlum; d.lum2 = dlum2;
     d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
-    d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc;
+    d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc; d.adjw = dadjw;
     return LOSS_OK;
 }
 
@@ -1011,6 +1056,7 @@ loss_status loss_set_media(loss_sim *s, const float *vp, const float *vs, const 
     HIPCHK(hipStreamSynchronize(s->st));
     double cmax = 0;
     for (float v : hv) cmax = std::max(cmax, (double)v);
+    s->cmax = cmax;
     double hmin = s->d.h[0];
     hmin = std::min(hmin, s->d.h[2]);
     if (s->d.ndim == 3) hmin = std::min(hmin, s->d.h[1]);
@@ -1068,12 +1114,59 @@ loss_status loss_add_receivers(loss_sim *s, int32_t shot, int64_t nrec, const in
     return LOSS_OK;
 }
 
+loss_status loss_set_pml(loss_sim *s, int32_t width, double reflection, double kmax, double f0)
+{
+    if (!s) return fail(LOSS_EINVAL, "null argument");
+    if (s->d.physics != LOSS_ACOUSTIC) return fail(LOSS_EUNSUPPORTED, "the absorbing layer is built for the acoustic system");
+    if (width < 0 || width > s->d.n[0] / 2 || width > s->d.n[2] / 2)
+        return fail(LOSS_EINVAL, "layer width must be in 0 .. n/2 on every axis");
+    if (width > 0 && (!(reflection > 0.0 && reflection < 1.0) || !(kmax >= 1.0) || !(f0 > 0.0)))
+        return fail(LOSS_EINVAL, "need 0 < reflection < 1, kmax >= 1, f0 > 0");
+    if (width > 0 && !s->media_set) return fail(LOSS_ESTATE, "loss_set_media must be called first");
+    loss_status r;
+    if ((r = unfuse_in_place(s))) return r;
+    drop_graph(s);
+    for (int a : {0, 2}) {
+        if (s->pml_tab[a]) { s->release(s->pml_tab[a]); s->pml_tab[a] = nullptr; }
+        s->axd[a].pml = nullptr;
+        s->axd[a].pml_w = 0;
+    }
+    if (s->pml_mem) { s->release(s->pml_mem); s->pml_mem = nullptr; }
+    s->pml_w = width;
+    if (width == 0) return LOSS_OK;
+    const int64_t fe = field_elems(s);
+    if ((r = s->alloc(&s->pml_mem, (size_t)(4 * fe)))) return r;
+    if (launch_fill(s->pml_mem, 4 * fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    for (int a : {0, 2}) {
+        const int N = (int)s->d.n[a];
+        const double h = s->d.h[a];
+        const double d0 = -3.0 * s->cmax * std::log(reflection) / (2.0 * width * h);
+        const double amax = 3.14159265358979323846 * f0;
+        std::vector<float4> tab(N + 1);
+        for (int j = 0; j <= N; ++j) {
+            int dist = 0;
+            if (j < width) dist = width - j;
+            if (j > N - width) dist = std::max(dist, j - (N - width));
+            const double del = (double)dist / width;
+            const double d = d0 * del * del, k = 1.0 + (kmax - 1.0) * del, al = amax * (1.0 - del);
+            tab[j] = make_float4((float)(d / k + al), (float)(d / (k * k)), (float)(1.0 / k), 0.f);
+        }
+        if ((r = s->alloc(&s->pml_tab[a], N + 1))) return r;
+        HIPCHK(hipMemcpy(s->pml_tab[a], tab.data(), sizeof(float4) * (N + 1), hipMemcpyHostToDevice));
+        s->axd[a].pml = s->pml_tab[a];
+        s->axd[a].pml_w = width;
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    return LOSS_OK;
+}
+
 loss_status loss_reset(loss_sim *s)
 {
     if (!s) return fail(LOSS_EINVAL, "null argument");
     const int64_t fe = field_elems(s);
     for (int i = 0; i < s->nf; ++i)
         if (launch_fill(s->f[i], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    if (s->pml_mem && launch_fill(s->pml_mem, 4 * fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
     if (s->traces && s->trace_total > 0)
         HIPCHK(hipMemsetAsync(s->traces, 0, sizeof(double) * s->trace_total, s->st));
     HIPCHK(launch_set_step(s->d_step, 0, s->st));
@@ -1196,10 +1289,13 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     const int64_t fe = field_elems(s);
     float *bk = nullptr;
     double *tbk = nullptr;
-    if ((r = s->alloc(&bk, (size_t)(s->nf * fe)))) return r;
+    const int npml = s->pml_mem ? 4 : 0;
+    if ((r = s->alloc(&bk, (size_t)((s->nf + npml) * fe)))) return r;
     if ((r = s->alloc(&tbk, (size_t)std::max<int64_t>(1, s->trace_total)))) return r;
     for (int f = 0; f < s->nf; ++f)
         HIPCHK(hipMemcpyAsync(bk + f * fe, s->f[f], sizeof(float) * fe, hipMemcpyDeviceToDevice, s->st));
+    if (npml)
+        HIPCHK(hipMemcpyAsync(bk + s->nf * fe, s->pml_mem, sizeof(float) * npml * fe, hipMemcpyDeviceToDevice, s->st));
     if (s->trace_total)
         HIPCHK(hipMemcpyAsync(tbk, s->traces, sizeof(double) * s->trace_total, hipMemcpyDeviceToDevice, s->st));
     const int64_t step0 = s->step;
@@ -1233,6 +1329,8 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     // restore
     for (int f = 0; f < s->nf; ++f)
         HIPCHK(hipMemcpyAsync(s->f[f], bk + f * fe, sizeof(float) * fe, hipMemcpyDeviceToDevice, s->st));
+    if (npml)
+        HIPCHK(hipMemcpyAsync(s->pml_mem, bk + s->nf * fe, sizeof(float) * npml * fe, hipMemcpyDeviceToDevice, s->st));
     if (s->trace_total)
         HIPCHK(hipMemcpyAsync(s->traces, tbk, sizeof(double) * s->trace_total, hipMemcpyDeviceToDevice, s->st));
     HIPCHK(launch_set_step(s->d_step, step0, s->st));
@@ -1275,6 +1373,10 @@ loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
     if (!s) return fail(LOSS_EINVAL, "null argument");
     if (s->d.physics != LOSS_ACOUSTIC) return fail(LOSS_EUNSUPPORTED, "the adjoint is built for the acoustic system");
     if (nsteps < 1 || ckpt_every < 1) return fail(LOSS_EINVAL, "nsteps and ckpt_every must be >= 1");
+    if (s->pml_mem) return fail(LOSS_EUNSUPPORTED, "the adjoint is built without the absorbing layer");
+    for (int a = 0; a < 3; ++a)
+        if (!(a == 1 && s->d.ndim == 2) && s->d.patch[a] < 2)
+            return fail(LOSS_EUNSUPPORTED, "the adjoint needs patches of at least 2 intervals");
     if (s->d.trace_len < nsteps) return fail(LOSS_EINVAL, "trace_len must cover nsteps");
     loss_status r;
     if ((r = ensure_ready(s))) return r;

@@ -77,6 +77,9 @@ struct AxisDev {
     const float *tap_c;
     const int *g_node;     // [N+1][kMaxGatherTaps]
     const float *g_c;
+    const float4 *adjw;    // [N+1] {c+ of row j-1, c0 of row j, c- of row j+1, 0}: column j of G's stencil
+    const float4 *pml;     // [N+1] absorbing layer {beta = d/k + alpha, d/k^2, 1/k, 0}, or null
+    int pml_w;             // layer width in nodes (nodes j < pml_w or j > N - pml_w)
 };
 
 // Epilogue of a line kernel.
@@ -132,15 +135,24 @@ struct LineArgs {
     const int64_t *rtoff;
     double *traces;
     int64_t trace_len;
+    // absorbing layer: memory variable of this pass (layout of the fields), the
+    // sub-flow time span (signed seconds), and whether the advanced variable is stored
+    // (a pass that only evaluates the field at another time leaves it unchanged)
+    float *pml_mem;
+    float pml_tau;
+    int pml_store;
 };
 
 // Launch helpers (kernels.hip).  axis: 0 = x (contiguous), 1 = y, 2 = z.
 hipError_t launch_line(int axis, int solve, int epi, const LineArgs &a, hipStream_t st);
+// Adjoint phase 2: Y at the junction rows from the junction rows of T^T, then
+// out (+)= alpha * (G^T Y) (EPI as for the line kernels).
+hipError_t launch_adj_junctions(int axis, const LineArgs &a, float *Y, hipStream_t st);
 hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st);
 // Fused x passes of the acoustic step (velocity along x, then T = d v1/dx of the
 // updated v1 into Tout): threads per block, 0 when a line does not fit one block.
 int line_xx_threads(const LineArgs &a);
-hipError_t launch_line_xx(const LineArgs &a, float *Tout, hipStream_t st);
+hipError_t launch_line_xx(const LineArgs &a, float *Tout, float *pml_mem_t, hipStream_t st);
 
 struct SrcDev {
     int shot, kind, field0, nfield;   // fields field0 .. field0+nfield-1 (consecutive ids)

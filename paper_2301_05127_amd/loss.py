@@ -29,7 +29,7 @@ EXPORTS = [
     "loss_reset", "loss_step", "loss_get_field", "loss_set_field", "loss_get_traces", "loss_deriv",
     "loss_forward_ckpt", "loss_adjoint", "loss_sync", "loss_set_timing", "loss_kernel_timing",
     "loss_current_step", "loss_status_str", "loss_last_error", "loss_autotune",
-    "loss_autotune_choice", "loss_set_shape",
+    "loss_autotune_choice", "loss_set_shape", "loss_set_pml",
 ]
 
 
@@ -83,6 +83,7 @@ def lib():
         "loss_autotune": (I32, [P, I32]),
         "loss_autotune_choice": (I32, [P, I32, ctypes.POINTER(I32)]),
         "loss_set_shape": (I32, [P, I32, I32]),
+        "loss_set_pml": (I32, [P, I32, D, D, D]),
         "loss_status_str": (ctypes.c_char_p, [I32]),
         "loss_last_error": (ctypes.c_char_p, []),
     }
@@ -202,6 +203,11 @@ class Simulation:
     # ---- running --------------------------------------------------------------
     def reset(self):
         _check(lib().loss_reset(self._h))
+
+    def set_pml(self, width, reflection=1e-6, kmax=1.0, f0=15.0):
+        """Absorbing layer of `width` nodes on both ends of x and z (acoustic; see
+        loss_set_pml).  Call after the media are set; width 0 removes it."""
+        _check(lib().loss_set_pml(self._h, int(width), float(reflection), float(kmax), float(f0)))
 
     def step(self, n=1):
         _check(lib().loss_step(self._h, int(n)))

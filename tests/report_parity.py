@@ -1,0 +1,145 @@
+"""Parity report at full workload sizes: the HIP path against the FP64 oracle.
+
+Not collected by pytest (the oracle needs minutes at these sizes).  Usage, on a machine
+with the GPU and the built libraries:
+
+    python tests/report_parity.py cfg1 cfg2 [cfg5 ...] [--steps N] [--shots K] [--out FILE]
+
+For every workload it runs the GPU simulation and the oracle over the same seeded
+inputs (the oracle in chunks of steps, printing progress), and prints one JSON line per
+workload with rel-L2 errors of every field (whole grid and the interior 16 nodes from
+every end) and of the traces.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def f32_inputs(w):
+    """Round media and wavelets the way the GPU receives them."""
+    w = dict(w)
+    for k in ("vp", "vs", "rho"):
+        if w.get(k) is not None:
+            w[k] = np.asarray(w[k], np.float32).astype(np.float64)
+    w["shots"] = [dict(sh, sources=[dict(s, wavelet=np.asarray(s["wavelet"], np.float32).astype(np.float64))
+                                    for s in sh["sources"]]) for sh in w["shots"]]
+    return w
+
+
+def rel(x, ref):
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = np.linalg.norm(ref)
+    return float(np.linalg.norm(x - ref) / d) if d > 0 else float(np.linalg.norm(x - ref))
+
+
+def interior(a, band):
+    sl = tuple(slice(band, -band) for _ in range(a.ndim))
+    return a[sl]
+
+
+def oracle_step(orc, w, shot, k, fields, step0, pml):
+    sh = w["shots"][shot]
+    if pml:
+        return orc.run_pml(w["grid"], pml, w["dt"], k, w["vp"], w["rho"], sources=sh["sources"],
+                           receivers=sh["receivers"], fields_in=fields, step0=step0)
+    return orc.run(w["grid"], w["physics"], w["dt"], k, w["vp"], w["rho"], vs=w.get("vs"),
+                   sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh.get("rec_comp", 0),
+                   fields_in=fields, step0=step0)
+
+
+def oracle_chunked(orc, w, shot, nsteps, chunk, pml=None):
+    fields, traces, done = None, [], 0
+    t0 = time.time()
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        fields, tr = oracle_step(orc, w, shot, k, fields, done, pml)
+        traces.append(tr)
+        done += k
+        print("  oracle shot %d: %d / %d steps, %.0f s" % (shot, done, nsteps, time.time() - t0), flush=True)
+    return fields, np.concatenate(traces, axis=1)
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("workloads", nargs="+")
+    p.add_argument("--steps", type=int, default=None)
+    p.add_argument("--shots", type=int, default=None, help="shots compared (default: all)")
+    p.add_argument("--chunk", type=int, default=50)
+    p.add_argument("--out", default=None)
+    p.add_argument("--pml", type=int, default=0,
+                   help="absorbing layer of this many nodes (acoustic; R = 1e-6, kmax = 1, f0 of the source)")
+    p.add_argument("--save-diff", default=None,
+                   help="write the GPU - oracle difference of field 0, shot 0, at the end (.npy)")
+    p.add_argument("--checkpoints", default="",
+                   help="comma-separated step counts at which the fields are also compared (shot 0)")
+    a = p.parse_args()
+    import oracle
+    from paper_2301_05127_amd import inputs, loss
+    oracle.build()
+    results = []
+    for name in a.workloads:
+        w = f32_inputs(inputs.config(name, **({"nshots": a.shots} if name == "cfg5" and a.shots else {})))
+        nsteps = a.steps or w["nsteps"]
+        S = len(w["shots"]) if a.shots is None else min(a.shots, len(w["shots"]))
+        print("[%s] GPU, %d shot(s), %d steps" % (name, S, nsteps), flush=True)
+        sim = loss.Simulation(w["grid"], w["physics"], w["dt"], nshots=S, trace_len=nsteps)
+        sim.setup_workload(w, shots=w["shots"][:S])
+        pml = None
+        if a.pml:
+            f0 = 15.0 if name != "cfg2" else 20.0
+            pml = dict(width=a.pml, R=1e-6, kmax=1.0, f0=f0, cmax=float(np.max(w["vp"])))
+            sim.set_pml(a.pml, 1e-6, 1.0, f0)
+        nf = 3 if w["physics"] == 0 else 9
+        res = {"workload": name, "steps": nsteps, "shots": S, "pml": a.pml, "fields": {}, "interior16": {},
+               "traces": {}, "checkpoints": {}}
+        cps = sorted(int(c) for c in a.checkpoints.split(",") if c and int(c) < nsteps)
+        if cps:
+            # shot 0 at intermediate step counts, the oracle advanced alongside
+            rf, done = None, 0
+            for cp in cps:
+                sim.step(cp - done)
+                while done < cp:
+                    k = min(a.chunk, cp - done)
+                    rf, _ = oracle_step(oracle, w, 0, k, rf, done, pml)
+                    done += k
+                e = [rel(sim.get_field(f, shot=0), rf[f]) for f in range(nf)]
+                ei = [rel(interior(sim.get_field(f, shot=0), 16), interior(rf[f], 16)) for f in range(nf)]
+                res["checkpoints"][cp] = {"fields": e, "interior16": ei}
+                print("  step %d: fields %s interior %s" % (cp, ["%.2e" % v for v in e], ["%.2e" % v for v in ei]),
+                      flush=True)
+            sim.step(nsteps - done)
+        else:
+            sim.step(nsteps)
+        sim.sync()
+        for s in range(S):
+            rf, rt = oracle_chunked(oracle, w, s, nsteps, a.chunk, pml)
+            if s == 0 and a.save_diff:
+                np.save(a.save_diff, (sim.get_field(0, shot=0) - rf[0]).astype(np.float32))
+            for f in range(nf):
+                g = sim.get_field(f, shot=s)
+                res["fields"]["shot%d_f%d" % (s, f)] = rel(g, rf[f])
+                res["interior16"]["shot%d_f%d" % (s, f)] = rel(interior(g, 16), interior(rf[f], 16))
+            res["traces"]["shot%d" % s] = rel(sim.get_traces(s), rt)
+        sim.close()
+        res["max_field"] = max(res["fields"].values())
+        res["max_interior16"] = max(res["interior16"].values())
+        res["max_traces"] = max(res["traces"].values())
+        print(json.dumps(res), flush=True)
+        results.append(res)
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(results, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()
