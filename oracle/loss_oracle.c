@@ -718,6 +718,7 @@ int or_run_pml(const or_grid *g, const or_pml *pml, double dt, int step0, int ns
                 double tau = 0.5 * dt;
                 deriv_into(&S, 0, sig, dx);
                 deriv_into(&S, 2, sig, dz);
+#pragma omp parallel for
                 for (i = 0; i < tot; ++i) {
                     int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
                     double p1, dvb;
@@ -740,6 +741,7 @@ int or_run_pml(const or_grid *g, const or_pml *pml, double dt, int step0, int ns
                  * exact flow, with K in place of b */
                 deriv_into(&S, 0, v1, dx);
                 deriv_into(&S, 2, v3, dz);
+#pragma omp parallel for
                 for (i = 0; i < tot; ++i) {
                     int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
                     double p1, dsk;

@@ -76,6 +76,9 @@ def main():
     p.add_argument("--shots", type=int, default=None, help="shots compared (default: all)")
     p.add_argument("--chunk", type=int, default=50)
     p.add_argument("--out", default=None)
+    p.add_argument("--grad", action="store_true",
+                   help="acoustic: also compare the batched adjoint gradient dJ/dK with the oracle's, for the "
+                        "residual = the oracle's traces")
     p.add_argument("--pml", type=int, default=0,
                    help="absorbing layer of this many nodes (acoustic; R = 1e-6, kmax = 1, f0 of the source)")
     p.add_argument("--save-diff", default=None,
@@ -103,26 +106,34 @@ def main():
         res = {"workload": name, "steps": nsteps, "shots": S, "pml": a.pml, "fields": {}, "interior16": {},
                "traces": {}, "checkpoints": {}}
         cps = sorted(int(c) for c in a.checkpoints.split(",") if c and int(c) < nsteps)
+        shot0 = None
         if cps:
-            # shot 0 at intermediate step counts, the oracle advanced alongside
-            rf, done = None, 0
-            for cp in cps:
-                sim.step(cp - done)
+            # shot 0 at intermediate step counts, the oracle advanced alongside (and on
+            # to the end: it is the final reference of shot 0)
+            rf, done, trs = None, 0, []
+            for cp in cps + [nsteps]:
+                if cp != nsteps:
+                    sim.step(cp - done)
                 while done < cp:
                     k = min(a.chunk, cp - done)
-                    rf, _ = oracle_step(oracle, w, 0, k, rf, done, pml)
+                    rf, tr = oracle_step(oracle, w, 0, k, rf, done, pml)
+                    trs.append(tr)
                     done += k
+                    print("  oracle shot 0: %d / %d steps" % (done, nsteps), flush=True)
+                if cp == nsteps:
+                    break
                 e = [rel(sim.get_field(f, shot=0), rf[f]) for f in range(nf)]
                 ei = [rel(interior(sim.get_field(f, shot=0), 16), interior(rf[f], 16)) for f in range(nf)]
                 res["checkpoints"][cp] = {"fields": e, "interior16": ei}
                 print("  step %d: fields %s interior %s" % (cp, ["%.2e" % v for v in e], ["%.2e" % v for v in ei]),
                       flush=True)
-            sim.step(nsteps - done)
+            sim.step(nsteps - cps[-1])
+            shot0 = (rf, np.concatenate(trs, axis=1))
         else:
             sim.step(nsteps)
         sim.sync()
         for s in range(S):
-            rf, rt = oracle_chunked(oracle, w, s, nsteps, a.chunk, pml)
+            rf, rt = shot0 if (s == 0 and shot0 is not None) else oracle_chunked(oracle, w, s, nsteps, a.chunk, pml)
             if s == 0 and a.save_diff:
                 np.save(a.save_diff, (sim.get_field(0, shot=0) - rf[0]).astype(np.float32))
             for f in range(nf):
@@ -131,6 +142,26 @@ def main():
                 res["interior16"]["shot%d_f%d" % (s, f)] = rel(interior(g, 16), interior(rf[f], 16))
             res["traces"]["shot%d" % s] = rel(sim.get_traces(s), rt)
         sim.close()
+        if a.grad and w["physics"] == 0:
+            # the oracle's traces of every shot as the residual (J = sum d^2 / 2)
+            resid = np.zeros((S, len(w["shots"][0]["receivers"]), nsteps))
+            gref = np.zeros(oracle.field_shape(w["grid"]))
+            t0 = time.time()
+            for sidx in range(S):
+                sh = w["shots"][sidx]
+                _, rt = oracle.run(w["grid"], 0, w["dt"], nsteps, w["vp"], w["rho"], sources=sh["sources"],
+                                   receivers=sh["receivers"])
+                resid[sidx] = rt
+                gref += oracle.acoustic_adjoint(w["grid"], w["dt"], nsteps, w["vp"], w["rho"], sh["sources"],
+                                                sh["receivers"], rt)
+                print("  oracle adjoint shot %d: %.0f s" % (sidx, time.time() - t0), flush=True)
+            g2 = loss.Simulation(w["grid"], 0, w["dt"], nshots=S, trace_len=nsteps)
+            g2.setup_workload(w, shots=w["shots"][:S])
+            g2.forward_ckpt(nsteps, int(w.get("ckpt_every", 100)))
+            ggpu = g2.adjoint(resid, param=loss.GRAD_K)
+            g2.close()
+            res["gradient_K"] = rel(ggpu, gref)
+            print("  gradient dJ/dK rel-L2 %.3e" % res["gradient_K"], flush=True)
         res["max_field"] = max(res["fields"].values())
         res["max_interior16"] = max(res["interior16"].values())
         res["max_traces"] = max(res["traces"].values())
