@@ -49,7 +49,7 @@ ALGO_BYTES = {
 }
 STEP_BYTES = {0: 44, 1: 120}   # compulsory bytes per cell-step (whole step)
 DEFAULT_STEPS = {"cfg1": 300, "cfg2": 2000, "cfg3": 1000, "cfg4": 1500, "cfg5": 3000}
-CPU_SAMPLE_STEPS = {"cfg1": 300, "cfg2": 40, "cfg3": 2, "cfg4": 1, "cfg5": 60}
+CPU_SAMPLE_STEPS = {"cfg1": 3000, "cfg2": 240, "cfg3": 12, "cfg4": 2, "cfg5": 700}
 
 
 def parse():

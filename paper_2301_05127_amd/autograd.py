@@ -1,0 +1,40 @@
+"""torch.autograd view of the acoustic solver: traces = F(m) for a model m (wave speed c
+or bulk modulus K = rho c^2), whose backward is the hand-written discrete adjoint.
+
+The forward runs the checkpointed acoustic stepper (`loss_forward_ckpt`); the backward
+injects the incoming trace gradient at the receivers and runs the adjoint sweep
+(`loss_adjoint`), which returns the vector-Jacobian product sum_r g_r dtraces_r/dm.
+Paper Sec. 2 (acoustic system) and Sec. 3.3 (the Strang step that is transposed).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import loss
+
+
+class _Seismograms(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, m, sim, rho, nsteps, ckpt_every, param):
+        if not m.is_cuda:
+            raise ValueError("the model must be a CUDA tensor")
+        r = rho.to(device=m.device, dtype=torch.float32).contiguous()
+        mf = m.detach().to(torch.float32)
+        vp = mf if param == loss.GRAD_VP else torch.sqrt(mf / r)
+        torch.cuda.current_stream(m.device).synchronize()
+        sim.set_media(vp.contiguous(), r)
+        sim.forward_ckpt(nsteps, ckpt_every)
+        ctx.sim, ctx.param, ctx.dtype = sim, param, m.dtype
+        return sim.traces_tensor(m.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        grad = ctx.sim.adjoint(g.detach().to(torch.float64).contiguous(), ctx.param)
+        return grad.to(ctx.dtype), None, None, None, None, None
+
+
+def seismograms(sim, m, rho, nsteps, ckpt_every=100, param=loss.GRAD_VP):
+    """Traces [S][nrec][trace_len] (FP64, CUDA) of every shot of `sim` for the model `m`
+    (a CUDA tensor of the field shape: c when param is GRAD_VP, K when GRAD_K); rho is
+    held fixed.  Differentiable with respect to m through the discrete adjoint."""
+    return _Seismograms.apply(m, sim, rho, int(nsteps), int(ckpt_every), int(param))

@@ -575,10 +575,18 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
         }
     };
     float w[C];
+    const float *__restrict__ icf = a.in_coef ? a.in_coef + mbase : nullptr;
     float we = x_unit<C, SOLVE>(
-        ax, k, G, l, a.in_coef == nullptr,
-        [&](int i) { return a.in_coef ? in[i] * a.in_coef[mbase + i] : in[i]; },
-        [&](int i) { return ld4(in + i); }, issue, w);
+        ax, k, G, l, true, [&](int i) { return icf ? in[i] * icf[i] : in[i]; },
+        [&](int i) {
+            float4 v = ld4(in + i);
+            if (icf) {
+                const float4 c = ld4(icf + i);
+                v = make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
+            }
+            return v;
+        },
+        issue, w);
 
     if (uact) {
         const int kc = (e - 1 - s) / C;
@@ -1032,6 +1040,165 @@ __global__ void __launch_bounds__(256) k_adj_gather(LineArgs a, const float *__r
     epilogue<EPI>(a, oidx, midx, shot, out, x, yy, z);
 }
 
+// Gather along y or z: a thread owns kGatherRows consecutive rows of one column; the
+// rows of a block are the same for all its lanes (blockIdx.y), so the stencil and tap
+// tables are read once per block, and each y row is loaded once per segment.
+constexpr int kGatherRows = 8;
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_adj_gather_s(LineArgs a, const float *__restrict__ Y, int axis, int cols)
+{
+    const AxisDev &ax = a.ax;
+    const int N = ax.N;
+    const int r0 = blockIdx.y * kGatherRows;
+    const int gc0 = blockIdx.x * 256 + threadIdx.x;   // (shot, column) with x fastest
+    const int shot = gc0 / cols;
+    const int c = gc0 - shot * cols;
+    const int pitch = (int)a.pitch;
+    const int x = c % pitch;
+    if (shot >= a.S || x >= a.nx) return;
+    // node 0 of the column: axis 2 -> (y, x) = c; axis 1 -> (z, x)
+    const int zc = axis == 1 ? c / pitch : 0;
+    const int yc = axis == 2 ? c / pitch : 0;
+    const int64_t stride = axis == 1 ? a.pitch : a.plane;
+    const int64_t m0 = (int64_t)zc * a.plane + (int64_t)yc * a.pitch + x;
+    const int64_t o0 = (int64_t)shot * a.shot_stride + m0;
+    const float *__restrict__ yl = Y + o0;
+    float yv[kGatherRows + 2];
+#pragma unroll
+    for (int i = 0; i < kGatherRows + 2; ++i) yv[i] = yl[clampi(r0 - 1 + i, 0, N) * stride];
+    Pre pre[kGatherRows];
+#pragma unroll
+    for (int i = 0; i < kGatherRows; ++i) {
+        const int64_t off = (int64_t)min(r0 + i, N) * stride;
+        pre[i] = pre_load<EPI>(a, o0 + off, m0 + off);
+    }
+#pragma unroll
+    for (int i = 0; i < kGatherRows; ++i) {
+        const int r = r0 + i;
+        if (r > N) break;
+        const float4 w = ax.adjw[r];
+        float out = w.y * yv[i + 1];
+        out = fmaf(w.x, yv[r > 0 ? i : i + 1], out);
+        out = fmaf(w.z, yv[r < N ? i + 2 : i + 1], out);
+        const int *gn = ax.g_node + (int64_t)r * kMaxGatherTaps;
+        const float *gcf = ax.g_c + (int64_t)r * kMaxGatherTaps;
+#pragma unroll
+        for (int t = 0; t < kMaxGatherTaps; ++t) {
+            const int J = gn[t];
+            if (J >= 0) out = fmaf(gcf[t], yl[J * stride], out);
+        }
+        const int64_t off = (int64_t)r * stride;
+        epilogue_pre<EPI>(a, o0 + off, m0 + off, shot, out, pre[i], x, axis == 1 ? r : yc, axis == 2 ? r : zc, false);
+    }
+}
+
+// The three adjoint phases of an x pass in one block per line (p*G lanes): the
+// patch-interior solve of T^T y = z, the junction rows of T^T, then G^T y, with y kept
+// in LDS between them.  Same arithmetic, in the same order, as the solve / junction /
+// gather kernels above.
+template <int C, int EPI>
+__global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
+{
+    extern __shared__ float4 lds4[];
+    float *ys = reinterpret_cast<float *>(lds4);
+    const AxisDev &ax = a.ax;
+    const int N = ax.N, M = ax.M, p = ax.p;
+    const int k = threadIdx.x & (G - 1);
+    const int lraw = threadIdx.x / G;
+    const bool uact = lraw < p;
+    const int l = min(lraw, p - 1);
+    const int line = blockIdx.x;
+    const int lps = a.nz * a.ny;
+    const int shot = line / lps;
+    const int64_t base = (int64_t)line * a.pitch;
+    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
+    const int s = l * M;
+    const int e = min(s + M, N);
+    const int kc = (e - 1 - s) / C;
+    const float *__restrict__ in = a.in + base;
+    const float *__restrict__ icf = a.in_coef ? a.in_coef + mbase : nullptr;
+    // junction rows owned here: row s (lane 0; not at a natural end), row N (closing
+    // lane of the last patch, junction ends only)
+    const bool js = uact && k == 0 && (ax.ends != 0 || s > 0);
+    const bool jn = uact && ax.ends != 0 && e == N && k == kc;
+    const int J = jn ? N : s;
+    // the gather phase gives node i to thread i mod blockDim (coalesced tables and
+    // output); its first PF output values are read ahead of the solve
+    constexpr int PF = C + 1;
+    const int nthr = blockDim.x;
+    Pre pre[PF];
+    float zJ = 0.f;
+    auto val = [&](int i) { return icf ? in[i] * icf[i] : in[i]; };
+    auto issue = [&]() {
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+            const int i = min((int)threadIdx.x + r * nthr, N);
+            pre[r] = pre_load<EPI>(a, base + i, mbase + i);
+        }
+        zJ = val(J);
+    };
+    float w[C];
+    float we = x_unit<C, SOLVE_T1>(
+        ax, k, G, l, true, val,
+        [&](int i) {
+            float4 v = ld4(in + i);
+            if (icf) {
+                const float4 c = ld4(icf + i);
+                v = make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
+            }
+            return v;
+        },
+        issue, w);
+    const int q = s + k * C;
+    if (uact) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (q + c < e) ys[q + c] = w[c];
+        if (e == N && k == kc) ys[N] = we;
+    }
+    __syncthreads();
+    // junction rows: y_J = z_J - sub_J y_{J-1} - sup_J y_{J+1} (neighbours are interior rows)
+    if (js || jn) {
+        const float4 t = ax.luT[J];
+        float v = zJ;
+        if (J > 0) v = fmaf(-t.w, ys[J - 1], v);
+        if (J < N) v = fmaf(-t.z, ys[J + 1], v);
+        ys[J] = v;
+    }
+    if (js && jn) {   // a one-lane last patch holding both of its junction rows
+        const float4 t = ax.luT[s];
+        float v = val(s);
+        if (s > 0) v = fmaf(-t.w, ys[s - 1], v);
+        v = fmaf(-t.z, ys[s + 1], v);
+        ys[s] = v;
+    }
+    __syncthreads();
+    // (G^T y)_i: stencil column i, then the transposed PMBC rows reaching node i
+    auto gather = [&](int i) {
+        const float4 aw = ax.adjw[i];
+        const int4 gn = *reinterpret_cast<const int4 *>(ax.g_node + (int64_t)i * kMaxGatherTaps);
+        const float4 gc = *reinterpret_cast<const float4 *>(ax.g_c + (int64_t)i * kMaxGatherTaps);
+        float o = aw.y * ys[i];
+        o = fmaf(aw.x, ys[max(i - 1, 0)], o);
+        o = fmaf(aw.z, ys[min(i + 1, N)], o);
+        if (gn.x >= 0) o = fmaf(gc.x, ys[gn.x], o);
+        if (gn.y >= 0) o = fmaf(gc.y, ys[gn.y], o);
+        if (gn.z >= 0) o = fmaf(gc.z, ys[gn.z], o);
+        if (gn.w >= 0) o = fmaf(gc.w, ys[gn.w], o);
+        return o;
+    };
+#pragma unroll
+    for (int r = 0; r < PF; ++r) {
+        const int i = (int)threadIdx.x + r * nthr;
+        if (i <= N) epilogue_pre<EPI>(a, base + i, mbase + i, shot, gather(i), pre[r], i, 0, 0, false);
+    }
+    for (int i = (int)threadIdx.x + PF * nthr; i <= N; i += nthr) {
+        const Pre pr = pre_load<EPI>(a, base + i, mbase + i);
+        epilogue_pre<EPI>(a, base + i, mbase + i, shot, gather(i), pr, i, 0, 0, false);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // sources, receivers, bookkeeping
 // ---------------------------------------------------------------------------
@@ -1327,6 +1494,26 @@ hipError_t launch_line_xx(const LineArgs &a, float *Tout, float *pml_mem_t, hipS
     return hipGetLastError();
 }
 
+hipError_t launch_adj_x(int epi, const LineArgs &a, hipStream_t st)
+{
+    const int threads = line_xx_threads(a);
+    if (!threads || (epi != EPI_STORE && epi != EPI_AXPY)) return hipErrorNotSupported;
+    const int cx = x_chunk(a);
+    int G = 1;
+    while (G * cx < a.ax.M) G <<= 1;
+    const size_t shm = (size_t)(a.ax.N + 4) / 4 * 16;
+    const int64_t lines = (int64_t)a.S * a.nz * a.ny;
+    if (lines >= (1ll << 31)) return hipErrorInvalidValue;
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, (unsigned)lines, threads, shm, st, a, G); };
+    const bool store = epi == EPI_STORE;
+    switch (cx) {
+    case 4: store ? go(k_adj_x<4, EPI_STORE>) : go(k_adj_x<4, EPI_AXPY>); break;
+    case 8: store ? go(k_adj_x<8, EPI_STORE>) : go(k_adj_x<8, EPI_AXPY>); break;
+    default: store ? go(k_adj_x<16, EPI_STORE>) : go(k_adj_x<16, EPI_AXPY>); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_junctions(int axis, const LineArgs &a, float *Y, hipStream_t st)
 {
     const int nj = a.ax.ends == 0 ? a.ax.p - 1 : a.ax.p + 1;
@@ -1340,6 +1527,20 @@ hipError_t launch_adj_junctions(int axis, const LineArgs &a, float *Y, hipStream
 
 hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st)
 {
+    if (axis != 0) {
+        const int cols = (int)(axis == 1 ? a.nz * a.pitch : a.ny * a.pitch);
+        const int64_t tot = (int64_t)a.S * cols;
+        if (tot >= (1ll << 31) || a.shot_stride * a.S >= (1ll << 40)) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)((tot + 255) / 256), (unsigned)((a.ax.N + kGatherRows) / kGatherRows));
+        switch (epi) {
+        case EPI_STORE: hipLaunchKernelGGL(k_adj_gather_s<EPI_STORE>, grid, 256, 0, st, a, Y, axis, cols); break;
+        case EPI_AXPY: hipLaunchKernelGGL(k_adj_gather_s<EPI_AXPY>, grid, 256, 0, st, a, Y, axis, cols); break;
+        case EPI_AXPY_AUX: hipLaunchKernelGGL(k_adj_gather_s<EPI_AXPY_AUX>, grid, 256, 0, st, a, Y, axis, cols); break;
+        case EPI_BASE: hipLaunchKernelGGL(k_adj_gather_s<EPI_BASE>, grid, 256, 0, st, a, Y, axis, cols); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int bpr = (a.nx + 255) / 256;
     const int64_t rows = (int64_t)a.S * a.nz * a.ny;
     if (rows * bpr >= (1ll << 31) || a.shot_stride * a.S >= (1ll << 40)) return hipErrorInvalidValue;

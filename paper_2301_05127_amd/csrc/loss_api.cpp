@@ -46,12 +46,12 @@ struct RecHost {
 // Kernel classes reported by loss_kernel_timing.
 enum KClass {
     KC_STRESS_X, KC_STRESS_Y, KC_STRESS_Z, KC_VEL_X, KC_VEL_Y, KC_VEL_Z, KC_SOURCE, KC_RECEIVER,
-    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_VEL_STRESS_X, KC_COUNT
+    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_VEL_STRESS_X, KC_ADJ_X, KC_COUNT
 };
 const char *kKClassName[KC_COUNT] = {
     "stress_line_x", "stress_line_y", "stress_line_z", "velocity_line_x", "velocity_line_y",
     "velocity_line_z", "source_inject", "receiver_record", "step_advance", "adjoint_line_solve",
-    "adjoint_gather", "gradient_accumulate", "velocity_stress_x"};
+    "adjoint_gather", "gradient_accumulate", "velocity_stress_x", "adjoint_line_x"};
 
 }  // namespace
 
@@ -248,6 +248,21 @@ void attach_sources(const loss_sim *s, LineArgs &a, int time_offset, const int *
 loss_status adj_deriv(loss_sim *s, int axis, const float *in, const float *in_coef, float *out,
                       float alpha, int epi, float *Y, int nshots)
 {
+    LineArgs x = base_args(s, 0);
+    x.S = nshots;
+    if (axis == 0 && !(s->d.flags & LOSS_FLAG_NO_FUSE_X) && line_xx_threads(x) > 0 &&
+        (epi == EPI_STORE || epi == EPI_AXPY)) {
+        // the whole line in one block: solve, junction rows and gather share y in LDS
+        x.in = in;
+        x.in_coef = in_coef;
+        x.out[0] = out;
+        x.alpha = alpha;
+        loss_status r = timed_begin(s);
+        if (r) return r;
+        const hipError_t e = launch_adj_x(epi, x, s->st);
+        if (e != hipSuccess) return fail(LOSS_EHIP, std::string("adjoint x: ") + hipGetErrorString(e));
+        return timed_end(s, KC_ADJ_X);
+    }
     LineArgs a = base_args(s, axis);
     a.S = nshots;
     a.in = in;
@@ -734,13 +749,14 @@ loss_status one_step(loss_sim *s, float *div_store, int64_t div_shot_stride)
 //   stress_x(1); for n = 1..K: stress_z(n) (records the pressure receivers), vel_z(n),
 //   then vel_x(n) + stress_x(n+1) fused (n < K) or vel_x(K).
 // Each step's first kernel advances the step counter (stress_x or the fused kernel).
-loss_status steps_fused_x(loss_sim *s, int64_t K)
+loss_status steps_fused_x(loss_sim *s, int64_t K, float *div_store, int64_t div_shot_stride)
 {
     loss_status r;
     s->pending_inc = true;
     if ((r = acoustic_stress_x(s))) return r;
     for (int64_t n = 0; n < K; ++n) {
-        if ((r = acoustic_stress_z(s, nullptr, 0))) return r;
+        float *ds = div_store ? div_store + n * s->S * div_shot_stride : nullptr;
+        if ((r = acoustic_stress_z(s, ds, div_shot_stride))) return r;
         if (!s->d_rcol && (r = record(s, s->d_rec_str, s->nrec_str, 1.0f, 0))) return r;
         if ((r = acoustic_velocity(s, 1))) return r;
         r = (n + 1 < K) ? acoustic_velocity_stress_x(s) : acoustic_velocity(s, 0);
@@ -753,7 +769,7 @@ loss_status steps_fused_x(loss_sim *s, int64_t K)
 loss_status steps_eager(loss_sim *s, int64_t K, float *div_store = nullptr, int64_t div_shot_stride = 0)
 {
     loss_status r;
-    if (div_store == nullptr && K > 0 && fused_x_ok(s)) return steps_fused_x(s, K);
+    if (K > 0 && fused_x_ok(s)) return steps_fused_x(s, K, div_store, div_shot_stride);
     for (int64_t done = 0; done < K; ++done) {
         float *ds = div_store ? div_store + done * s->S * div_shot_stride : nullptr;
         if ((r = one_step(s, ds, div_shot_stride))) return r;
@@ -1433,8 +1449,7 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
                                   hipMemcpyDeviceToDevice, s->st));
         HIPCHK(launch_set_step(s->d_step, n0, s->st));
         s->fused = true;
-        for (int64_t k = 0; k < nc; ++k)
-            if ((r = one_step(s, s->divstore + k * fe, ss))) return r;
+        if ((r = steps_eager(s, nc, s->divstore, ss))) return r;
         // reverse sweep over the segment
         for (int64_t k = nc - 1; k >= 0; --k) {
             const int64_t n = n0 + k;

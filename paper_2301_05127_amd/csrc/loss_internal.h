@@ -149,6 +149,9 @@ hipError_t launch_line(int axis, int solve, int epi, const LineArgs &a, hipStrea
 // out (+)= alpha * (G^T Y) (EPI as for the line kernels).
 hipError_t launch_adj_junctions(int axis, const LineArgs &a, float *Y, hipStream_t st);
 hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *Y, hipStream_t st);
+// Fused adjoint x pass (solve, junction rows, gather); hipErrorNotSupported when the
+// line does not fit one block or the epilogue is not STORE / AXPY.
+hipError_t launch_adj_x(int epi, const LineArgs &a, hipStream_t st);
 // Fused x passes of the acoustic step (velocity along x, then T = d v1/dx of the
 // updated v1 into Tout): threads per block, 0 when a line does not fit one block.
 int line_xx_threads(const LineArgs &a);

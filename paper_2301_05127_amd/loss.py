@@ -262,11 +262,38 @@ class Simulation:
         _check(lib().loss_forward_ckpt(self._h, int(nsteps), int(ckpt_every)))
 
     def adjoint(self, residual, param=GRAD_VP):
+        """Gradient of sum(residual * traces) with respect to K or c over the run of the
+        last forward_ckpt.  residual [S][nrec][nt] FP64: a host array (the gradient comes
+        back as a numpy array) or a contiguous CUDA tensor (the gradient is a CUDA tensor)."""
+        if _is_torch(residual) and residual.is_cuda:
+            import torch
+            if residual.dtype != torch.float64 or not residual.is_contiguous():
+                raise TypeError("residual must be a contiguous float64 tensor")
+            g = torch.empty(self.shape, dtype=torch.float64, device=residual.device)
+            # the library runs on its own stream: the residual must be complete first
+            torch.cuda.current_stream(residual.device).synchronize()
+            _check(lib().loss_adjoint(self._h, ctypes.c_void_p(residual.data_ptr()), param,
+                                      ctypes.c_void_p(g.data_ptr()), MEM_DEVICE))
+            return g
         r = np.ascontiguousarray(residual, dtype=np.float64)
         g = np.zeros(self.shape, dtype=np.float64)
         _check(lib().loss_adjoint(self._h, r.ctypes.data_as(ctypes.c_void_p), param,
                                   g.ctypes.data_as(ctypes.c_void_p), MEM_HOST))
         return g
+
+    def traces_tensor(self, device):
+        """Traces of every shot as one CUDA tensor [S][nrec][trace_len] (FP64); shots must
+        have equal receiver counts."""
+        import torch
+        if len(set(self._nrec)) != 1:
+            raise ValueError("shots have different receiver counts")
+        out = torch.empty((len(self._nrec), self._nrec[0], self.trace_len), dtype=torch.float64, device=device)
+        torch.cuda.current_stream(out.device).synchronize()
+        for s in range(len(self._nrec)):
+            if out[s].numel():
+                _check(lib().loss_get_traces(self._h, s, ctypes.c_void_p(out[s].data_ptr()), MEM_DEVICE))
+        self.sync()
+        return out
 
     # ---- launch-shape autotuning ----------------------------------------------------
     def autotune(self, trial_steps=5):

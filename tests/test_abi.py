@@ -103,3 +103,13 @@ def test_null_arguments():
     assert L.loss_destroy(None) == 0
     assert L.loss_step(None, 1) == -1
     assert L.loss_current_step(None) == -1
+
+
+def test_autograd_wrapper_rejects_host_model():
+    """The autograd view runs only on device tensors; a host model is refused before any
+    library call."""
+    import torch
+    from paper_2301_05127_amd import autograd
+    m = torch.ones((5, 5), dtype=torch.float64, requires_grad=True)
+    with pytest.raises(ValueError, match="CUDA"):
+        autograd.seismograms(None, m, torch.ones((5, 5)), 3)

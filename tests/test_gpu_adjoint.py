@@ -118,3 +118,75 @@ def test_forward_ckpt_traces_match_plain_run():
     for s in range(2):
         assert np.array_equal(a.get_traces(s), b.get_traces(s))
     a.close(); b.close()
+
+
+@pytest.mark.parametrize("param", [0, 1])
+def test_autograd_function_matches_adjoint(orc, param):
+    """torch.autograd over the seismograms: J = 1/2 |traces - obs|^2 built in torch, its
+    backward (the discrete adjoint fed the trace gradient from torch) equals the direct
+    adjoint call with the same residual, and the traces equal the numpy readout."""
+    require_gpu()
+    import torch
+    from paper_2301_05127_amd import autograd, loss
+    w = _small_fwi(nshots=2, nsteps=90)
+    S, nsteps = 2, 90
+    announce("autograd seismograms param=%d" % param)
+    obs = np.stack([orc.run(w["grid"], 0, w["dt"], nsteps, w["vp"] * 1.02, w["rho"], sources=sh["sources"],
+                            receivers=sh["receivers"])[1] for sh in w["shots"]])
+    rho = torch.tensor(w["rho"], dtype=torch.float32, device="cuda")
+    vp = torch.tensor(w["vp"], dtype=torch.float64, device="cuda")
+    m = (vp if param == loss.GRAD_VP else rho.double() * vp * vp).clone().requires_grad_(True)
+    sim = loss.Simulation(w["grid"], 0, w["dt"], nshots=S, trace_len=nsteps)
+    sim.setup_workload(w)
+    tr = autograd.seismograms(sim, m, rho, nsteps, ckpt_every=30, param=param)
+    J = 0.5 * ((tr - torch.tensor(obs, device="cuda")) ** 2).sum()
+    J.backward()
+    g_auto = m.grad.cpu().numpy()
+    tr_np = tr.detach().cpu().numpy()
+    # the direct path on a second handle with the same model and residual
+    b = loss.Simulation(w["grid"], 0, w["dt"], nshots=S, trace_len=nsteps)
+    b.setup_workload(w)
+    b.set_media(vp.float().cpu().numpy() if param == loss.GRAD_VP else
+                torch.sqrt(m.detach().float() / rho).cpu().numpy(), w["rho"])
+    b.forward_ckpt(nsteps, 30)
+    tb = np.stack([b.get_traces(s) for s in range(S)])
+    assert np.array_equal(tr_np, tb)
+    g_dir = b.adjoint(tb - obs, param)
+    assert np.abs(J.item() - 0.5 * np.sum((tb - obs) ** 2)) <= 1e-12 * J.item()
+    assert rel_l2(g_auto, g_dir) < 1e-12
+    sim.close(); b.close()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fused_x_adjoint_bitwise_equal(case):
+    """The one-block x adjoint (solve, junction rows, gather with y in LDS) gives the bits
+    of the three separate kernels, for the transposed derivative and its AXPY form."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    n, M, halo, mode = case
+    g = inputs.grid(2, n, (10.0, 10.0, 10.0), M, halo, mode)
+    announce("fused x adjoint %s" % (case,))
+    out = []
+    for flags in (0, loss.FLAG_NO_FUSE_X):
+        sim = loss.Simulation(g, loss.ACOUSTIC, 1e-4, nshots=1, flags=flags)
+        w = inputs.random_field(sim.shape, seed=11).astype(np.float32)
+        out.append(sim.deriv(0, -1, np.stack([w, 2 * w])))
+        sim.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_fused_x_adjoint_gradient_bitwise_equal():
+    """Whole FWI gradient with the fused x adjoint and with the separate kernels."""
+    require_gpu()
+    from paper_2301_05127_amd import loss
+    w = _small_fwi(nshots=2, nsteps=70)
+    announce("fused x adjoint gradient")
+    grads = []
+    for flags in (0, loss.FLAG_NO_FUSE_X):
+        sim = loss.Simulation(w["grid"], 0, w["dt"], nshots=2, trace_len=70, flags=flags)
+        sim.setup_workload(w)
+        sim.forward_ckpt(70, 25)
+        res = np.concatenate([sim.get_traces(s).ravel() for s in range(2)])
+        grads.append(sim.adjoint(res, loss.GRAD_K))
+        sim.close()
+    assert np.array_equal(grads[0], grads[1])

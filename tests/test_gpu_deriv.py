@@ -45,3 +45,25 @@ def test_deriv_matches_oracle(orc, case, order):
             tol = 2e-6 if order == 1 else 5e-6
             assert err < tol and mx < 10 * tol, (axis, b, err, mx)
     sim.close()
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c[0] == 3])
+def test_transposed_deriv_3d_matches_dense(orc, case):
+    """D^T along x, y and z of a 3-D batch (the adjoint's solve, junction rows and
+    gather on every axis) against the dense FP64 line operator of the oracle."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    ndim, n, M, halo, mode = case
+    hs = (10.0, 7.0, 5.0)
+    g = inputs.grid(ndim, n, hs, M, halo, mode)
+    announce("transposed deriv 3-D %s" % (case,))
+    sim = loss.Simulation(g, loss.ELASTIC, 1e-4, nshots=2)
+    w = inputs.random_field((2,) + sim.shape, seed=5).astype(np.float32)
+    for axis in range(3):
+        got = sim.deriv(axis, -1, w)
+        D = orc.line_deriv_matrix(n[axis], hs[axis], M[axis], halo, mode)
+        for b in range(2):
+            w64 = w[b].astype(np.float64)
+            ref = np.moveaxis(np.tensordot(np.moveaxis(w64, 2 - axis, -1), D, axes=([-1], [0])), -1, 2 - axis)
+            assert rel_l2(got[b], ref) < 2e-6, (axis, b)
+    sim.close()

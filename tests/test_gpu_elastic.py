@@ -102,3 +102,58 @@ def test_elastic_periodic_plane_wave(orc):
     for f in (0, 1, 3, 4, 5, 6):
         assert rel_l2(sim.get_field(f), rf[f]) < 1e-5, f
     sim.close()
+
+
+def _pulse_fields(shape, h_nodes):
+    """Smooth initial state so that a few steps move every node and every field at first
+    order: an explosive stress pulse and off-centre pulses of v1, v2, v3 (Gaussians of
+    width h_nodes), as float32."""
+    c = [0.45 * (n - 1) for n in shape]
+    g = lambda n, c0: np.exp(-(np.arange(n) - c0) ** 2 / (2 * h_nodes ** 2))
+
+    def blob(dz, dy, dx):
+        return (g(shape[0], c[0] + dz)[:, None, None] * g(shape[1], c[1] + dy)[None, :, None]
+                * g(shape[2], c[2] + dx)[None, None, :]).astype(np.float32)
+
+    fin = np.zeros((9,) + shape, np.float32)
+    fin[3] = 1e6 * blob(0, 0, 0)
+    fin[4] = fin[5] = fin[3]
+    fin[0] = blob(-7, 0, 10)
+    fin[1] = 0.8 * blob(5, 9, -8)
+    fin[2] = 0.6 * blob(8, -11, 6)
+    return fin
+
+
+@pytest.mark.parametrize("name,nsteps,shape", [
+    ("cfg3", 4, (4, 3208, 3208)),
+    pytest.param("cfg4", 2, (4, 3208, 3208), marks=pytest.mark.timeout(400)),   # inputs + oracle ~1 min
+])
+def test_full_size_few_steps(orc, name, nsteps, shape):
+    """257^3 (4^3 patches of 64, halo 10, two shots) and 513^3 (8^3 patches of 64, halo 12,
+    layered medium): a few steps at full size in the launch shape the benchmark picks,
+    every field against the FP64 oracle."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    w = _f32(inputs.config(name, nsteps=nsteps))
+    S = len(w["shots"])
+    announce("%s full size %d steps, %d shot(s), shape %s" % (name, nsteps, S, shape))
+    sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=S, trace_len=nsteps)
+    sim.setup_workload(w)
+    sim.set_shape(shape)
+    fshape = sim.shape
+    fin = _pulse_fields(fshape, 12.0)
+    for s in range(S):
+        for f in range(9):
+            sim.set_field(f, fin[f], shot=s)
+    sim.step(nsteps)
+    for s in range(S):
+        sh = w["shots"][s]
+        rf, rt = orc.run(w["grid"], 1, w["dt"], nsteps, w["vp"], w["rho"], vs=w["vs"], sources=sh["sources"],
+                         receivers=sh["receivers"], rec_comp=sh.get("rec_comp", 0),
+                         fields_in=fin.astype(np.float64))
+        for f in range(9):
+            e = rel_l2(sim.get_field(f, shot=s), rf[f])
+            assert e < 1e-5, (s, f, e)
+        assert rel_l2(sim.get_traces(s), rt) < 1e-5, s
+        del rf
+    sim.close()
