@@ -214,7 +214,7 @@ loss_status loss_autotune(loss_sim *sim, int32_t trial_steps);
 loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
 
 /* Set the launch shape along `axis` in the encoding of loss_autotune_choice
- * (x: 4, 8 or 16; y/z: 100 * {16, 32, 64} + {8, 16}; 0 = automatic).  LOSS_EINVAL
+ * (x: 4, 8 or 16; y/z: 100 * {8, 16, 32, 64} + {8, 16}; 0 = automatic).  LOSS_EINVAL
  * for any other value. */
 loss_status loss_set_shape(loss_sim *sim, int32_t axis, int32_t shape);
 

@@ -726,7 +726,7 @@ constexpr int kTapChunks = 16;     // chunks of a unit that share the PMBC taps
 constexpr int kTapsPerChunk = 2;   // taps per chunk loaded ahead of the solve
 
 // Columns are the flattened (shot, other coordinate, x) positions of the lines: one
-// lane per column, CW consecutive columns per wave (64, 32 or 16), the 64/CW lane
+// lane per column, CW consecutive columns per wave (64, 32, 16 or 8), the 64/CW lane
 // groups of a wave and the waves of the block holding consecutive chunks of C nodes
 // along the axis.  Chunk maps and PMBC partial sums meet in LDS: two barriers.
 // WIDE (CW = 64, one chunk per wave): the chunk index and so the factor rows are
@@ -1176,9 +1176,13 @@ __global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
     __syncthreads();
     // (G^T y)_i: stencil column i, then the transposed PMBC rows reaching node i
     auto gather = [&](int i) {
-        const float4 aw = ax.adjw[i];
-        const int4 gn = *reinterpret_cast<const int4 *>(ax.g_node + (int64_t)i * kMaxGatherTaps);
-        const float4 gc = *reinterpret_cast<const float4 *>(ax.g_c + (int64_t)i * kMaxGatherTaps);
+        float4 aw = ax.adjw_plain, gc = make_float4(0.f, 0.f, 0.f, 0.f);
+        int4 gn = make_int4(-1, -1, -1, -1);
+        if (!((ax.plain[i >> 5] >> (i & 31)) & 1u)) {
+            aw = ax.adjw[i];
+            gn = *reinterpret_cast<const int4 *>(ax.g_node + (int64_t)i * kMaxGatherTaps);
+            gc = *reinterpret_cast<const float4 *>(ax.g_c + (int64_t)i * kMaxGatherTaps);
+        }
         float o = aw.y * ys[i];
         o = fmaf(aw.x, ys[max(i - 1, 0)], o);
         o = fmaf(aw.z, ys[min(i + 1, N)], o);
@@ -1398,7 +1402,7 @@ hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
     // columns per wave: the caller's choice, else the widest that still gives
     // >= 2048 workgroups (or 16)
     int CW = a.cw;
-    if (CW != 16 && CW != 32 && CW != 64) {
+    if (CW != 8 && CW != 16 && CW != 32 && CW != 64) {
         CW = 64;
         while (CW > 16 && ((F + CW - 1) / CW) * a.ax.p < 2048) CW >>= 1;
     }

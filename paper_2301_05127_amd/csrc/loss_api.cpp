@@ -890,6 +890,17 @@ loss_status upload_axis(loss_sim *s, int axis)
     std::vector<float4> adjw(n);
     for (int j = 0; j < n; ++j)
         adjw[j] = make_float4(j > 0 ? (float)h.cp[j - 1] : 0.f, (float)h.c0[j], j < h.N ? (float)h.cm[j + 1] : 0.f, 0.f);
+    // columns of the plain interior form, without transposed PMBC taps (the gather
+    // reads no table for them)
+    const float s3f = (float)(3.0 / h.h);
+    const float4 plain4 = make_float4(s3f, 0.f, -s3f, 0.f);
+    std::vector<unsigned> plain((n + 31) / 32, 0u);
+    for (int j = 0; j < n; ++j) {
+        bool ok = adjw[j].x == plain4.x && adjw[j].y == plain4.y && adjw[j].z == plain4.z;
+        for (int t = 0; t < kMaxGatherTaps; ++t) ok = ok && h.g_node[(size_t)j * kMaxGatherTaps + t] < 0;
+        if (ok) plain[j >> 5] |= 1u << (j & 31);
+    }
+    unsigned *dplain;
     float4 *dadjw;
     std::copy(h.tap_c.begin(), h.tap_c.end(), tc.begin());
     float4 *dlu, *drc, *dluT, *dlu2;
@@ -902,8 +913,10 @@ loss_status upload_axis(loss_sim *s, int axis)
         (r = s->alloc(&dlum2, np)) ||
         (r = s->alloc(&dti, std::max<size_t>(1, h.tap_idx.size()))) ||
         (r = s->alloc(&dtc, tc.size())) ||
-        (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())) || (r = s->alloc(&dadjw, n)))
+        (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())) || (r = s->alloc(&dadjw, n)) ||
+        (r = s->alloc(&dplain, plain.size())))
         return r;
+    HIPCHK(hipMemcpy(dplain, plain.data(), plain.size() * sizeof(unsigned), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dlu, lu.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(drc, rc.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dluT, luT.data(), np * sizeof(float4), hipMemcpyHostToDevice));
@@ -927,6 +940,7 @@ loss_status upload_axis(loss_sim *s, int axis)
     d.lum = dlum; d.lum2 = dlum2;
     d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
     d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc; d.adjw = dadjw;
+    d.plain = dplain; d.adjw_plain = plain4;
     return LOSS_OK;
 }
 
@@ -1368,7 +1382,7 @@ loss_status loss_set_shape(loss_sim *s, int32_t axis, int32_t shape)
         s->cx = shape;
     } else {
         const int cw = shape / 100, cs = shape % 100;
-        if (shape != 0 && !((cw == 16 || cw == 32 || cw == 64) && (cs == 8 || cs == 16)))
+        if (shape != 0 && !((cw == 8 || cw == 16 || cw == 32 || cw == 64) && (cs == 8 || cs == 16)))
             return fail(LOSS_EINVAL, "bad y/z shape");
         s->cw[axis] = cw;
         s->cs[axis] = cs;

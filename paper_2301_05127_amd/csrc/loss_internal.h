@@ -78,6 +78,8 @@ struct AxisDev {
     const int *g_node;     // [N+1][kMaxGatherTaps]
     const float *g_c;
     const float4 *adjw;    // [N+1] {c+ of row j-1, c0 of row j, c- of row j+1, 0}: column j of G's stencil
+    const unsigned *plain; // bit j: column j is {s3, 0, -s3, 0} and no junction row's taps reach node j
+    float4 adjw_plain;     // that column
     const float4 *pml;     // [N+1] absorbing layer {beta = d/k + alpha, d/k^2, 1/k, 0}, or null
     int pml_w;             // layer width in nodes (nodes j < pml_w or j > N - pml_w)
 };

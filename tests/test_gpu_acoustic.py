@@ -178,7 +178,7 @@ def test_set_get_field_roundtrip_and_restart(orc):
     a.close(); b.close(); c.close()
 
 
-@pytest.mark.parametrize("shape", [None, (8, 0, 1608), (4, 0, 3216), (16, 0, 6416)])
+@pytest.mark.parametrize("shape", [None, (8, 0, 1608), (4, 0, 3216), (16, 0, 6416), (8, 0, 808)])
 def test_cfg2_full_size_few_steps(orc, shape):
     """2048x2048 intervals, 8x8 patches of 256, halo 12, GRF medium: 6 steps at full
     size, in the launch shapes the benchmark chooses among (x nodes per lane; z columns
