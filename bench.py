@@ -40,10 +40,11 @@ ALGO_BYTES = {
         "velocity_line_z": 16,   # read sigma, v3, b; write v3
         "velocity_stress_x": 20,  # read sigma, v1, b; write v1 and T = d(v1 new)/dx
     },
-    1: {  # elastic, per axis: one normal-stress pass (read v_i, 3 sigma, lambda, lambda+2mu;
-          # write 3 sigma: 36 B) and two shear passes (read v, sigma_ij, mu; write sigma_ij:
-          # 16 B) -> 68 B over 3 launches; velocity passes read sigma_ij, v_i, b, write v_i
-        "stress_line_x": 68 / 3, "stress_line_y": 68 / 3, "stress_line_z": 68 / 3,
+    1: {  # elastic stress passes per axis: x and y store d_i v_i (read v_i, write T_i: 8 B),
+          # z updates the three normal stresses (read v3, T1, T2, 3 sigma, lambda,
+          # lambda+2mu; write 3 sigma: 44 B); two shear passes per axis (read v, sigma_ij,
+          # mu; write sigma_ij: 16 B); velocity passes read sigma_ij, v_i, b, write v_i
+        "stress_line_x": 40 / 3, "stress_line_y": 40 / 3, "stress_line_z": 76 / 3,
         "velocity_line_x": 16, "velocity_line_y": 16, "velocity_line_z": 16,
     },
 }

@@ -128,6 +128,19 @@ __device__ __forceinline__ float epilogue(const LineArgs &a, int64_t oidx, int64
         a.out[0][oidx] = v;
         if (a.div) a.div[(int64_t)shot * a.div_shot_stride + midx] = dv;
         return v;
+    } else if constexpr (EPI == EPI_NORMAL3) {
+        const float t[3] = {a.aux[oidx], a.aux2[oidx], D};
+        const float l2m = a.coef[0][midx], lam = a.coef[1][midx];
+        float v0 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float other = j == 0 ? t[1] + t[2] : (j == 1 ? t[0] + t[2] : t[0] + t[1]);
+            float v = fmaf(a.alpha, fmaf(l2m, t[j], lam * other), a.out[j][oidx]);
+            if (srcs && a.src) v += source_terms(a, j, shot, x, y, z, midx);
+            a.out[j][oidx] = v;
+            if (j == 0) v0 = v;
+        }
+        return v0;
     } else {  // EPI_BASE
         const float c = a.coef[0] ? a.coef[0][midx] : 1.f;
         const float v = fmaf(a.alpha * c, D, a.aux[oidx]);
@@ -824,7 +837,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
         }
     }
     // epilogue operands (small chunks only: they cost 3 registers per node)
-    constexpr bool kPre = C <= 8;
+    constexpr bool kPre = C <= 8 && EPI != EPI_NORMAL3;
     Pre pre[kPre ? C : 1];
     if constexpr (kPre) {
 #pragma unroll
@@ -1421,6 +1434,10 @@ hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
             case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY, true>), grid, threads, shm, st, a, axis, CW, gx); break;
             case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX, true>), grid, threads, shm, st, a, axis, CW, gx); break;
             case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE, true>), grid, threads, shm, st, a, axis, CW, gx); break;
+            case EPI_NORMAL3:
+                if constexpr (SOLVE != SOLVE_D1) return hipErrorInvalidValue;
+                else hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_NORMAL3, true>), grid, threads, shm, st, a, axis, CW, gx);
+                break;
             default: return hipErrorInvalidValue;
             }
             return hipGetLastError();
@@ -1431,6 +1448,10 @@ hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
     case EPI_AXPY: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY, false>), grid, threads, shm, st, a, axis, CW, gx); break;
     case EPI_AXPY_AUX: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_AXPY_AUX, false>), grid, threads, shm, st, a, axis, CW, gx); break;
     case EPI_BASE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_BASE, false>), grid, threads, shm, st, a, axis, CW, gx); break;
+    case EPI_NORMAL3:
+        if constexpr (SOLVE != SOLVE_D1) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_NORMAL3, false>), grid, threads, shm, st, a, axis, CW, gx);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -455,21 +455,28 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
     }
     float *const *F = s->f.data();
     const float *lam = s->med[0], *mu = s->med[1], *l2m = s->med[2];
-    // normal components from d_i v_i
-    for (int i = 0; i < 3; ++i) {
+    // normal components: T1 = d1 v1 and T2 = d2 v2 stored, then the z pass updates all
+    // three from T1, T2 and d3 v3: sigma_ii += (lambda + 2 mu) d_i v_i + lambda (sum of
+    // the other two) (media hold dt lambda, dt mu, dt (lambda + 2 mu))
+    for (int i = 0; i < 2; ++i) {
         LineArgs a = base_args(s, i);
         a.in = F[LOSS_F_EV1 + i];
+        a.out[0] = s->tmp[i];
+        if ((r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_STORE, a))) return r;
+    }
+    {
+        LineArgs a = base_args(s, 2);
+        a.in = F[LOSS_F_EV3];
         a.alpha = 1.f;
         a.nout = 3;
         a.out[0] = F[LOSS_F_S11]; a.out[1] = F[LOSS_F_S22]; a.out[2] = F[LOSS_F_S33];
-        a.coef[0] = a.coef[1] = a.coef[2] = lam;
-        a.coef[i] = l2m;
-        if (i == 2) {
-            const int fid[3] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33};
-            attach_sources(s, a, -1, fid, 3, false);
-        }
-        r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_AXPY, a);
-        if (r) return r;
+        a.coef[0] = l2m;
+        a.coef[1] = lam;
+        a.aux = s->tmp[0];
+        a.aux2 = s->tmp[1];
+        const int fid[3] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33};
+        attach_sources(s, a, -1, fid, 3, false);
+        if ((r = run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_NORMAL3, a))) return r;
     }
     // shear components: sigma_ij += dt mu (d_i v_j + d_j v_i)
     static const int sh[3][3] = {{LOSS_F_S12, 0, 1}, {LOSS_F_S13, 0, 2}, {LOSS_F_S23, 1, 2}};

@@ -90,6 +90,8 @@ enum EpiKind : int {
     EPI_AXPY = 1,         // out_j += alpha * coef_j * D       (j < nout, coef_j may be null)
     EPI_AXPY_AUX = 2,     // out0 += alpha * coef0 * (D + aux); optional div store: div = D + aux
     EPI_BASE = 3,         // out0 = aux + alpha * coef0 * D
+    EPI_NORMAL3 = 4,      // elastic normal stresses, this pass the last of d1 v1 = aux, d2 v2 = aux2,
+                          // d3 v3 = D: out_i += alpha (coef0 d_i v_i + coef1 (sum of the other two))
 };
 
 // Which system the line kernel solves.
@@ -107,6 +109,7 @@ struct LineArgs {
     float *out[3];
     const float *coef[3];
     const float *aux;
+    const float *aux2;     // second auxiliary field (EPI_NORMAL3)
     float *div;            // optional store of D + aux (EPI_AXPY_AUX)
     int64_t div_shot_stride;
     float alpha;
