@@ -40,12 +40,15 @@ ALGO_BYTES = {
         "velocity_line_z": 16,   # read sigma, v3, b; write v3
         "velocity_stress_x": 20,  # read sigma, v1, b; write v1 and T = d(v1 new)/dx
     },
-    1: {  # elastic stress passes per axis: x and y store d_i v_i (read v_i, write T_i: 8 B),
-          # z updates the three normal stresses (read v3, T1, T2, 3 sigma, lambda,
-          # lambda+2mu; write 3 sigma: 44 B); two shear passes per axis (read v, sigma_ij,
-          # mu; write sigma_ij: 16 B); velocity passes read sigma_ij, v_i, b, write v_i
-        "stress_line_x": 40 / 3, "stress_line_y": 40 / 3, "stress_line_z": 76 / 3,
-        "velocity_line_x": 16, "velocity_line_y": 16, "velocity_line_z": 16,
+    1: {  # elastic stress passes: x stores d1 v1, d1 v2, d1 v3 (read v, write T: 8 B each);
+          # y stores d2 v2, d2 v3 (8 B each) and adds mu (d2 v1 + T) to sigma12 (read v1,
+          # T, sigma12, mu; write sigma12: 20 B); z updates the three normal stresses (read
+          # v3, T1, T2, 3 sigma, lambda, lambda+2mu; write 3 sigma: 44 B) and sigma13,
+          # sigma23 (20 B each); velocity, per component: x stores T = d1 sigma_i1 (8 B),
+          # y adds d2 sigma_i2 to T (read sigma, T; write T: 12 B), z updates v_i (read
+          # sigma_i3, T, v_i, b; write v_i: 20 B)
+        "stress_line_x": 24 / 3, "stress_line_y": 36 / 3, "stress_line_z": 84 / 3,
+        "velocity_line_x": 8, "velocity_line_y": 12, "velocity_line_z": 20,
     },
 }
 STEP_BYTES = {0: 44, 1: 120}   # compulsory bytes per cell-step (whole step)

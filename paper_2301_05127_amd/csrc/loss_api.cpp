@@ -213,18 +213,6 @@ loss_status run_line(loss_sim *s, int kc, int axis, int solve, int epi, const Li
     return timed_end(s, kc);
 }
 
-// derivative of field `in` along axis, out[j] += alpha * coef[j] * D
-loss_status deriv_axpy(loss_sim *s, int kc, int axis, const float *in, float alpha, int nout,
-                       float *const *out, const float *const *coef)
-{
-    LineArgs a = base_args(s, axis);
-    a.in = in;
-    a.alpha = alpha;
-    a.nout = nout;
-    for (int j = 0; j < nout; ++j) { a.out[j] = out[j]; a.coef[j] = coef[j]; }
-    return run_line(s, kc, axis, SOLVE_D1, EPI_AXPY, a);
-}
-
 // Let the epilogue of a line kernel add the sources whose fields are among out_field.
 // Stress sources are added as dt * s(t) * weight; body forces as (dt b) * f(t) * weight
 // with dt b taken from the media array, so their scale is 1.
@@ -345,6 +333,33 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
     static const int sidx[3][3] = {{LOSS_F_S11, LOSS_F_S12, LOSS_F_S13},
                                    {LOSS_F_S12, LOSS_F_S22, LOSS_F_S23},
                                    {LOSS_F_S13, LOSS_F_S23, LOSS_F_S33}};
+    if (!base) {
+        // T = d_x sigma_{i1} (stored), T += d_y sigma_{i2}, v_i += frac b (T + d_z sigma_{i3})
+        for (int i = 0; i < 3; ++i) {
+            float *T = s->tmp[i];
+            LineArgs x = base_args(s, 0);
+            x.in = s->f[sidx[i][0]];
+            x.out[0] = T;
+            if ((r = run_line(s, KC_VEL_X, 0, SOLVE_D1, EPI_STORE, x))) return r;
+            LineArgs y = base_args(s, 1);
+            y.in = s->f[sidx[i][1]];
+            y.alpha = 1.f;
+            y.out[0] = T;
+            if ((r = run_line(s, KC_VEL_Y, 1, SOLVE_D1, EPI_AXPY, y))) return r;
+            LineArgs z = base_args(s, 2);
+            z.in = s->f[sidx[i][2]];
+            z.alpha = frac;
+            z.out[0] = vel[i];
+            z.coef[0] = b;
+            z.aux = T;
+            if (with_forces) {
+                const int fid = LOSS_F_EV1 + i;
+                attach_sources(s, z, 0, &fid, 1, true);
+            }
+            if ((r = run_line(s, KC_VEL_Z, 2, SOLVE_D1, EPI_AXPY_AUX, z))) return r;
+        }
+        return LOSS_OK;
+    }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             LineArgs a = base_args(s, j);
@@ -478,16 +493,24 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         attach_sources(s, a, -1, fid, 3, false);
         if ((r = run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_NORMAL3, a))) return r;
     }
-    // shear components: sigma_ij += dt mu (d_i v_j + d_j v_i)
+    // shear components: T = d_i v_j stored, then sigma_ij += dt mu (d_j v_i + T)
     static const int sh[3][3] = {{LOSS_F_S12, 0, 1}, {LOSS_F_S13, 0, 2}, {LOSS_F_S23, 1, 2}};
     for (int k = 0; k < 3; ++k) {
         const int sij = sh[k][0], i = sh[k][1], j = sh[k][2];
-        float *out[1] = {F[sij]};
-        const float *coef[1] = {mu};
-        r = deriv_axpy(s, KC_STRESS_X + i, i, F[LOSS_F_EV1 + j], 1.f, 1, out, coef);
-        if (r) return r;
-        r = deriv_axpy(s, KC_STRESS_X + j, j, F[LOSS_F_EV1 + i], 1.f, 1, out, coef);
-        if (r) return r;
+        LineArgs t = base_args(s, i);
+        t.in = F[LOSS_F_EV1 + j];
+        t.out[0] = s->tmp[k];
+        if ((r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_STORE, t))) return r;
+    }
+    for (int k = 0; k < 3; ++k) {
+        const int sij = sh[k][0], i = sh[k][1], j = sh[k][2];
+        LineArgs a = base_args(s, j);
+        a.in = F[LOSS_F_EV1 + i];
+        a.alpha = 1.f;
+        a.out[0] = F[sij];
+        a.coef[0] = mu;
+        a.aux = s->tmp[k];
+        if ((r = run_line(s, KC_STRESS_X + j, j, SOLVE_D1, EPI_AXPY_AUX, a))) return r;
     }
     return LOSS_OK;
 }
