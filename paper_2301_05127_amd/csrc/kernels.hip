@@ -1141,6 +1141,7 @@ __global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
     constexpr int PF = C + 1;
     const int nthr = blockDim.x;
     Pre pre[PF];
+    unsigned pw[PF];   // words of the plain-column bits of those nodes
     float zJ = 0.f;
     auto val = [&](int i) { return icf ? in[i] * icf[i] : in[i]; };
     auto issue = [&]() {
@@ -1148,6 +1149,7 @@ __global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
         for (int r = 0; r < PF; ++r) {
             const int i = min((int)threadIdx.x + r * nthr, N);
             pre[r] = pre_load<EPI>(a, base + i, mbase + i);
+            pw[r] = ax.plain[i >> 5];
         }
         zJ = val(J);
     };
@@ -1187,15 +1189,10 @@ __global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
         ys[s] = v;
     }
     __syncthreads();
-    // (G^T y)_i: stencil column i, then the transposed PMBC rows reaching node i
-    auto gather = [&](int i) {
-        float4 aw = ax.adjw_plain, gc = make_float4(0.f, 0.f, 0.f, 0.f);
-        int4 gn = make_int4(-1, -1, -1, -1);
-        if (!((ax.plain[i >> 5] >> (i & 31)) & 1u)) {
-            aw = ax.adjw[i];
-            gn = *reinterpret_cast<const int4 *>(ax.g_node + (int64_t)i * kMaxGatherTaps);
-            gc = *reinterpret_cast<const float4 *>(ax.g_c + (int64_t)i * kMaxGatherTaps);
-        }
+    // (G^T y)_i: stencil column i, then the transposed PMBC rows reaching node i.
+    // Plain columns ({s3, 0, -s3}, no PMBC row) first, from the bits read ahead; the
+    // others (rows near junctions and ends) from the packed table, one entry per thread.
+    auto col = [&](int i, float4 aw, int4 gn, float4 gc) {
         float o = aw.y * ys[i];
         o = fmaf(aw.x, ys[max(i - 1, 0)], o);
         o = fmaf(aw.z, ys[min(i + 1, N)], o);
@@ -1205,14 +1202,26 @@ __global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
         if (gn.w >= 0) o = fmaf(gc.w, ys[gn.w], o);
         return o;
     };
+    const int4 none = make_int4(-1, -1, -1, -1);
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int r = 0; r < PF; ++r) {
         const int i = (int)threadIdx.x + r * nthr;
-        if (i <= N) epilogue_pre<EPI>(a, base + i, mbase + i, shot, gather(i), pre[r], i, 0, 0, false);
+        if (i <= N && ((pw[r] >> (i & 31)) & 1u))
+            epilogue_pre<EPI>(a, base + i, mbase + i, shot, col(i, ax.adjw_plain, none, zero4), pre[r], i, 0, 0,
+                              false);
     }
     for (int i = (int)threadIdx.x + PF * nthr; i <= N; i += nthr) {
+        if ((ax.plain[i >> 5] >> (i & 31)) & 1u) {
+            const Pre pr = pre_load<EPI>(a, base + i, mbase + i);
+            epilogue_pre<EPI>(a, base + i, mbase + i, shot, col(i, ax.adjw_plain, none, zero4), pr, i, 0, 0, false);
+        }
+    }
+    for (int k = threadIdx.x; k < ax.nspec; k += nthr) {
+        const SpecialCol sc = ax.spec[k];
+        const int i = sc.row;
         const Pre pr = pre_load<EPI>(a, base + i, mbase + i);
-        epilogue_pre<EPI>(a, base + i, mbase + i, shot, gather(i), pr, i, 0, 0, false);
+        epilogue_pre<EPI>(a, base + i, mbase + i, shot, col(i, sc.aw, sc.gn, sc.gc), pr, i, 0, 0, false);
     }
 }
 

@@ -930,7 +930,19 @@ loss_status upload_axis(loss_sim *s, int axis)
         for (int t = 0; t < kMaxGatherTaps; ++t) ok = ok && h.g_node[(size_t)j * kMaxGatherTaps + t] < 0;
         if (ok) plain[j >> 5] |= 1u << (j & 31);
     }
+    std::vector<SpecialCol> spec;
+    for (int j = 0; j < n; ++j) {
+        if ((plain[j >> 5] >> (j & 31)) & 1u) continue;
+        SpecialCol sc{};
+        sc.aw = adjw[j];
+        const size_t g = (size_t)j * kMaxGatherTaps;
+        sc.gn = make_int4(h.g_node[g], h.g_node[g + 1], h.g_node[g + 2], h.g_node[g + 3]);
+        sc.gc = make_float4(gc[g], gc[g + 1], gc[g + 2], gc[g + 3]);
+        sc.row = j;
+        spec.push_back(sc);
+    }
     unsigned *dplain;
+    SpecialCol *dspec;
     float4 *dadjw;
     std::copy(h.tap_c.begin(), h.tap_c.end(), tc.begin());
     float4 *dlu, *drc, *dluT, *dlu2;
@@ -944,8 +956,10 @@ loss_status upload_axis(loss_sim *s, int axis)
         (r = s->alloc(&dti, std::max<size_t>(1, h.tap_idx.size()))) ||
         (r = s->alloc(&dtc, tc.size())) ||
         (r = s->alloc(&dgn, h.g_node.size())) || (r = s->alloc(&dgc, gc.size())) || (r = s->alloc(&dadjw, n)) ||
-        (r = s->alloc(&dplain, plain.size())))
+        (r = s->alloc(&dplain, plain.size())) || (r = s->alloc(&dspec, std::max<size_t>(1, spec.size()))))
         return r;
+    if (!spec.empty())
+        HIPCHK(hipMemcpy(dspec, spec.data(), spec.size() * sizeof(SpecialCol), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dplain, plain.data(), plain.size() * sizeof(unsigned), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dlu, lu.data(), n * sizeof(float4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(drc, rc.data(), n * sizeof(float4), hipMemcpyHostToDevice));
@@ -971,6 +985,7 @@ loss_status upload_axis(loss_sim *s, int axis)
     d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
     d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc; d.adjw = dadjw;
     d.plain = dplain; d.adjw_plain = plain4;
+    d.spec = dspec; d.nspec = (int)spec.size();
     return LOSS_OK;
 }
 

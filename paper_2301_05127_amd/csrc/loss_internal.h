@@ -59,6 +59,15 @@ struct AxisHost {
 // Build the tables; returns an empty string on success, else the reason.
 std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_mode);
 
+// A node whose column of G^T is not the plain interior form: its stencil column and
+// the transposed PMBC rows reaching it (gather of the adjoint x pass).
+struct SpecialCol {
+    float4 aw;             // {c+ of row j-1, c0 of row j, c- of row j+1, 0}
+    float4 gc;             // coefficients of the junction rows in gn
+    int4 gn;               // junction rows reaching the node (-1 = none)
+    int row, pad0, pad1, pad2;
+};
+
 // Device copy of one axis (float32).
 struct AxisDev {
     int N, M, p, ntap, halo, periodic;
@@ -80,6 +89,8 @@ struct AxisDev {
     const float4 *adjw;    // [N+1] {c+ of row j-1, c0 of row j, c- of row j+1, 0}: column j of G's stencil
     const unsigned *plain; // bit j: column j is {s3, 0, -s3, 0} and no junction row's taps reach node j
     float4 adjw_plain;     // that column
+    const SpecialCol *spec;  // the other nodes, by row
+    int nspec;
     const float4 *pml;     // [N+1] absorbing layer {beta = d/k + alpha, d/k^2, 1/k, 0}, or null
     int pml_w;             // layer width in nodes (nodes j < pml_w or j > N - pml_w)
 };
