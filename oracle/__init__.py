@@ -214,6 +214,8 @@ def run(g, physics, dt, nsteps, vp, rho, vs=None, sources=(), receivers=None, re
     fields = np.zeros((nf,) + shape)
     traces = np.zeros((nrec, nsteps))
     fin = _f64(fields_in) if fields_in is not None else None
+    if fin is not None and fin.shape != fields.shape:
+        raise ValueError("fields_in must have shape %s" % (fields.shape,))
     gs = _grid(g)
     rc = lib().or_run_from(ctypes.byref(gs), physics, float(dt), int(step0), int(nsteps), _dp(vp),
                            _dp(vs), _dp(rho), len(keep), src, nrec, _ip(rec), int(rec_comp),
@@ -244,6 +246,8 @@ def run_pml(g, pml, dt, nsteps, vp, rho, sources=(), receivers=None, fields_in=N
     fields = np.zeros((7,) + shape)
     traces = np.zeros((rec.shape[0], nsteps))
     fin = _f64(fields_in) if fields_in is not None else None
+    if fin is not None and fin.shape != fields.shape:
+        raise ValueError("fields_in must have shape %s (sigma, v1, v3 and four memory variables)" % (fields.shape,))
     p = _Pml(int(pml["width"]), float(pml["R"]), float(pml["kmax"]), float(pml["f0"]), float(pml["cmax"]))
     gs = _grid(g)
     rc = lib().or_run_pml(ctypes.byref(gs), ctypes.byref(p), float(dt), int(step0), int(nsteps), _dp(vp), _dp(rho),

@@ -190,3 +190,42 @@ def test_fused_x_adjoint_gradient_bitwise_equal():
         grads.append(sim.adjoint(res, loss.GRAD_K))
         sim.close()
     assert np.array_equal(grads[0], grads[1])
+
+
+@pytest.mark.timeout(400)   # the FP64 oracle adjoint takes ~30 s per shot at this size
+def test_gradient_full_size_few_steps(orc):
+    """1025^2 nodes, patches of 128, halo 12, 1024 receivers per shot (the batched-adjoint
+    workload's grid), 2 shots, 12 steps with checkpoints every 5, in the launch shape of
+    the benchmark: dJ/dK against the FP64 oracle adjoint for J = 1/2 sum d^2."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    nsteps = 12
+    w = inputs.config("cfg5", nshots=2, nsteps=nsteps)
+    for s, sh in enumerate(w["shots"]):   # sources already active in the first steps
+        sh["sources"][0]["wavelet"] = inputs.ricker(15.0, 0.004 + 0.002 * s, w["dt"], nsteps + 1, 0.5)
+    w = _f32_adj(w)
+    announce("gradient full size 2 shots %d steps" % nsteps)
+    resid, g_ref = [], np.zeros((1025, 1025))
+    for sh in w["shots"]:
+        d = orc.run(w["grid"], 0, w["dt"], nsteps, w["vp"], w["rho"], sources=sh["sources"],
+                    receivers=sh["receivers"])[1]
+        resid.append(d)
+        g_ref += orc.acoustic_adjoint(w["grid"], w["dt"], nsteps, w["vp"], w["rho"], sh["sources"],
+                                      sh["receivers"], d)
+    sim = loss.Simulation(w["grid"], 0, w["dt"], nshots=2, trace_len=nsteps)
+    sim.setup_workload(w)
+    sim.set_shape([8, None, 1608])
+    sim.forward_ckpt(nsteps, 5)
+    g = sim.adjoint(np.concatenate([r.ravel() for r in resid]), loss.GRAD_K)
+    e = rel_l2(g, g_ref)
+    assert np.abs(g_ref).max() > 0 and e < 1e-4, e
+    sim.close()
+
+
+def _f32_adj(w):
+    w = dict(w)
+    w["vp"] = np.asarray(w["vp"], np.float32).astype(np.float64)
+    w["rho"] = np.asarray(w["rho"], np.float32).astype(np.float64)
+    w["shots"] = [dict(sh, sources=[dict(s, wavelet=np.asarray(s["wavelet"], np.float32).astype(np.float64))
+                                    for s in sh["sources"]]) for sh in w["shots"]]
+    return w

@@ -102,3 +102,35 @@ def test_pml_restart_through_fields():
     for f in range(3):
         assert rel_l2(b.get_field(f), a.get_field(f)) < 1e-5, f
     a.close(); b.close()
+
+
+@pytest.mark.parametrize("shape", [None, (8, 0, 1608)])
+def test_pml_full_size_few_steps(orc, shape):
+    """2048^2 intervals, patches of 256, halo 12, a 50-node layer on every side: a
+    pressure pulse centred inside the layer near a corner, 8 steps, every field against
+    the oracle's layer, in the launch shapes the benchmark chooses among."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    w = inputs.config("cfg2", nsteps=8)
+    w["vp"] = np.asarray(w["vp"], np.float32).astype(np.float64)
+    sh = w["shots"][0]
+    for src in sh["sources"]:
+        src["wavelet"] = np.asarray(src["wavelet"], np.float32).astype(np.float64)
+    announce("pml full size 8 steps, shape %s" % (shape,))
+    sim = loss.Simulation(w["grid"], 0, w["dt"], nshots=1, trace_len=8)
+    sim.setup_workload(w)
+    sim.set_pml(50, 1e-6, 1.0, 20.0)
+    if shape:
+        sim.set_shape(shape)
+    z, x = np.meshgrid(np.arange(2049), np.arange(2049), indexing="ij")
+    sig0 = np.exp(-((x - 40.0) ** 2 + (z - 2000.0) ** 2) / (2 * 15.0 ** 2)).astype(np.float32)
+    sim.set_field(0, sig0)
+    sim.step(8)
+    fin = np.zeros((7, 2049, 2049))   # sigma, v1, v3 and the layer's four memory variables
+    fin[0] = sig0
+    pml = dict(width=50, R=1e-6, kmax=1.0, f0=20.0, cmax=float(w["vp"].max()))
+    rf, _ = orc.run_pml(w["grid"], pml, w["dt"], 8, w["vp"], w["rho"], sources=sh["sources"],
+                        receivers=sh["receivers"], fields_in=fin)
+    for f in range(3):
+        assert rel_l2(sim.get_field(f), rf[f]) < 1e-5, f
+    sim.close()
