@@ -1110,61 +1110,34 @@ __global__ void __launch_bounds__(256) k_adj_gather_s(LineArgs a, const float *_
 // patch-interior solve of T^T y = z, the junction rows of T^T, then G^T y, with y kept
 // in LDS between them.  Same arithmetic, in the same order, as the solve / junction /
 // gather kernels above.
-template <int C, int EPI>
-__global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
+// One adjoint pass along x of the line held by the workgroup (every thread calls it;
+// barriers inside): the patch-interior solve of T^T y = z with z_i = val(i), y to the
+// LDS line ys, the junction rows, then for every node i the value (G^T y)_i handed to
+// emit(i, D, r), where r is the thread's read-ahead slot of node i (node i = thread +
+// r * blockDim for r < C + 1, read ahead by issue() together with the plain-column
+// bits pw), or -1.  Plain columns ({s3, 0, -s3}, no PMBC row) need no table; the
+// others (rows near junctions and ends) come from the packed table, one entry per
+// thread.  Same arithmetic, in the same order, as the solve / junction / gather kernels.
+template <int C, typename Val, typename Val4, typename Issue, typename Emit>
+__device__ __forceinline__ void adj_x_pass(const AxisDev &ax, int G, float *ys, const unsigned *pw, Val val, Val4 val4,
+                                           Issue issue, Emit emit)
 {
-    extern __shared__ float4 lds4[];
-    float *ys = reinterpret_cast<float *>(lds4);
-    const AxisDev &ax = a.ax;
     const int N = ax.N, M = ax.M, p = ax.p;
     const int k = threadIdx.x & (G - 1);
     const int lraw = threadIdx.x / G;
     const bool uact = lraw < p;
     const int l = min(lraw, p - 1);
-    const int line = blockIdx.x;
-    const int lps = a.nz * a.ny;
-    const int shot = line / lps;
-    const int64_t base = (int64_t)line * a.pitch;
-    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
     const int s = l * M;
     const int e = min(s + M, N);
     const int kc = (e - 1 - s) / C;
-    const float *__restrict__ in = a.in + base;
-    const float *__restrict__ icf = a.in_coef ? a.in_coef + mbase : nullptr;
     // junction rows owned here: row s (lane 0; not at a natural end), row N (closing
     // lane of the last patch, junction ends only)
     const bool js = uact && k == 0 && (ax.ends != 0 || s > 0);
     const bool jn = uact && ax.ends != 0 && e == N && k == kc;
     const int J = jn ? N : s;
-    // the gather phase gives node i to thread i mod blockDim (coalesced tables and
-    // output); its first PF output values are read ahead of the solve
-    constexpr int PF = C + 1;
-    const int nthr = blockDim.x;
-    Pre pre[PF];
-    unsigned pw[PF];   // words of the plain-column bits of those nodes
     float zJ = 0.f;
-    auto val = [&](int i) { return icf ? in[i] * icf[i] : in[i]; };
-    auto issue = [&]() {
-#pragma unroll
-        for (int r = 0; r < PF; ++r) {
-            const int i = min((int)threadIdx.x + r * nthr, N);
-            pre[r] = pre_load<EPI>(a, base + i, mbase + i);
-            pw[r] = ax.plain[i >> 5];
-        }
-        zJ = val(J);
-    };
     float w[C];
-    float we = x_unit<C, SOLVE_T1>(
-        ax, k, G, l, true, val,
-        [&](int i) {
-            float4 v = ld4(in + i);
-            if (icf) {
-                const float4 c = ld4(icf + i);
-                v = make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
-            }
-            return v;
-        },
-        issue, w);
+    float we = x_unit<C, SOLVE_T1>(ax, k, G, l, true, val, val4, [&]() { issue(); zJ = val(J); }, w);
     const int q = s + k * C;
     if (uact) {
 #pragma unroll
@@ -1189,9 +1162,6 @@ __global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
         ys[s] = v;
     }
     __syncthreads();
-    // (G^T y)_i: stencil column i, then the transposed PMBC rows reaching node i.
-    // Plain columns ({s3, 0, -s3}, no PMBC row) first, from the bits read ahead; the
-    // others (rows near junctions and ends) from the packed table, one entry per thread.
     auto col = [&](int i, float4 aw, int4 gn, float4 gc) {
         float o = aw.y * ys[i];
         o = fmaf(aw.x, ys[max(i - 1, 0)], o);
@@ -1204,25 +1174,138 @@ __global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
     };
     const int4 none = make_int4(-1, -1, -1, -1);
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int nthr = blockDim.x;
 #pragma unroll
-    for (int r = 0; r < PF; ++r) {
+    for (int r = 0; r < C + 1; ++r) {
         const int i = (int)threadIdx.x + r * nthr;
-        if (i <= N && ((pw[r] >> (i & 31)) & 1u))
-            epilogue_pre<EPI>(a, base + i, mbase + i, shot, col(i, ax.adjw_plain, none, zero4), pre[r], i, 0, 0,
-                              false);
+        if (i <= N && ((pw[r] >> (i & 31)) & 1u)) emit(i, col(i, ax.adjw_plain, none, zero4), r);
     }
-    for (int i = (int)threadIdx.x + PF * nthr; i <= N; i += nthr) {
-        if ((ax.plain[i >> 5] >> (i & 31)) & 1u) {
-            const Pre pr = pre_load<EPI>(a, base + i, mbase + i);
-            epilogue_pre<EPI>(a, base + i, mbase + i, shot, col(i, ax.adjw_plain, none, zero4), pr, i, 0, 0, false);
+    for (int i = (int)threadIdx.x + (C + 1) * nthr; i <= N; i += nthr)
+        if ((ax.plain[i >> 5] >> (i & 31)) & 1u) emit(i, col(i, ax.adjw_plain, none, zero4), -1);
+    for (int t = threadIdx.x; t < ax.nspec; t += nthr) {
+        const SpecialCol sc = ax.spec[t];
+        emit(sc.row, col(sc.row, sc.aw, sc.gn, sc.gc), -1);
+    }
+}
+
+// The three adjoint phases of an x pass in one block per line (p*G lanes), y in LDS.
+template <int C, int EPI>
+__global__ void __launch_bounds__(512) k_adj_x(LineArgs a, int G)
+{
+    extern __shared__ float4 lds4[];
+    float *ys = reinterpret_cast<float *>(lds4);
+    const AxisDev &ax = a.ax;
+    const int N = ax.N;
+    const int line = blockIdx.x;
+    const int lps = a.nz * a.ny;
+    const int shot = line / lps;
+    const int64_t base = (int64_t)line * a.pitch;
+    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
+    const float *__restrict__ in = a.in + base;
+    const float *__restrict__ icf = a.in_coef ? a.in_coef + mbase : nullptr;
+    constexpr int PF = C + 1;
+    const int nthr = blockDim.x;
+    Pre pre[PF];
+    unsigned pw[PF];
+    auto val = [&](int i) { return icf ? in[i] * icf[i] : in[i]; };
+    auto val4 = [&](int i) {
+        float4 v = ld4(in + i);
+        if (icf) {
+            const float4 c = ld4(icf + i);
+            v = make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
         }
-    }
-    for (int k = threadIdx.x; k < ax.nspec; k += nthr) {
-        const SpecialCol sc = ax.spec[k];
-        const int i = sc.row;
-        const Pre pr = pre_load<EPI>(a, base + i, mbase + i);
-        epilogue_pre<EPI>(a, base + i, mbase + i, shot, col(i, sc.aw, sc.gn, sc.gc), pr, i, 0, 0, false);
-    }
+        return v;
+    };
+    auto issue = [&]() {
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+            const int i = min((int)threadIdx.x + r * nthr, N);
+            pre[r] = pre_load<EPI>(a, base + i, mbase + i);
+            pw[r] = ax.plain[i >> 5];
+        }
+    };
+    auto emit = [&](int i, float D, int r) {
+        Pre pr;
+        if (r >= 0) {
+#pragma unroll
+            for (int t = 0; t < PF; ++t)
+                if (t == r) pr = pre[t];
+        } else {
+            pr = pre_load<EPI>(a, base + i, mbase + i);
+        }
+        epilogue_pre<EPI>(a, base + i, mbase + i, shot, D, pr, i, 0, 0, false);
+    };
+    adj_x_pass<C>(ax, G, ys, pw, val, val4, issue, emit);
+}
+
+// Two adjoint x passes of consecutive reverse steps in one block per line:
+// out += alpha Dx^T(coef in) (the mu1 update from lambda), the updated line kept in
+// LDS, then out2 += alpha2 Dx^T(coef2 out) (the next step's lambda update, which reads
+// only the new mu1); out2 is the array `in`, whose values phase 1 has finished reading.
+template <int C>
+__global__ void __launch_bounds__(512) k_adj_xx(LineArgs a, const float *__restrict__ coef2, float *__restrict__ out2,
+                                                float alpha2, int G)
+{
+    extern __shared__ float4 lds4[];
+    const AxisDev &ax = a.ax;
+    const int N = ax.N;
+    const int nl4 = (N + 4) / 4;
+    float *ys = reinterpret_cast<float *>(lds4);
+    float4 *ms4 = lds4 + nl4;
+    float *ms = reinterpret_cast<float *>(ms4);
+    const int line = blockIdx.x;
+    const int lps = a.nz * a.ny;
+    const int shot = line / lps;
+    const int64_t base = (int64_t)line * a.pitch;
+    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
+    const float *__restrict__ in = a.in + base;
+    const float *__restrict__ icf = a.in_coef + mbase;
+    const float *__restrict__ c2 = coef2 + mbase;
+    float *__restrict__ o1 = a.out[0] + base;
+    float *__restrict__ o2 = out2 + base;
+    constexpr int PF = C + 1;
+    const int nthr = blockDim.x;
+    float p1[PF], p2[PF];   // out and out2 at the thread's first nodes, read ahead
+    unsigned pw[PF];
+    auto issue1 = [&]() {
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+            const int i = min((int)threadIdx.x + r * nthr, N);
+            p1[r] = o1[i];
+            p2[r] = o2[i];
+            pw[r] = ax.plain[i >> 5];
+        }
+    };
+    auto pick = [&](const float (&arr)[PF], int r) {
+        float v = 0.f;
+#pragma unroll
+        for (int t = 0; t < PF; ++t)
+            if (t == r) v = arr[t];
+        return v;
+    };
+    // phase 1: out = out + alpha D^T(coef in), also into LDS
+    adj_x_pass<C>(
+        ax, G, ys, pw, [&](int i) { return in[i] * icf[i]; },
+        [&](int i) {
+            const float4 v = ld4(in + i), c = ld4(icf + i);
+            return make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
+        },
+        issue1,
+        [&](int i, float D, int r) {
+            const float v = fmaf(a.alpha * 1.f, D, r >= 0 ? pick(p1, r) : o1[i]);
+            o1[i] = v;
+            ms[i] = v;
+        });
+    __syncthreads();
+    // phase 2: out2 = out2 + alpha2 D^T(coef2 out_new), out_new from LDS
+    adj_x_pass<C>(
+        ax, G, ys, pw, [&](int i) { return ms[i] * c2[i]; },
+        [&](int i) {
+            const float4 v = ms4[i >> 2], c = ld4(c2 + i);
+            return make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
+        },
+        [] {},
+        [&](int i, float D, int r) { o2[i] = fmaf(alpha2 * 1.f, D, r >= 0 ? pick(p2, r) : o2[i]); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1544,6 +1627,24 @@ hipError_t launch_adj_x(int epi, const LineArgs &a, hipStream_t st)
     case 4: store ? go(k_adj_x<4, EPI_STORE>) : go(k_adj_x<4, EPI_AXPY>); break;
     case 8: store ? go(k_adj_x<8, EPI_STORE>) : go(k_adj_x<8, EPI_AXPY>); break;
     default: store ? go(k_adj_x<16, EPI_STORE>) : go(k_adj_x<16, EPI_AXPY>); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_xx(const LineArgs &a, const float *coef2, float *out2, float alpha2, hipStream_t st)
+{
+    const int threads = line_xx_threads(a);
+    if (!threads || !a.in_coef || !coef2) return hipErrorNotSupported;
+    const int cx = x_chunk(a);
+    int G = 1;
+    while (G * cx < a.ax.M) G <<= 1;
+    const size_t shm = 2 * ((size_t)(a.ax.N + 4) / 4 * 16);
+    const int64_t lines = (int64_t)a.S * a.nz * a.ny;
+    if (lines >= (1ll << 31)) return hipErrorInvalidValue;
+    switch (cx) {
+    case 4: hipLaunchKernelGGL(k_adj_xx<4>, (unsigned)lines, threads, shm, st, a, coef2, out2, alpha2, G); break;
+    case 8: hipLaunchKernelGGL(k_adj_xx<8>, (unsigned)lines, threads, shm, st, a, coef2, out2, alpha2, G); break;
+    default: hipLaunchKernelGGL(k_adj_xx<16>, (unsigned)lines, threads, shm, st, a, coef2, out2, alpha2, G); break;
     }
     return hipGetLastError();
 }

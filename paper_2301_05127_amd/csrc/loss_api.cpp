@@ -46,12 +46,12 @@ struct RecHost {
 // Kernel classes reported by loss_kernel_timing.
 enum KClass {
     KC_STRESS_X, KC_STRESS_Y, KC_STRESS_Z, KC_VEL_X, KC_VEL_Y, KC_VEL_Z, KC_SOURCE, KC_RECEIVER,
-    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_VEL_STRESS_X, KC_ADJ_X, KC_COUNT
+    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_VEL_STRESS_X, KC_ADJ_X, KC_ADJ_XX, KC_COUNT
 };
 const char *kKClassName[KC_COUNT] = {
     "stress_line_x", "stress_line_y", "stress_line_z", "velocity_line_x", "velocity_line_y",
     "velocity_line_z", "source_inject", "receiver_record", "step_advance", "adjoint_line_solve",
-    "adjoint_gather", "gradient_accumulate", "velocity_stress_x", "adjoint_line_x"};
+    "adjoint_gather", "gradient_accumulate", "velocity_stress_x", "adjoint_line_x", "adjoint_line_x_pair"};
 
 }  // namespace
 
@@ -269,6 +269,28 @@ loss_status adj_deriv(loss_sim *s, int axis, const float *in, const float *in_co
     if (e == hipSuccess) e = launch_adj_gather(axis, epi, g, Y, s->st);
     if (e != hipSuccess) return fail(LOSS_EHIP, std::string("adjoint gather: ") + hipGetErrorString(e));
     return timed_end(s, KC_ADJ_GATHER);
+}
+
+// mu1 += -Dx^T(K lam), then lam += -Dx^T(b mu1) with the updated mu1: one kernel when a
+// whole x line fits a workgroup, else the two passes in that order (same arithmetic).
+loss_status adj_x_pair(loss_sim *s, float *lam, const float *K, float *mu1, const float *b, float *Y, int nshots)
+{
+    LineArgs x = base_args(s, 0);
+    x.S = nshots;
+    x.in = lam;
+    x.in_coef = K;
+    x.out[0] = mu1;
+    x.alpha = -1.f;
+    if (!(s->d.flags & LOSS_FLAG_NO_FUSE_X) && line_xx_threads(x) > 0) {
+        loss_status r = timed_begin(s);
+        if (r) return r;
+        const hipError_t e = launch_adj_xx(x, b, lam, -1.f, s->st);
+        if (e != hipSuccess) return fail(LOSS_EHIP, std::string("adjoint x pair: ") + hipGetErrorString(e));
+        return timed_end(s, KC_ADJ_XX);
+    }
+    loss_status r = adj_deriv(s, 0, lam, K, mu1, -1.f, EPI_AXPY, Y, nshots);
+    if (r) return r;
+    return adj_deriv(s, 0, mu1, b, lam, -1.f, EPI_AXPY, Y, nshots);
 }
 
 loss_status inject(loss_sim *s, float **fields_dev, int time_offset, float scale, int want_force)
@@ -1500,6 +1522,7 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
     float *lam = s->adj[0], *mu1 = s->adj[1], *mu3 = s->adj[2], *Y = s->adj[3];
     const float *K = s->med[0], *b = s->med[1];
     const int fid[3] = {LOSS_F_SIGMA, LOSS_F_V1, LOSS_F_V3};
+    bool lam_x_done = false;   // the coming step's lambda x pass already applied
     for (int64_t c = s->ck_nseg - 1; c >= 0; --c) {
         const int64_t n0 = c * s->ck_every, nc = std::min(s->ck_every, s->ck_steps - n0);
         // restore the fused state at step n0 and recompute the segment, keeping div u
@@ -1509,24 +1532,31 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
         HIPCHK(launch_set_step(s->d_step, n0, s->st));
         s->fused = true;
         if ((r = steps_eager(s, nc, s->divstore, ss))) return r;
-        // reverse sweep over the segment
+        // reverse sweep over the segment.  Per step: lambda^{n+1} += -dt Dx^T(b mu1) (done
+        // by the previous step's paired x pass, except at the first reverse step), the
+        // residual, -dt Dz^T(b mu3); dJ/dK += -dt lambda^{n+1} div u^n; then
+        // mu^n = mu^{n+1} - dt D^T(K lambda^{n+1}), whose x pass is paired with the next
+        // step's lambda x pass (media hold dt b, dt K)
         for (int64_t k = nc - 1; k >= 0; --k) {
             const int64_t n = n0 + k;
+            if (!lam_x_done && (r = adj_deriv(s, 0, mu1, b, lam, -1.f, EPI_AXPY, Y, (int)S))) return r;
             if ((r = timed_begin(s))) return r;
             hipError_t e = launch_residual_inject(s->d_rec_str, s->nrec_str, lam, ss, s->res_dev, n, s->st);
             if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
             if ((r = timed_end(s, KC_RECEIVER))) return r;
-            // lambda^{n+1} += -dt (Dx^T(b mu1) + Dz^T(b mu3))   (media hold dt b, dt K)
-            if ((r = adj_deriv(s, 0, mu1, b, lam, -1.f, EPI_AXPY, Y, (int)S))) return r;
             if ((r = adj_deriv(s, 2, mu3, b, lam, -1.f, EPI_AXPY, Y, (int)S))) return r;
-            // dJ/dK += -dt lambda^{n+1} div u^n
             if ((r = timed_begin(s))) return r;
             e = launch_grad_accum(s->grad_pad, lam, s->divstore + k * fe, -dt, (int)S, ss, ss, s->st);
             if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
             if ((r = timed_end(s, KC_GRAD))) return r;
-            // mu^n = mu^{n+1} - dt D^T(K lambda^{n+1})
-            if ((r = adj_deriv(s, 0, lam, K, mu1, -1.f, EPI_AXPY, Y, (int)S))) return r;
             if ((r = adj_deriv(s, 2, lam, K, mu3, -1.f, EPI_AXPY, Y, (int)S))) return r;
+            if (n == 0) {
+                if ((r = adj_deriv(s, 0, lam, K, mu1, -1.f, EPI_AXPY, Y, (int)S))) return r;
+                lam_x_done = false;
+            } else {
+                if ((r = adj_x_pair(s, lam, K, mu1, b, Y, (int)S))) return r;
+                lam_x_done = true;
+            }
         }
     }
     hipError_t e = launch_grad_unpad(s->grad_pad, s->grad_dense, s->nx, s->ny * s->nz, s->pitch, s->d_vp,

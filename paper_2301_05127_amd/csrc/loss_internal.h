@@ -168,6 +168,9 @@ hipError_t launch_adj_gather(int axis, int epi, const LineArgs &a, const float *
 // Fused adjoint x pass (solve, junction rows, gather); hipErrorNotSupported when the
 // line does not fit one block or the epilogue is not STORE / AXPY.
 hipError_t launch_adj_x(int epi, const LineArgs &a, hipStream_t st);
+// Two adjoint x passes in one kernel: a.out[0] += a.alpha Dx^T(a.in_coef a.in), then
+// out2 += alpha2 Dx^T(coef2 a.out[0]) with the updated a.out[0]; out2 may be a.in.
+hipError_t launch_adj_xx(const LineArgs &a, const float *coef2, float *out2, float alpha2, hipStream_t st);
 // Fused x passes of the acoustic step (velocity along x, then T = d v1/dx of the
 // updated v1 into Tout): threads per block, 0 when a line does not fit one block.
 int line_xx_threads(const LineArgs &a);
