@@ -84,6 +84,8 @@ def lib():
             "or_pml_flow": (None, [c_double, c_double, c_double, c_double, c_double, c_double, D, D]),
             "or_run_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, c_int, S, c_int,
                                    I, D, D, D]),
+            "or_run_pml_elastic": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, D, c_int, S,
+                                           c_int, I, c_int, D, D, D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -254,6 +256,31 @@ def run_pml(g, pml, dt, nsteps, vp, rho, sources=(), receivers=None, fields_in=N
                           len(keep), src, rec.shape[0], _ip(rec), _dp(fin), _dp(fields), _dp(traces))
     if rc != 0:
         raise ValueError("oracle or_run_pml rejected its arguments (rc=%d)" % rc)
+    return fields, traces
+
+
+def run_pml_elastic(g, pml, dt, nsteps, vp, vs, rho, sources=(), receivers=None, rec_comp=0, fields_in=None,
+                    step0=0):
+    """Elastic 3-D run with the ADE-PML layer on all three axes (Sec. 3.3, applied to
+    every derivative of the elastic system).  pml: dict(width, R, kmax, f0, cmax).
+    Returns (fields (27, *shape): the 9 elastic fields, psi[3i + j] of d_j sigma_ij,
+    phi[3i + j] of d_j v_i; traces (nrec, nsteps) of field rec_comp)."""
+    shape = field_shape(g)
+    vp, vs, rho = _f64(vp), _f64(vs), _f64(rho)
+    src, keep = _sources(list(sources))
+    rec = np.zeros((0, 3), dtype=np.int32) if receivers is None else np.ascontiguousarray(receivers, dtype=np.int32)
+    fields = np.zeros((27,) + shape)
+    traces = np.zeros((rec.shape[0], nsteps))
+    fin = _f64(fields_in) if fields_in is not None else None
+    if fin is not None and fin.shape != fields.shape:
+        raise ValueError("fields_in must have shape %s (9 fields and 18 memory variables)" % (fields.shape,))
+    p = _Pml(int(pml["width"]), float(pml["R"]), float(pml["kmax"]), float(pml["f0"]), float(pml["cmax"]))
+    gs = _grid(g)
+    rc = lib().or_run_pml_elastic(ctypes.byref(gs), ctypes.byref(p), float(dt), int(step0), int(nsteps), _dp(vp),
+                                  _dp(vs), _dp(rho), len(keep), src, rec.shape[0], _ip(rec), int(rec_comp),
+                                  _dp(fin), _dp(fields), _dp(traces))
+    if rc != 0:
+        raise ValueError("oracle or_run_pml_elastic rejected its arguments (rc=%d)" % rc)
     return fields, traces
 
 

@@ -4,7 +4,9 @@
  *
  * Parity unpinned: none of the routines below lacks a pin; the pins live in
  * tests/test_oracle_pins.py (dense brute force, closed forms, invariants,
- * analytic plane-wave dispersion, finite differences of the adjoint).
+ * analytic plane-wave dispersion, finite differences of the adjoint) and
+ * tests/test_oracle_pml*.py (the layer: ODE integration, no-damping limit,
+ * absorption, wider domains, elastic plane waves against the acoustic layer).
  *
  * Method, in the paper's order (Sec. 3):
  *   1. cubic B-spline coefficients v~_{-1..N+1} of a line from the collocation rows
@@ -19,8 +21,10 @@
  *      difference of the coefficients divided by h^2 (second derivative of B_i);
  *   5. time: Strang splitting, half step of the velocity sub-flow, full step of the
  *      stress sub-flow, half step of the velocity sub-flow (Sec. 3.3);
- *   6. optional absorbing layer (acoustic 2-D): the ADE-PML memory variables, each
- *      sub-flow solved exactly with the driving derivative frozen (Sec. 3.3).
+ *   6. optional absorbing layer: the ADE-PML memory variables, each sub-flow solved
+ *      exactly with the driving derivative frozen (Sec. 3.3); written out in the paper
+ *      for the 2-D acoustic system, applied here to every derivative of the elastic
+ *      system as well.
  */
 #include "loss_oracle.h"
 
@@ -770,6 +774,157 @@ int or_run_pml(const or_grid *g, const or_pml *pml, double dt, int step0, int ns
     free(W);
     free(F);
     for (a = 0; a < 3; a += 2) {
+        free(pd[a]);
+        axis_tab_free(&S.T[a]);
+    }
+    return 0;
+}
+
+/* Elastic 3-D run with the layer on all three axes.  The paper writes the layer out
+ * for the 2-D acoustic system only; the same stretching applies to every spatial
+ * derivative of the elastic system: each derivative d_j f met in a sub-flow gets a
+ * memory variable driven by the profile of axis j, and its sub-flow with d_j f
+ * frozen is the exact flow of or_pml_flow.  The elastic signs are +b d_j sigma_ij and
+ * +lambda div + 2 mu eps, so each field moves by +(tau D / k + int psi) per derivative.
+ * State: the 9 elastic fields (OR_E_* order), then psi[3i + j] of d_j sigma_ij (velocity
+ * sub-flow), then phi[3i + j] of d_j v_i (stress sub-flow). */
+int or_run_pml_elastic(const or_grid *g, const or_pml *pml, double dt, int step0, int nsteps,
+                       const double *vp, const double *vs, const double *rho, int nsrc, const or_source *src,
+                       int nrec, const int *rec_idx, int rec_comp,
+                       const double *fields_in, double *fields, double *traces)
+{
+    /* sigma_ij as an index into the elastic fields */
+    static const int sig_of[3][3] = {{OR_E_S11, OR_E_S12, OR_E_S13},
+                                     {OR_E_S12, OR_E_S22, OR_E_S23},
+                                     {OR_E_S13, OR_E_S23, OR_E_S33}};
+    stepper S;
+    long nn[3], tot, i;
+    int a, k, n, r, ci, cj;
+    const int nf = 9 + 18;
+    double *F, *lam, *mu, *b, *d[9], **W, *pd[3], *pk[3], *pa[3], *psi, *phi;
+    if (check_grid(g, OR_ELASTIC) || pml->width < 1 || !(pml->R > 0.0 && pml->R < 1.0) || pml->kmax < 1.0 ||
+        pml->f0 <= 0.0 || rec_comp < 0 || rec_comp >= 9)
+        return -1;
+    for (a = 0; a < 3; ++a)
+        if (pml->width > g->n[a] / 2) return -1;
+    grid_nodes(g, nn);
+    tot = grid_total(g);
+    S.g = g; S.tot = tot;
+    for (a = 0; a < 3; ++a) {
+        tab_for_axis(g, a, &S.T[a]);
+        S.c[a].T = &S.T[a];
+        S.c[a].order = 1;
+    }
+    /* the acoustic profiles, on every axis */
+    for (a = 0; a < 3; ++a) {
+        int j, N = g->n[a];
+        double d0 = -3.0 * pml->cmax * log(pml->R) / (2.0 * pml->width * g->h[a]);
+        pd[a] = (double *)malloc(sizeof(double) * 3 * (N + 1));
+        pk[a] = pd[a] + N + 1;
+        pa[a] = pk[a] + N + 1;
+        for (j = 0; j <= N; ++j) {
+            double del = pml_delta(j, N, pml->width);
+            pd[a][j] = d0 * del * del;
+            pk[a][j] = 1.0 + (pml->kmax - 1.0) * del;
+            pa[a][j] = 3.14159265358979323846 * pml->f0 * (1.0 - del);
+        }
+    }
+    F = (double *)calloc((size_t)tot * (nf + 3 + 9), sizeof(double));
+    lam = F + (size_t)tot * nf;
+    mu = lam + tot;
+    b = mu + tot;
+    for (k = 0; k < 9; ++k) d[k] = b + tot + (size_t)k * tot;
+    psi = F + (size_t)9 * tot;
+    phi = F + (size_t)18 * tot;
+    if (fields_in) memcpy(F, fields_in, sizeof(double) * (size_t)tot * nf);
+    for (i = 0; i < tot; ++i) {
+        b[i] = 1.0 / rho[i];
+        mu[i] = rho[i] * vs[i] * vs[i];
+        lam[i] = rho[i] * vp[i] * vp[i] - 2.0 * mu[i];
+    }
+    W = (double **)malloc(sizeof(double *) * (nsrc > 0 ? nsrc : 1));
+    for (k = 0; k < nsrc; ++k) {
+        W[k] = (double *)malloc(sizeof(double) * tot);
+        or_source_weights(g, src[k].pos, src[k].spread, W[k]);
+    }
+    for (n = 0; n < nsteps; ++n) {
+        long sn = (long)step0 + n;
+        int half;
+        for (half = 0; half < 3; ++half) {
+            if (half != 1) {
+                /* (A) over dt/2 with the stress frozen: v_i += b sum_j (d_j sigma_ij)_stretched */
+                long fk = half == 0 ? sn : sn + 1;
+                double tau = 0.5 * dt;
+                for (ci = 0; ci < 3; ++ci) {
+                    double *v = F + (size_t)(OR_E_V1 + ci) * tot;
+                    for (cj = 0; cj < 3; ++cj) deriv_into(&S, cj, F + (size_t)sig_of[ci][cj] * tot, d[cj]);
+#pragma omp parallel for
+                    for (i = 0; i < tot; ++i) {
+                        const int c[3] = {(int)(i % nn[0]), (int)(i / nn[0] % nn[1]), (int)(i / (nn[0] * nn[1]))};
+                        int j;
+                        for (j = 0; j < 3; ++j) {
+                            double p1, dvb, *m = psi + (size_t)(3 * ci + j) * tot;
+                            or_pml_flow(pd[j][c[j]], pk[j][c[j]], pa[j][c[j]], tau, d[j][i], m[i], &p1, &dvb);
+                            m[i] = p1;
+                            v[i] -= b[i] * dvb;
+                        }
+                    }
+                }
+                for (k = 0; k < nsrc; ++k) {
+                    int fld = src[k].kind == OR_SRC_FORCE_X ? OR_E_V1
+                            : src[k].kind == OR_SRC_FORCE_Y ? OR_E_V2
+                            : src[k].kind == OR_SRC_FORCE_Z ? OR_E_V3 : -1;
+                    double s = sample(&src[k], fk);
+                    if (fld < 0) continue;
+                    for (i = 0; i < tot; ++i) F[fld * tot + i] += tau * b[i] * s * W[k][i];
+                }
+            } else {
+                /* (B) over dt with the velocity frozen: every d_j v_i stretched, then the
+                 * stress-strain law applied to the stretched increments */
+                for (ci = 0; ci < 3; ++ci)
+                    for (cj = 0; cj < 3; ++cj) deriv_into(&S, cj, F + (size_t)(OR_E_V1 + ci) * tot, d[3 * ci + cj]);
+#pragma omp parallel for
+                for (i = 0; i < tot; ++i) {
+                    const int c[3] = {(int)(i % nn[0]), (int)(i / nn[0] % nn[1]), (int)(i / (nn[0] * nn[1]))};
+                    double e[9], div;
+                    int q;
+                    for (q = 0; q < 9; ++q) {
+                        const int j = q % 3;
+                        double p1, dvb, *m = phi + (size_t)q * tot;
+                        or_pml_flow(pd[j][c[j]], pk[j][c[j]], pa[j][c[j]], dt, d[q][i], m[i], &p1, &dvb);
+                        m[i] = p1;
+                        e[q] = -dvb;   /* tau D / k + int phi */
+                    }
+                    div = e[0] + e[4] + e[8];
+                    F[OR_E_S11 * tot + i] += lam[i] * div + 2.0 * mu[i] * e[0];
+                    F[OR_E_S22 * tot + i] += lam[i] * div + 2.0 * mu[i] * e[4];
+                    F[OR_E_S33 * tot + i] += lam[i] * div + 2.0 * mu[i] * e[8];
+                    F[OR_E_S12 * tot + i] += mu[i] * (e[1] + e[3]);
+                    F[OR_E_S13 * tot + i] += mu[i] * (e[2] + e[6]);
+                    F[OR_E_S23 * tot + i] += mu[i] * (e[5] + e[7]);
+                }
+                for (k = 0; k < nsrc; ++k) {
+                    double s = sample(&src[k], sn);
+                    if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                    for (i = 0; i < tot; ++i) {
+                        F[OR_E_S11 * tot + i] += dt * s * W[k][i];
+                        F[OR_E_S22 * tot + i] += dt * s * W[k][i];
+                        F[OR_E_S33 * tot + i] += dt * s * W[k][i];
+                    }
+                }
+            }
+        }
+        if (traces)
+            for (r = 0; r < nrec; ++r) {
+                long ix = rec_idx[3 * r], iy = rec_idx[3 * r + 1], iz = rec_idx[3 * r + 2];
+                traces[(size_t)r * nsteps + n] = F[(size_t)rec_comp * tot + (iz * nn[1] + iy) * nn[0] + ix];
+            }
+    }
+    if (fields) memcpy(fields, F, sizeof(double) * (size_t)tot * nf);
+    for (k = 0; k < nsrc; ++k) free(W[k]);
+    free(W);
+    free(F);
+    for (a = 0; a < 3; ++a) {
         free(pd[a]);
         axis_tab_free(&S.T[a]);
     }

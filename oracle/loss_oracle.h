@@ -142,6 +142,16 @@ int or_run_pml(const or_grid *g, const or_pml *pml, double dt, int step0, int ns
                const double *vp, const double *rho, int nsrc, const or_source *src,
                int nrec, const int *rec_idx, const double *fields_in, double *fields, double *traces);
 
+/* Elastic 3-D run with the layer on all three axes: every derivative d_j f of the
+ * elastic sub-flows is stretched with the profile of axis j.  fields (27 x nodes) =
+ * the 9 elastic fields (OR_E_* order), psi[3i + j] (memory of d_j sigma_ij, velocity
+ * sub-flow), phi[3i + j] (memory of d_j v_i, stress sub-flow).  Receivers record field
+ * rec_comp.  Returns 0 on success. */
+int or_run_pml_elastic(const or_grid *g, const or_pml *pml, double dt, int step0, int nsteps,
+                       const double *vp, const double *vs, const double *rho, int nsrc, const or_source *src,
+                       int nrec, const int *rec_idx, int rec_comp,
+                       const double *fields_in, double *fields, double *traces);
+
 /* Gradient of J = 1/2 sum_n sum_r (trace - obs)^2 of one acoustic 2-D shot with
  * respect to the bulk modulus K = rho c^2 at every node, given the residual
  * res[r*nsteps+n] = trace - obs.  Exact transpose of the discrete canonical Strang
