@@ -84,6 +84,7 @@ def lib():
             "or_pml_flow": (None, [c_double, c_double, c_double, c_double, c_double, c_double, D, D]),
             "or_run_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, c_int, S, c_int,
                                    I, D, D, D]),
+            "or_elastic_adjoint": (c_int, [G, c_double, c_int, D, D, D, c_int, S, c_int, I, c_int, D, D, D]),
             "or_run_pml_elastic": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, D, c_int, S,
                                            c_int, I, c_int, D, D, D]),
         }
@@ -299,6 +300,24 @@ def acoustic_adjoint(g, dt, nsteps, vp, rho, sources, receivers, residual):
     if rc != 0:
         raise ValueError("oracle or_acoustic_adjoint rejected its arguments (rc=%d)" % rc)
     return grad
+
+
+def elastic_adjoint(g, dt, nsteps, vp, vs, rho, sources, receivers, rec_comp, residual):
+    """Gradients (dJ/dlambda, dJ/dmu) at every node for J = 1/2 sum residual^2 of the
+    traces of field rec_comp."""
+    shape = field_shape(g)
+    vp, vs, rho = _f64(vp), _f64(vs), _f64(rho)
+    src, keep = _sources(list(sources))
+    rec = np.ascontiguousarray(receivers, dtype=np.int32)
+    res = _f64(residual)
+    gl, gm = np.zeros(shape), np.zeros(shape)
+    gs = _grid(g)
+    rc = lib().or_elastic_adjoint(ctypes.byref(gs), float(dt), int(nsteps), _dp(vp), _dp(vs), _dp(rho),
+                                  len(keep), src, rec.shape[0], _ip(rec), int(rec_comp), _dp(res), _dp(gl),
+                                  _dp(gm))
+    if rc != 0:
+        raise ValueError("oracle or_elastic_adjoint rejected its arguments (rc=%d)" % rc)
+    return gl, gm
 
 
 def rel_l2(x, ref):

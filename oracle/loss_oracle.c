@@ -1032,3 +1032,159 @@ int or_acoustic_adjoint(const or_grid *g, double dt, int nsteps,
     free(Dm[0]); free(Dm[1]);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of the elastic 3-D Strang scheme                         */
+/* ------------------------------------------------------------------------ */
+/* Plain transposes, one operation at a time, of the canonical sequence of or_run_from:
+ *   A(dt/2): v_i += (dt/2) b sum_j D_j sigma_ij (+ forces)
+ *   B(dt):   sigma_kk += dt (lambda tr(e) + 2 mu e_kk), sigma_ij += dt mu g_ij (i < j)
+ *            with e_kk = D_k v_k, g_ij = D_j v_i + D_i v_j
+ *   A(dt/2) again; trace n samples field rec_comp after the step.
+ * Adjoints (bars) in the same field order as the state.  Transposing A: each
+ * sigma_ij-bar gains (dt/2) D_j^T (b v_i-bar) from every velocity it drives.
+ * Transposing B: v_k-bar gains dt D_k^T (lambda S + 2 mu sigma_kk-bar) with S the sum of
+ * the normal stress bars, and v_i-bar, v_j-bar gain dt D_j^T (mu sigma_ij-bar),
+ * dt D_i^T (mu sigma_ij-bar).  Lambda and mu enter B only:
+ *   dJ/dlambda += dt tr(e) S,  dJ/dmu += dt (2 sum_k e_kk sigma_kk-bar + sum g_ij sigma_ij-bar),
+ * with the strains of the state B was applied to. */
+int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
+                       const double *vp, const double *vs, const double *rho,
+                       int nsrc, const or_source *src,
+                       int nrec, const int *rec_idx, int rec_comp,
+                       const double *res, double *grad_lam, double *grad_mu)
+{
+    /* sigma_ij as an index into the fields; shear pairs (i, j) */
+    static const int sig_of[3][3] = {{OR_E_S11, OR_E_S12, OR_E_S13},
+                                     {OR_E_S12, OR_E_S22, OR_E_S23},
+                                     {OR_E_S13, OR_E_S23, OR_E_S33}};
+    static const int shear[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    long nn[3], tot, i;
+    int n, r, k, a, ci, cj, half;
+    double *Dm[3];
+    dense_ctx dc[3];
+    double *F, *Fb, *lam, *mu, *b, *t0, *t1, *strain, **W;
+    if (check_grid(g, OR_ELASTIC) || rec_comp < 0 || rec_comp >= 9) return -1;
+    grid_nodes(g, nn);
+    tot = grid_total(g);
+    for (a = 0; a < 3; ++a) {
+        int N = g->n[a];
+        Dm[a] = (double *)malloc(sizeof(double) * (size_t)(N + 1) * (N + 1));
+        or_line_deriv_matrix(N, g->h[a], g->M[a], g->halo, g->end_mode, Dm[a]);
+        dc[a].D = Dm[a]; dc[a].n = N + 1; dc[a].transpose = 0;
+    }
+    F = (double *)calloc((size_t)tot * 23, sizeof(double));
+    Fb = F + (size_t)9 * tot;
+    lam = Fb + (size_t)9 * tot; mu = lam + tot; b = mu + tot; t0 = b + tot; t1 = t0 + tot;
+    strain = (double *)malloc(sizeof(double) * (size_t)tot * 6 * nsteps);
+    if (!strain) { free(F); return -2; }
+    for (i = 0; i < tot; ++i) {
+        b[i] = 1.0 / rho[i];
+        mu[i] = rho[i] * vs[i] * vs[i];
+        lam[i] = rho[i] * vp[i] * vp[i] - 2.0 * mu[i];
+    }
+    W = (double **)malloc(sizeof(double *) * (nsrc > 0 ? nsrc : 1));
+    for (k = 0; k < nsrc; ++k) {
+        W[k] = (double *)malloc(sizeof(double) * tot);
+        or_source_weights(g, src[k].pos, src[k].spread, W[k]);
+    }
+    /* forward, keeping e_11, e_22, e_33, g_12, g_13, g_23 of the state B sees */
+    for (n = 0; n < nsteps; ++n) {
+        for (half = 0; half < 2; ++half) {
+            long fk = half == 0 ? n : n + 1;
+            for (ci = 0; ci < 3; ++ci)
+                for (cj = 0; cj < 3; ++cj) {
+                    apply_lines(g, cj, F + (size_t)sig_of[ci][cj] * tot, t0, dense_op, &dc[cj], 0);
+                    for (i = 0; i < tot; ++i) F[(size_t)(OR_E_V1 + ci) * tot + i] += 0.5 * dt * b[i] * t0[i];
+                }
+            for (k = 0; k < nsrc; ++k) {
+                int fld = src[k].kind == OR_SRC_FORCE_X ? OR_E_V1
+                        : src[k].kind == OR_SRC_FORCE_Y ? OR_E_V2
+                        : src[k].kind == OR_SRC_FORCE_Z ? OR_E_V3 : -1;
+                double s = sample(&src[k], fk);
+                if (fld < 0) continue;
+                for (i = 0; i < tot; ++i) F[(size_t)fld * tot + i] += 0.5 * dt * b[i] * s * W[k][i];
+            }
+            if (half == 1) break;
+            {
+                double *e = strain + (size_t)n * 6 * tot;
+                for (k = 0; k < 3; ++k)
+                    apply_lines(g, k, F + (size_t)(OR_E_V1 + k) * tot, e + (size_t)k * tot, dense_op, &dc[k], 0);
+                for (k = 0; k < 3; ++k) {
+                    int p = shear[k][0], q = shear[k][1];
+                    double *gk = e + (size_t)(3 + k) * tot;
+                    apply_lines(g, q, F + (size_t)(OR_E_V1 + p) * tot, gk, dense_op, &dc[q], 0);
+                    apply_lines(g, p, F + (size_t)(OR_E_V1 + q) * tot, t0, dense_op, &dc[p], 0);
+                    for (i = 0; i < tot; ++i) gk[i] += t0[i];
+                }
+                for (i = 0; i < tot; ++i) {
+                    double tr = e[i] + e[tot + i] + e[2 * tot + i];
+                    for (k = 0; k < 3; ++k)
+                        F[(size_t)(OR_E_S11 + k) * tot + i] += dt * (lam[i] * tr + 2.0 * mu[i] * e[(size_t)k * tot + i]);
+                    F[(size_t)OR_E_S12 * tot + i] += dt * mu[i] * e[3 * (size_t)tot + i];
+                    F[(size_t)OR_E_S13 * tot + i] += dt * mu[i] * e[4 * (size_t)tot + i];
+                    F[(size_t)OR_E_S23 * tot + i] += dt * mu[i] * e[5 * (size_t)tot + i];
+                }
+            }
+            for (k = 0; k < nsrc; ++k) {
+                double s = sample(&src[k], n);
+                if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                for (i = 0; i < tot; ++i)
+                    for (a = 0; a < 3; ++a) F[(size_t)(OR_E_S11 + a) * tot + i] += dt * s * W[k][i];
+            }
+        }
+    }
+    /* reverse sweep */
+    for (i = 0; i < tot; ++i) { grad_lam[i] = 0.0; grad_mu[i] = 0.0; }
+    dc[0].transpose = dc[1].transpose = dc[2].transpose = 1;
+    for (n = nsteps - 1; n >= 0; --n) {
+        const double *e = strain + (size_t)n * 6 * tot;
+        for (r = 0; r < nrec; ++r) {
+            long ix = rec_idx[3 * r], iy = rec_idx[3 * r + 1], iz = rec_idx[3 * r + 2];
+            Fb[(size_t)rec_comp * tot + (iz * nn[1] + iy) * nn[0] + ix] += res[(size_t)r * nsteps + n];
+        }
+        for (half = 0; half < 2; ++half) {
+            /* transpose of A(dt/2) */
+            for (ci = 0; ci < 3; ++ci) {
+                for (i = 0; i < tot; ++i) t1[i] = b[i] * Fb[(size_t)(OR_E_V1 + ci) * tot + i];
+                for (cj = 0; cj < 3; ++cj) {
+                    apply_lines(g, cj, t1, t0, dense_op, &dc[cj], 0);
+                    for (i = 0; i < tot; ++i) Fb[(size_t)sig_of[ci][cj] * tot + i] += 0.5 * dt * t0[i];
+                }
+            }
+            if (half == 1) break;
+            /* gradient with the strains B used, then the transpose of B */
+            for (i = 0; i < tot; ++i) {
+                double S = Fb[(size_t)OR_E_S11 * tot + i] + Fb[(size_t)OR_E_S22 * tot + i] + Fb[(size_t)OR_E_S33 * tot + i];
+                double tr = e[i] + e[tot + i] + e[2 * tot + i], m = 0.0;
+                for (k = 0; k < 3; ++k) m += 2.0 * e[(size_t)k * tot + i] * Fb[(size_t)(OR_E_S11 + k) * tot + i];
+                m += e[3 * (size_t)tot + i] * Fb[(size_t)OR_E_S12 * tot + i] + e[4 * (size_t)tot + i] * Fb[(size_t)OR_E_S13 * tot + i]
+                   + e[5 * (size_t)tot + i] * Fb[(size_t)OR_E_S23 * tot + i];
+                grad_lam[i] += dt * tr * S;
+                grad_mu[i] += dt * m;
+            }
+            for (k = 0; k < 3; ++k) {
+                for (i = 0; i < tot; ++i) {
+                    double S = Fb[(size_t)OR_E_S11 * tot + i] + Fb[(size_t)OR_E_S22 * tot + i] + Fb[(size_t)OR_E_S33 * tot + i];
+                    t1[i] = lam[i] * S + 2.0 * mu[i] * Fb[(size_t)(OR_E_S11 + k) * tot + i];
+                }
+                apply_lines(g, k, t1, t0, dense_op, &dc[k], 0);
+                for (i = 0; i < tot; ++i) Fb[(size_t)(OR_E_V1 + k) * tot + i] += dt * t0[i];
+            }
+            for (k = 0; k < 3; ++k) {
+                int p = shear[k][0], q = shear[k][1];
+                for (i = 0; i < tot; ++i) t1[i] = mu[i] * Fb[(size_t)sig_of[p][q] * tot + i];
+                apply_lines(g, q, t1, t0, dense_op, &dc[q], 0);
+                for (i = 0; i < tot; ++i) Fb[(size_t)(OR_E_V1 + p) * tot + i] += dt * t0[i];
+                apply_lines(g, p, t1, t0, dense_op, &dc[p], 0);
+                for (i = 0; i < tot; ++i) Fb[(size_t)(OR_E_V1 + q) * tot + i] += dt * t0[i];
+            }
+        }
+    }
+    for (k = 0; k < nsrc; ++k) free(W[k]);
+    free(W);
+    free(strain);
+    free(F);
+    for (a = 0; a < 3; ++a) free(Dm[a]);
+    return 0;
+}
