@@ -71,6 +71,8 @@ def parse():
     p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--shape", default=None,
                    help="launch shape per axis 'x,y,z' (loss_set_shape encoding); skips autotuning")
+    p.add_argument("--pml", type=int, default=0,
+                   help="absorbing layer of this many nodes on every side (R 1e-6, kmax 1, f0 of the source)")
     p.add_argument("--copy-probe", action="store_true",
                    help="accepted for compatibility: the 1 GiB copy probe always runs")
     return p.parse_args()
@@ -85,13 +87,28 @@ def workload_desc(w, shots):
                w["dt"], "x".join(str(m) for m in (g["M"][0], g["M"][2])), g["halo"], shots))
 
 
-def cpu_baseline(w, nsteps):
+def source_f0(name):
+    """Dominant frequency of the workload's Ricker sources (sets the layer's alpha)."""
+    return 20.0 if name == "cfg2" else 15.0
+
+
+def cpu_baseline(w, nsteps, pml=0):
     import oracle
     oracle.build()
     sh = w["shots"][0]
     t0 = time.perf_counter()
-    oracle.run(w["grid"], w["physics"], w["dt"], nsteps, w["vp"], w["rho"], vs=w.get("vs"),
-               sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh.get("rec_comp", 0))
+    if pml:
+        lay = dict(width=pml, R=1e-6, kmax=1.0, f0=source_f0(w["name"]), cmax=float(np.max(w["vp"])))
+        if w["physics"] == 0:
+            oracle.run_pml(w["grid"], lay, w["dt"], nsteps, w["vp"], w["rho"], sources=sh["sources"],
+                           receivers=sh["receivers"])
+        else:
+            oracle.run_pml_elastic(w["grid"], lay, w["dt"], nsteps, w["vp"], w["vs"], w["rho"],
+                                   sources=sh["sources"], receivers=sh["receivers"],
+                                   rec_comp=sh.get("rec_comp", 0))
+    else:
+        oracle.run(w["grid"], w["physics"], w["dt"], nsteps, w["vp"], w["rho"], vs=w.get("vs"),
+                   sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh.get("rec_comp", 0))
     el = time.perf_counter() - t0
     n = w["grid"]["n"]
     nodes = (n[0] + 1) * (n[2] + 1) * (1 if w["grid"]["ndim"] == 2 else n[1] + 1)
@@ -99,7 +116,7 @@ def cpu_baseline(w, nsteps):
     return {"value": nodes * nsteps / el / 1e6, "unit": "Mcell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d steps of the same workload, one shot, FP64 C oracle (canonical unfused "
-                      "Strang, OpenMP over lines), %.1f s wall" % (nsteps, el)}
+                      "Strang, OpenMP over lines%s), %.1f s wall" % (nsteps, ", same layer" if pml else "", el)}
 
 
 def measured_traffic(workload_key, kernel):
@@ -128,7 +145,7 @@ def gradient_ratio(sim, w, S, nsteps, t_fwd):
     """Time forward-with-checkpoints + adjoint over the same steps as the plain forward
     (t_fwd); the residual is the recorded traces themselves (J = sum d^2 / 2)."""
     import torch
-    every = int(w.get("ckpt_every", 100))
+    every = int(w.get("ckpt_every", 100 if w["physics"] == 0 else 20))
     sim.reset()
     sim.sync()
     t0 = time.perf_counter()
@@ -153,6 +170,10 @@ def main():
         print("bench.py: this build measures one GPU; --gpus %d is not supported (shots and "
               "space would shard across GPUs, see DESIGN.md)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.grad and a.pml:
+        print("bench.py: the adjoint is built without the absorbing layer; drop --pml or --grad",
+              file=sys.stderr)
+        sys.exit(2)
     import torch
     from paper_2301_05127_amd import inputs, loss
     if not torch.cuda.is_available():
@@ -168,6 +189,8 @@ def main():
     g = w["grid"]
     sim = loss.Simulation(g, w["physics"], w["dt"], nshots=S, trace_len=total)
     sim.setup_workload(w, shots=shots)
+    if a.pml:
+        sim.set_pml(a.pml, 1e-6, 1.0, source_f0(a.workload))
     nodes = sim.nodes
     if a.shape:
         cw = [int(v) for v in a.shape.split(",")]
@@ -203,7 +226,7 @@ def main():
         bytes_per_launch = algo[dom[0]] * nodes * S
         avg_s = dom[1] / dom[2] / 1e3
         ach = bytes_per_launch / avg_s / 1e9
-        tr = measured_traffic(PROFILE_KEYS[a.workload], dom[0]) if S == len(w["shots"]) else None
+        tr = measured_traffic(PROFILE_KEYS[a.workload], dom[0]) if S == len(w["shots"]) and not a.pml else None
         roof = {"bound": "hbm", "kernel": dom[0], "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
                 "bytes_per_node": round(algo[dom[0]], 3), "algorithmic_bytes": round(bytes_per_launch)}
@@ -244,7 +267,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload_desc(w, S), "nodes": nodes, "shots": S,
+        "config": {"workload": workload_desc(w, S) + (", absorbing layer of %d nodes" % a.pml if a.pml else ""),
+                   "nodes": nodes, "shots": S,
                    "columns_per_wave": cw,
                    "hbm_effective_GBs": round(eff, 1),
                    "hbm_effective_frac": round(eff / HBM_PEAK_GBS, 4),
@@ -257,7 +281,7 @@ def main():
         res["gradient"] = grad
     if not a.no_cpu_baseline:
         cs = a.cpu_sample_steps or CPU_SAMPLE_STEPS[a.workload]
-        res["cpu_baseline"] = cpu_baseline(inputs.config(a.workload, nsteps=cs), cs)
+        res["cpu_baseline"] = cpu_baseline(inputs.config(a.workload, nsteps=cs), cs, a.pml)
     sim.close()
     print(json.dumps(res), flush=True)
 

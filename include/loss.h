@@ -138,26 +138,33 @@ loss_status loss_add_source(loss_sim *sim, int32_t shot, const double pos[3], in
 /* Add receivers to `shot`: node_idx (host) = nrec triples (ix, iy, iz).  After every
  * step n (counted from the last reset) sample n of each trace receives the field
  * `component` at t_{n+1} (acoustic: LOSS_F_SIGMA only; elastic: any field id),
- * accumulated in float64.  Replaces earlier receivers of the shot. */
+ * accumulated in float64.  A velocity at t_{n+1} is the mean of the half-step-ahead
+ * states on either side (exact for the Strang scheme, whose velocity sub-flow is linear
+ * in its step; inside an absorbing layer the exact sub-flow is not, and a velocity
+ * receiver there is off by the layer's second-order term, about 1e-4 relative).
+ * Replaces earlier receivers of the shot. */
 loss_status loss_add_receivers(loss_sim *sim, int32_t shot, int64_t nrec, const int32_t *node_idx,
                                int32_t component);
 
 /* Zero every wavefield, trace and the step counter (media and sources are kept). */
 loss_status loss_reset(loss_sim *sim);
 
-/* Absorbing layer (paper Sec. 3.3: ADE-PML with the exponential operator splitting),
- * acoustic only: the outermost `width` nodes at both ends of x and z carry memory
- * variables (psi for the velocity sub-flow, phi for the stress sub-flow) that damp
- * outgoing waves.  At depth fraction delta in (0, 1] into the layer:
+/* Absorbing layer (paper Sec. 3.3: ADE-PML with the exponential operator splitting):
+ * the outermost `width` nodes at both ends of every axis carry memory variables that
+ * damp outgoing waves, one per spatial derivative of a sub-flow (acoustic: psi_x,
+ * psi_z of the velocity sub-flow, phi_x, phi_z of the stress sub-flow; elastic, where
+ * the paper's acoustic construction is applied to every derivative: 9 for the
+ * d_j sigma_ij and 9 for the d_j v_i), each stretched by the profile of its own axis.
+ * At depth fraction delta in (0, 1] into the layer:
  *   d = d0 delta^2, k = 1 + (kmax - 1) delta, alpha = pi f0 (1 - delta),
  *   d0 = -3 cmax ln(reflection) / (2 width h), cmax = the largest velocity of the
  * media set (call after loss_set_media; setting media again does not update d0).
  * Each sub-flow is solved exactly with its driving derivative frozen.  width = 0
- * removes the layer.  The memory variables start at zero (and return to zero on
- * loss_reset); loss_forward_ckpt / loss_adjoint refuse a simulation with a layer
- * (LOSS_EUNSUPPORTED).  Errors: LOSS_EINVAL (width < 0 or > n/2 on an axis,
- * reflection outside (0, 1), kmax < 1, f0 <= 0), LOSS_EUNSUPPORTED (elastic),
- * LOSS_ESTATE (no media yet). */
+ * removes the layer.  The memory variables (4 or 18 fields of device memory) start at
+ * zero (and return to zero on loss_reset); loss_forward_ckpt / loss_adjoint refuse a
+ * simulation with a layer (LOSS_EUNSUPPORTED).  Errors: LOSS_EINVAL (width < 0 or
+ * > n/2 on an axis, reflection outside (0, 1), kmax < 1, f0 <= 0), LOSS_ESTATE (no
+ * media yet). */
 loss_status loss_set_pml(loss_sim *sim, int32_t width, double reflection, double kmax, double f0);
 
 /* Advance all shots by nsteps Strang steps, asynchronously on the sim stream.
@@ -185,18 +192,25 @@ loss_status loss_get_traces(loss_sim *sim, int32_t shot, double *dst, int32_t me
 loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *in, float *out,
                        int64_t batch, int32_t mem);
 
-/* Adjoint-state gradient (acoustic only).  loss_forward_ckpt resets, runs nsteps
- * (<= trace_len) steps from rest recording traces and keeping the state every
- * ckpt_every steps in device memory.  loss_adjoint then takes the trace residual
- * of J = 1/2 sum residual^2, laid out like the traces of all shots concatenated
- * (residual[shot][rec][t], t < trace_len, float64; samples t >= nsteps are ignored)
- * and returns dJ/dparam summed over shots (float64, nodes), param = LOSS_GRAD_K
- * (bulk modulus K) or LOSS_GRAD_VP (c with rho fixed: 2 rho c dJ/dK).  The adjoint
- * applies the exact transpose of every discrete operator of the time-stepping
- * scheme; forward states are recomputed from the checkpoints segment by segment.
- * Afterwards the wavefields hold an intermediate state (call loss_reset). */
-#define LOSS_GRAD_K  0
-#define LOSS_GRAD_VP 1
+/* Adjoint-state gradient.  loss_forward_ckpt resets, runs nsteps (<= trace_len) steps
+ * from rest recording traces and keeping the state every ckpt_every steps in device
+ * memory.  loss_adjoint then takes the trace residual of J = 1/2 sum residual^2, laid
+ * out like the traces of all shots concatenated (residual[shot][rec][t], t < trace_len,
+ * float64; samples t >= nsteps are ignored) and returns dJ/dparam summed over shots
+ * (float64).  Acoustic: param = LOSS_GRAD_K (bulk modulus K) or LOSS_GRAD_VP (c with rho
+ * fixed: 2 rho c dJ/dK), grad = nodes values.  Elastic: param = LOSS_GRAD_LAME
+ * (grad = dJ/dlambda then dJ/dmu, 2 x nodes) or LOSS_GRAD_VPVS (dJ/dvp then dJ/dvs with
+ * rho fixed, 2 x nodes); the segment recompute keeps six strain fields per step
+ * (6 x ckpt_every fields of device memory).  The adjoint applies the exact transpose
+ * of every discrete operator of the time-stepping scheme; forward states are
+ * recomputed from the checkpoints segment by segment.  Afterwards the wavefields hold
+ * an intermediate state (call loss_reset).  Errors: LOSS_EUNSUPPORTED (absorbing layer,
+ * patches shorter than 2 intervals), LOSS_EINVAL (param not of the physics),
+ * LOSS_ESTATE (no loss_forward_ckpt). */
+#define LOSS_GRAD_K    0
+#define LOSS_GRAD_VP   1
+#define LOSS_GRAD_LAME 2
+#define LOSS_GRAD_VPVS 3
 loss_status loss_forward_ckpt(loss_sim *sim, int64_t nsteps, int64_t ckpt_every);
 loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, double *grad,
                          int32_t mem);

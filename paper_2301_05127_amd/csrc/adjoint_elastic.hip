@@ -1,0 +1,148 @@
+// Pointwise kernels of the elastic discrete adjoint (the transposed derivatives reuse
+// the line kernels of kernels.hip).  The forward stress sub-flow B (Sec. 3.3, Strang
+// splitting of the velocity-stress system of Sec. 2) is
+//   sigma_kk += (dt lambda) tr(e) + 2 (dt mu) e_kk,  sigma_ij += (dt mu) g_ij  (i < j),
+// e_kk = D_k v_k, g_ij = D_j v_i + D_i v_j; the media hold dt lambda, dt mu,
+// dt (lambda + 2 mu) and dt / rho.  Fields are padded rows of `pitch` floats, shots
+// `shot_stride` apart; only the nx valid columns of a row are touched.
+#include <hip/hip_runtime.h>
+
+#include "loss_internal.h"
+
+namespace loss {
+
+namespace {
+
+__device__ __forceinline__ bool valid_node(int64_t i, int nx, int64_t pitch, int64_t per_shot, int S,
+                                           int64_t *shot_off, int64_t *p)
+{
+    const int64_t rows = per_shot / pitch;
+    const int64_t row = i / nx;                 // over all shots
+    const int x = (int)(i - row * nx);
+    const int64_t shot = row / rows;
+    if (shot >= S) return false;
+    *p = (row - shot * rows) * pitch + x;
+    *shot_off = shot * per_shot;
+    return true;
+}
+
+// w = (dt(lambda + 2 mu)) sbar_kk + (dt lambda) (sum of the other two normal bars): the
+// operand of D_k^T in the transpose of B for velocity k.
+__global__ void k_el_normal_operand(float *__restrict__ w, const float *__restrict__ s11,
+                                    const float *__restrict__ s22, const float *__restrict__ s33,
+                                    const float *__restrict__ l2m, const float *__restrict__ lam, int k, int nx,
+                                    int64_t pitch, int64_t per_shot, int S, int64_t total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int64_t so, p;
+    if (!valid_node(i, nx, pitch, per_shot, S, &so, &p)) return;
+    const float a = s11[so + p], b = s22[so + p], c = s33[so + p];
+    const float own = k == 0 ? a : (k == 1 ? b : c);
+    const float others = k == 0 ? b + c : (k == 1 ? a + c : a + b);
+    w[so + p] = fmaf(l2m[p], own, lam[p] * others);
+}
+
+// dJ/dlambda += dt tr(e) (sbar_11 + sbar_22 + sbar_33),
+// dJ/dmu     += dt (2 sum_k e_kk sbar_kk + sum_{i<j} g_ij sbar_ij), summed over shots in
+// FP64.  e: six strain fields (e11, e22, e33, g12, g13, g23) of the state B was applied
+// to; sb: the six stress bars (11, 22, 33, 12, 13, 23).  g: two padded accumulators.
+struct Six {
+    const float *p[6];
+};
+
+__global__ void k_el_grad_accum(double *__restrict__ gl, double *__restrict__ gm, Six e, Six sb, double dt,
+                                int nx, int64_t pitch, int64_t per_shot, int S, int64_t total_one_shot)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total_one_shot) return;
+    int64_t so, p;
+    if (!valid_node(i, nx, pitch, per_shot, 1, &so, &p)) return;
+    double al = 0.0, am = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const int64_t q = (int64_t)s * per_shot + p;
+        const double e11 = e.p[0][q], e22 = e.p[1][q], e33 = e.p[2][q];
+        const double b11 = sb.p[0][q], b22 = sb.p[1][q], b33 = sb.p[2][q];
+        al += (e11 + e22 + e33) * (b11 + b22 + b33);
+        am += 2.0 * (e11 * b11 + e22 * b22 + e33 * b33) + (double)e.p[3][q] * sb.p[3][q] +
+              (double)e.p[4][q] * sb.p[4][q] + (double)e.p[5][q] * sb.p[5][q];
+    }
+    gl[p] += dt * al;
+    gm[p] += dt * am;
+}
+
+// adjoint field rec.comp += w * residual sample n, for every receiver
+__global__ void k_el_residual_inject(const RecDev *__restrict__ rec, int nrec, float *const *adj,
+                                     int64_t shot_stride, const double *__restrict__ res, int64_t n, float w)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const RecDev rd = rec[r];
+    atomicAdd(adj[rd.comp] + (int64_t)rd.shot * shot_stride + rd.node, w * (float)res[rd.trace_off + n]);
+}
+
+// padded accumulators -> dense gradients: (dJ/dlambda, dJ/dmu) or, with rho fixed,
+// (dJ/dvp, dJ/dvs) from lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2
+__global__ void k_el_grad_unpad(const double *__restrict__ gl, const double *__restrict__ gm, double *g,
+                                int nx, int64_t pitch, const float *__restrict__ vp, const float *__restrict__ vs,
+                                const float *__restrict__ rho, int to_velocity, int64_t nodes)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nodes) return;
+    const int x = (int)(idx % nx);
+    const int64_t p = (idx / nx) * pitch + x;
+    double a = gl[p], b = gm[p];
+    if (to_velocity) {
+        const double r = rho[idx], cp = vp[idx], cs = vs[idx];
+        const double dvp = a * 2.0 * r * cp;
+        const double dvs = a * (-4.0 * r * cs) + b * 2.0 * r * cs;
+        a = dvp;
+        b = dvs;
+    }
+    g[idx] = a;
+    g[nodes + idx] = b;
+}
+
+}  // namespace
+
+hipError_t launch_el_normal_operand(float *w, const float *s11, const float *s22, const float *s33,
+                                    const float *l2m, const float *lam, int k, int nx, int64_t pitch,
+                                    int64_t per_shot, int S, hipStream_t st)
+{
+    const int64_t total = (int64_t)S * (per_shot / pitch) * nx;
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(k_el_normal_operand, blocks, 256, 0, st, w, s11, s22, s33, l2m, lam, k, nx, pitch,
+                       per_shot, S, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_el_grad_accum(double *gl, double *gm, const float *const *strain, const float *const *sbar,
+                                double dt, int nx, int64_t pitch, int64_t per_shot, int S, hipStream_t st)
+{
+    Six e, sb;
+    for (int k = 0; k < 6; ++k) { e.p[k] = strain[k]; sb.p[k] = sbar[k]; }
+    const int64_t total = (per_shot / pitch) * nx;
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(k_el_grad_accum, blocks, 256, 0, st, gl, gm, e, sb, dt, nx, pitch, per_shot, S, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_el_residual_inject(const RecDev *rec, int nrec, float *const *adj, int64_t shot_stride,
+                                     const double *res, int64_t n, float w, hipStream_t st)
+{
+    if (nrec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_el_residual_inject, (unsigned)((nrec + 255) / 256), 256, 0, st, rec, nrec, adj,
+                       shot_stride, res, n, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_el_grad_unpad(const double *gl, const double *gm, double *g, int nx, int64_t pitch,
+                                const float *vp, const float *vs, const float *rho, int to_velocity,
+                                int64_t nodes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_el_grad_unpad, (unsigned)((nodes + 255) / 256), 256, 0, st, gl, gm, g, nx, pitch, vp,
+                       vs, rho, to_velocity, nodes);
+    return hipGetLastError();
+}
+
+}  // namespace loss

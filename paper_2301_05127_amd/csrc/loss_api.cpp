@@ -112,16 +112,22 @@ struct loss_sim {
     int *d_rrow = nullptr;
     int64_t *d_rtoff = nullptr;
     // adjoint
-    float *ckpt = nullptr;         // [nseg][3 fields][S][shot_stride] fused states
+    float *ckpt = nullptr;         // [nseg][nf fields][S][shot_stride] fused states
     int64_t ck_every = 0, ck_steps = 0, ck_nseg = 0;
-    float *divstore = nullptr;     // [ck_every][S][shot_stride]
+    // per recomputed step, acoustic: div u; elastic: e11, e22, e33, g12, g13, g23
+    float *divstore = nullptr;     // [ck_every][1 or 6][S][shot_stride]
     float *adj[4] = {nullptr, nullptr, nullptr, nullptr};   // lambda, mu1, mu3, Y scratch
+    float *adj_el[11] = {};        // elastic: the 9 field bars (field order), Y scratch, operand
+    float **d_adjtab = nullptr;    // device copy of adj_el[0..8]
     double *grad_pad = nullptr, *grad_dense = nullptr, *res_dev = nullptr;
     float *d_vp = nullptr, *d_rho = nullptr;   // dense copies of the media for the gradient map
+    float *d_vs = nullptr;
     double cmax = 0.0;                         // largest velocity of the media
-    // absorbing layer: memory variables psi_x, psi_z (velocity sub-flow), phi_x, phi_z
-    // (stress sub-flow), each laid out like a field; per-axis coefficient tables
+    // absorbing layer: memory variables, each laid out like a field (acoustic: psi_x,
+    // psi_z of the velocity sub-flow, phi_x, phi_z of the stress sub-flow; elastic:
+    // 3i + j of d_j sigma_ij, then 9 + 3i + j of d_j v_i); per-axis coefficient tables
     float *pml_mem = nullptr;
+    int npml = 0;
     float4 *pml_tab[3] = {nullptr, nullptr, nullptr};
     int pml_w = 0;
 
@@ -359,14 +365,18 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
         // T = d_x sigma_{i1} (stored), T += d_y sigma_{i2}, v_i += frac b (T + d_z sigma_{i3})
         for (int i = 0; i < 3; ++i) {
             float *T = s->tmp[i];
+            // with the layer each pass stores the stretched derivative and advances its
+            // memory variable; the sum is still linear in the three
             LineArgs x = base_args(s, 0);
             x.in = s->f[sidx[i][0]];
             x.out[0] = T;
+            set_pml(s, x, 3 * i + 0, frac * s->d.dt, true);
             if ((r = run_line(s, KC_VEL_X, 0, SOLVE_D1, EPI_STORE, x))) return r;
             LineArgs y = base_args(s, 1);
             y.in = s->f[sidx[i][1]];
             y.alpha = 1.f;
             y.out[0] = T;
+            set_pml(s, y, 3 * i + 1, frac * s->d.dt, true);
             if ((r = run_line(s, KC_VEL_Y, 1, SOLVE_D1, EPI_AXPY, y))) return r;
             LineArgs z = base_args(s, 2);
             z.in = s->f[sidx[i][2]];
@@ -374,6 +384,7 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             z.out[0] = vel[i];
             z.coef[0] = b;
             z.aux = T;
+            set_pml(s, z, 3 * i + 2, frac * s->d.dt, true);
             if (with_forces) {
                 const int fid = LOSS_F_EV1 + i;
                 attach_sources(s, z, 0, &fid, 1, true);
@@ -391,6 +402,7 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             a.coef[0] = b;
             int epi = EPI_AXPY;
             if (base && j == 0) { a.aux = base[i]; epi = EPI_BASE; }
+            set_pml(s, a, 3 * i + j, frac * s->d.dt, base == nullptr);
             if (with_forces && j == 2) {
                 const int fid = LOSS_F_EV1 + i;
                 attach_sources(s, a, 0, &fid, 1, true);
@@ -483,7 +495,6 @@ bool fused_x_ok(loss_sim *s)
 // ---- stress sub-flow (B) over dt with the velocity frozen --------------------
 loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
 {
-    const float dt = (float)s->d.dt;
     loss_status r;
     if (s->d.physics == LOSS_ACOUSTIC) {
         // T = d v1/dx ; sigma -= dt K (T + d v3/dz)
@@ -495,11 +506,26 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
     // normal components: T1 = d1 v1 and T2 = d2 v2 stored, then the z pass updates all
     // three from T1, T2 and d3 v3: sigma_ii += (lambda + 2 mu) d_i v_i + lambda (sum of
     // the other two) (media hold dt lambda, dt mu, dt (lambda + 2 mu))
+    // (with the layer every d_j v_i is stretched, memory variable 9 + 3i + j, and the
+    // stress-strain law applies to the stretched derivatives)
+    // (div_store, if given: six strain fields e11, e22, e33, g12, g13, g23 of this
+    // step for the adjoint, field_elems apart)
+    const int64_t fe = field_elems(s);
     for (int i = 0; i < 2; ++i) {
         LineArgs a = base_args(s, i);
         a.in = F[LOSS_F_EV1 + i];
         a.out[0] = s->tmp[i];
+        set_pml(s, a, 9 + 4 * i, s->d.dt, true);
         if ((r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_STORE, a))) return r;
+        if (div_store)
+            HIPCHK(hipMemcpyAsync(div_store + i * fe, s->tmp[i], sizeof(float) * fe, hipMemcpyDeviceToDevice,
+                                  s->st));
+    }
+    if (div_store) {
+        LineArgs a = base_args(s, 2);
+        a.in = F[LOSS_F_EV3];
+        a.out[0] = div_store + 2 * fe;
+        if ((r = run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_STORE, a))) return r;
     }
     {
         LineArgs a = base_args(s, 2);
@@ -511,6 +537,7 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         a.coef[1] = lam;
         a.aux = s->tmp[0];
         a.aux2 = s->tmp[1];
+        set_pml(s, a, 9 + 8, s->d.dt, true);
         const int fid[3] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33};
         attach_sources(s, a, -1, fid, 3, false);
         if ((r = run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_NORMAL3, a))) return r;
@@ -518,10 +545,11 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
     // shear components: T = d_i v_j stored, then sigma_ij += dt mu (d_j v_i + T)
     static const int sh[3][3] = {{LOSS_F_S12, 0, 1}, {LOSS_F_S13, 0, 2}, {LOSS_F_S23, 1, 2}};
     for (int k = 0; k < 3; ++k) {
-        const int sij = sh[k][0], i = sh[k][1], j = sh[k][2];
+        const int i = sh[k][1], j = sh[k][2];
         LineArgs t = base_args(s, i);
         t.in = F[LOSS_F_EV1 + j];
         t.out[0] = s->tmp[k];
+        set_pml(s, t, 9 + 3 * j + i, s->d.dt, true);
         if ((r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_STORE, t))) return r;
     }
     for (int k = 0; k < 3; ++k) {
@@ -532,6 +560,11 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         a.out[0] = F[sij];
         a.coef[0] = mu;
         a.aux = s->tmp[k];
+        set_pml(s, a, 9 + 3 * i + j, s->d.dt, true);
+        if (div_store) {
+            a.div = div_store + (3 + k) * fe;
+            a.div_shot_stride = div_shot_stride;
+        }
         if ((r = run_line(s, KC_STRESS_X + j, j, SOLVE_D1, EPI_AXPY_AUX, a))) return r;
     }
     return LOSS_OK;
@@ -755,7 +788,9 @@ loss_status unfuse_in_place(loss_sim *s)
     if (s->pml_mem) {
         // the layer's memory variables go back with the velocity: the exact velocity
         // sub-flow over -dt/2, in place
-        std::vector<float *> vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
+        std::vector<float *> vel;
+        if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
+        else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
         loss_status r = velocity_stage(s, -0.5f, vel.data(), nullptr);
         if (r) return r;
         if ((r = inject(s, s->d_fields, 0, -0.5f, 1))) return r;
@@ -822,8 +857,9 @@ loss_status steps_eager(loss_sim *s, int64_t K, float *div_store = nullptr, int6
 {
     loss_status r;
     if (K > 0 && fused_x_ok(s)) return steps_fused_x(s, K, div_store, div_shot_stride);
+    const int64_t nslot = s->d.physics == LOSS_ACOUSTIC ? 1 : 6;
     for (int64_t done = 0; done < K; ++done) {
-        float *ds = div_store ? div_store + done * s->S * div_shot_stride : nullptr;
+        float *ds = div_store ? div_store + done * nslot * s->S * div_shot_stride : nullptr;
         if ((r = one_step(s, ds, div_shot_stride))) return r;
     }
     return LOSS_OK;
@@ -1011,6 +1047,105 @@ loss_status upload_axis(loss_sim *s, int axis)
     return LOSS_OK;
 }
 
+
+// Elastic adjoint of the fused schedule that loss_forward_ckpt ran.  Forward step n:
+//   B: sigma += (dt lambda) tr(e) I + 2 (dt mu) e, strains e of u^n; stress receivers
+//      record sigma, velocity receivers half of u^n (the half-step-ahead state);
+//   A: u_i += (dt b) sum_j D_j sigma_ij (+ forces); velocity receivers add half of the new u.
+// Reverse step n (bars: adjoints of the fields after step n; the initial half step and
+// the sources carry no parameter):
+//   ubar += residual / 2 (velocity receivers); sigma_ij bar += D_j^T((dt b) u_i bar) for
+//   every (i, j); sigma bar += residual (stress receivers); ubar += residual / 2;
+//   dJ/dlambda, dJ/dmu from the stored strains of u^n and the stress bars; then
+//   u_k bar += D_k^T(dt(lambda + 2 mu) sbar_kk + dt lambda (other normal bars)) and, per
+//   shear pair i < j, u_i bar += D_j^T((dt mu) sbar_ij), u_j bar += D_i^T((dt mu) sbar_ij).
+loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, double *grad, int32_t mem)
+{
+    if (param != LOSS_GRAD_LAME && param != LOSS_GRAD_VPVS)
+        return fail(LOSS_EINVAL, "elastic gradients are LOSS_GRAD_LAME or LOSS_GRAD_VPVS");
+    loss_status r;
+    const int64_t fe = field_elems(s), ss = s->shot_stride;
+    const int S = s->S;
+    for (int k = 0; k < 11; ++k)
+        if (!s->adj_el[k] && (r = s->alloc(&s->adj_el[k], fe))) return r;
+    if (!s->d_adjtab) {
+        if ((r = s->alloc(&s->d_adjtab, 9))) return r;
+        HIPCHK(hipMemcpy(s->d_adjtab, s->adj_el, sizeof(float *) * 9, hipMemcpyHostToDevice));
+    }
+    if (!s->divstore && (r = s->alloc(&s->divstore, (size_t)(6 * s->ck_every * fe)))) return r;
+    if (!s->grad_pad && (r = s->alloc(&s->grad_pad, 2 * ss))) return r;
+    if (!s->grad_dense && (r = s->alloc(&s->grad_dense, 2 * s->nodes))) return r;
+    if (!s->res_dev && (r = s->alloc(&s->res_dev, std::max<int64_t>(1, s->trace_total)))) return r;
+    if (s->trace_total > 0)
+        HIPCHK(hipMemcpyAsync(s->res_dev, residual, sizeof(double) * s->trace_total,
+                              mem == LOSS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->st));
+    for (int k = 0; k < 9; ++k)
+        if (launch_fill(s->adj_el[k], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    HIPCHK(hipMemsetAsync(s->grad_pad, 0, sizeof(double) * 2 * ss, s->st));
+    float *const *A = s->adj_el;
+    float *Y = s->adj_el[9], *Wop = s->adj_el[10];
+    const float *lam = s->med[0], *mu = s->med[1], *l2m = s->med[2], *b = s->med[3];
+    static const int sidx[3][3] = {{LOSS_F_S11, LOSS_F_S12, LOSS_F_S13},
+                                   {LOSS_F_S12, LOSS_F_S22, LOSS_F_S23},
+                                   {LOSS_F_S13, LOSS_F_S23, LOSS_F_S33}};
+    static const int sh[3][3] = {{LOSS_F_S12, 0, 1}, {LOSS_F_S13, 0, 2}, {LOSS_F_S23, 1, 2}};
+    const float *sbar[6] = {A[LOSS_F_S11], A[LOSS_F_S22], A[LOSS_F_S33], A[LOSS_F_S12], A[LOSS_F_S13],
+                            A[LOSS_F_S23]};
+    auto inject_res = [&](const RecDev *rec, int nrec, int64_t n, float w) -> loss_status {
+        if (nrec == 0) return LOSS_OK;
+        loss_status q = timed_begin(s);
+        if (q) return q;
+        const hipError_t e = launch_el_residual_inject(rec, nrec, s->d_adjtab, ss, s->res_dev, n, w, s->st);
+        if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+        return timed_end(s, KC_RECEIVER);
+    };
+    for (int64_t c = s->ck_nseg - 1; c >= 0; --c) {
+        const int64_t n0 = c * s->ck_every, nc = std::min(s->ck_every, s->ck_steps - n0);
+        // restore the fused state at step n0 and recompute the segment, keeping the strains
+        for (int k = 0; k < s->nf; ++k)
+            HIPCHK(hipMemcpyAsync(s->f[k], s->ckpt + (c * s->nf + k) * fe, sizeof(float) * fe,
+                                  hipMemcpyDeviceToDevice, s->st));
+        HIPCHK(launch_set_step(s->d_step, n0, s->st));
+        s->fused = true;
+        if ((r = steps_eager(s, nc, s->divstore, ss))) return r;
+        for (int64_t k = nc - 1; k >= 0; --k) {
+            const int64_t n = n0 + k;
+            if ((r = inject_res(s->d_rec_vel, s->nrec_vel, n, 0.5f))) return r;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    if ((r = adj_deriv(s, j, A[LOSS_F_EV1 + i], b, A[sidx[i][j]], 1.f, EPI_AXPY, Y, S))) return r;
+            if ((r = inject_res(s->d_rec_str, s->nrec_str, n, 1.f))) return r;
+            if ((r = inject_res(s->d_rec_vel, s->nrec_vel, n, 0.5f))) return r;
+            const float *strain[6];
+            for (int q = 0; q < 6; ++q) strain[q] = s->divstore + (k * 6 + q) * fe;
+            if ((r = timed_begin(s))) return r;
+            hipError_t e = launch_el_grad_accum(s->grad_pad, s->grad_pad + ss, strain, sbar, s->d.dt, s->nx,
+                                                s->pitch, ss, S, s->st);
+            if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+            if ((r = timed_end(s, KC_GRAD))) return r;
+            for (int kk = 0; kk < 3; ++kk) {
+                e = launch_el_normal_operand(Wop, A[LOSS_F_S11], A[LOSS_F_S22], A[LOSS_F_S33], l2m, lam, kk, s->nx,
+                                             s->pitch, ss, S, s->st);
+                if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+                if ((r = adj_deriv(s, kk, Wop, nullptr, A[LOSS_F_EV1 + kk], 1.f, EPI_AXPY, Y, S))) return r;
+            }
+            for (int q = 0; q < 3; ++q) {
+                const int sij = sh[q][0], i = sh[q][1], j = sh[q][2];
+                if ((r = adj_deriv(s, j, A[sij], mu, A[LOSS_F_EV1 + i], 1.f, EPI_AXPY, Y, S))) return r;
+                if ((r = adj_deriv(s, i, A[sij], mu, A[LOSS_F_EV1 + j], 1.f, EPI_AXPY, Y, S))) return r;
+            }
+        }
+    }
+    hipError_t e = launch_el_grad_unpad(s->grad_pad, s->grad_pad + ss, s->grad_dense, s->nx, s->pitch, s->d_vp,
+                                        s->d_vs, s->d_rho, param == LOSS_GRAD_VPVS ? 1 : 0, s->nodes, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(grad, s->grad_dense, sizeof(double) * 2 * s->nodes,
+                          mem == LOSS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->step = s->ck_every < s->ck_steps ? s->ck_every : s->ck_steps;
+    return LOSS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1144,9 +1279,10 @@ loss_status loss_set_media(loss_sim *s, const float *vp, const float *vs, const 
     // keep dense vp and rho for the gradient map
     if (s->d_vp) s->release(s->d_vp);
     if (s->d_rho) s->release(s->d_rho);
+    if (s->d_vs) s->release(s->d_vs);
     s->d_vp = dv[0];
+    s->d_vs = dv[1];
     s->d_rho = dv[2];
-    if (dv[1]) { HIPCHK(hipStreamSynchronize(s->st)); s->release(dv[1]); }
     // stability bound of the Strang scheme with the spline symbol (max k* h = sqrt 3)
     std::vector<float> hv(n);
     HIPCHK(hipMemcpyAsync(hv.data(), s->d_vp, sizeof(float) * n, hipMemcpyDeviceToHost, s->st));
@@ -1214,8 +1350,7 @@ loss_status loss_add_receivers(loss_sim *s, int32_t shot, int64_t nrec, const in
 loss_status loss_set_pml(loss_sim *s, int32_t width, double reflection, double kmax, double f0)
 {
     if (!s) return fail(LOSS_EINVAL, "null argument");
-    if (s->d.physics != LOSS_ACOUSTIC) return fail(LOSS_EUNSUPPORTED, "the absorbing layer is built for the acoustic system");
-    if (width < 0 || width > s->d.n[0] / 2 || width > s->d.n[2] / 2)
+    if (width < 0 || width > s->d.n[0] / 2 || width > s->d.n[2] / 2 || (s->d.ndim == 3 && width > s->d.n[1] / 2))
         return fail(LOSS_EINVAL, "layer width must be in 0 .. n/2 on every axis");
     if (width > 0 && (!(reflection > 0.0 && reflection < 1.0) || !(kmax >= 1.0) || !(f0 > 0.0)))
         return fail(LOSS_EINVAL, "need 0 < reflection < 1, kmax >= 1, f0 > 0");
@@ -1223,18 +1358,22 @@ loss_status loss_set_pml(loss_sim *s, int32_t width, double reflection, double k
     loss_status r;
     if ((r = unfuse_in_place(s))) return r;
     drop_graph(s);
-    for (int a : {0, 2}) {
+    for (int a = 0; a < 3; ++a) {
         if (s->pml_tab[a]) { s->release(s->pml_tab[a]); s->pml_tab[a] = nullptr; }
         s->axd[a].pml = nullptr;
         s->axd[a].pml_w = 0;
     }
     if (s->pml_mem) { s->release(s->pml_mem); s->pml_mem = nullptr; }
+    s->npml = 0;
     s->pml_w = width;
     if (width == 0) return LOSS_OK;
     const int64_t fe = field_elems(s);
-    if ((r = s->alloc(&s->pml_mem, (size_t)(4 * fe)))) return r;
-    if (launch_fill(s->pml_mem, 4 * fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
-    for (int a : {0, 2}) {
+    const int npml = s->d.physics == LOSS_ACOUSTIC ? 4 : 18;
+    if ((r = s->alloc(&s->pml_mem, (size_t)(npml * fe)))) return r;
+    s->npml = npml;
+    if (launch_fill(s->pml_mem, npml * fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    for (int a = 0; a < 3; ++a) {
+        if (a == 1 && s->d.ndim == 2) continue;
         const int N = (int)s->d.n[a];
         const double h = s->d.h[a];
         const double d0 = -3.0 * s->cmax * std::log(reflection) / (2.0 * width * h);
@@ -1263,7 +1402,7 @@ loss_status loss_reset(loss_sim *s)
     const int64_t fe = field_elems(s);
     for (int i = 0; i < s->nf; ++i)
         if (launch_fill(s->f[i], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
-    if (s->pml_mem && launch_fill(s->pml_mem, 4 * fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    if (s->pml_mem && launch_fill(s->pml_mem, s->npml * fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
     if (s->traces && s->trace_total > 0)
         HIPCHK(hipMemsetAsync(s->traces, 0, sizeof(double) * s->trace_total, s->st));
     HIPCHK(launch_set_step(s->d_step, 0, s->st));
@@ -1386,7 +1525,7 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     const int64_t fe = field_elems(s);
     float *bk = nullptr;
     double *tbk = nullptr;
-    const int npml = s->pml_mem ? 4 : 0;
+    const int npml = s->pml_mem ? s->npml : 0;
     if ((r = s->alloc(&bk, (size_t)((s->nf + npml) * fe)))) return r;
     if ((r = s->alloc(&tbk, (size_t)std::max<int64_t>(1, s->trace_total)))) return r;
     for (int f = 0; f < s->nf; ++f)
@@ -1468,7 +1607,6 @@ loss_status loss_autotune_choice(loss_sim *s, int32_t axis, int32_t *cw)
 loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
 {
     if (!s) return fail(LOSS_EINVAL, "null argument");
-    if (s->d.physics != LOSS_ACOUSTIC) return fail(LOSS_EUNSUPPORTED, "the adjoint is built for the acoustic system");
     if (nsteps < 1 || ckpt_every < 1) return fail(LOSS_EINVAL, "nsteps and ckpt_every must be >= 1");
     if (s->pml_mem) return fail(LOSS_EUNSUPPORTED, "the adjoint is built without the absorbing layer");
     for (int a = 0; a < 3; ++a)
@@ -1482,15 +1620,14 @@ loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
     const int64_t fe = field_elems(s);
     if (s->ckpt && s->ck_nseg != nseg) { s->release(s->ckpt); s->ckpt = nullptr; }
-    if (!s->ckpt && (r = s->alloc(&s->ckpt, (size_t)(nseg * 3 * fe)))) return r;
+    if (!s->ckpt && (r = s->alloc(&s->ckpt, (size_t)(nseg * s->nf * fe)))) return r;
     if (s->divstore && s->ck_every != ckpt_every) { s->release(s->divstore); s->divstore = nullptr; }
     s->ck_nseg = nseg;
     s->ck_every = ckpt_every;
     s->ck_steps = 0;
-    const int fid[3] = {LOSS_F_SIGMA, LOSS_F_V1, LOSS_F_V3};
     for (int64_t c = 0; c < nseg; ++c) {
-        for (int k = 0; k < 3; ++k)
-            HIPCHK(hipMemcpyAsync(s->ckpt + (c * 3 + k) * fe, s->f[fid[k]], sizeof(float) * fe,
+        for (int k = 0; k < s->nf; ++k)
+            HIPCHK(hipMemcpyAsync(s->ckpt + (c * s->nf + k) * fe, s->f[k], sizeof(float) * fe,
                                   hipMemcpyDeviceToDevice, s->st));
         const int64_t nc = std::min(ckpt_every, nsteps - c * ckpt_every);
         if ((r = run_steps(s, nc, nullptr, 0))) return r;
@@ -1502,8 +1639,9 @@ loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
 loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, double *grad, int32_t mem)
 {
     if (!s || !residual || !grad) return fail(LOSS_EINVAL, "null argument");
-    if (param != LOSS_GRAD_K && param != LOSS_GRAD_VP) return fail(LOSS_EINVAL, "unknown gradient parameter");
     if (s->ck_steps < 1) return fail(LOSS_ESTATE, "loss_forward_ckpt must run first");
+    if (s->d.physics == LOSS_ELASTIC) return elastic_adjoint(s, residual, param, grad, mem);
+    if (param != LOSS_GRAD_K && param != LOSS_GRAD_VP) return fail(LOSS_EINVAL, "unknown gradient parameter");
     loss_status r;
     const int64_t fe = field_elems(s), S = s->S, ss = s->shot_stride;
     const float dt = (float)s->d.dt;
@@ -1521,13 +1659,12 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
     HIPCHK(hipMemsetAsync(s->grad_pad, 0, sizeof(double) * ss, s->st));
     float *lam = s->adj[0], *mu1 = s->adj[1], *mu3 = s->adj[2], *Y = s->adj[3];
     const float *K = s->med[0], *b = s->med[1];
-    const int fid[3] = {LOSS_F_SIGMA, LOSS_F_V1, LOSS_F_V3};
     bool lam_x_done = false;   // the coming step's lambda x pass already applied
     for (int64_t c = s->ck_nseg - 1; c >= 0; --c) {
         const int64_t n0 = c * s->ck_every, nc = std::min(s->ck_every, s->ck_steps - n0);
         // restore the fused state at step n0 and recompute the segment, keeping div u
         for (int k = 0; k < 3; ++k)
-            HIPCHK(hipMemcpyAsync(s->f[fid[k]], s->ckpt + (c * 3 + k) * fe, sizeof(float) * fe,
+            HIPCHK(hipMemcpyAsync(s->f[k], s->ckpt + (c * 3 + k) * fe, sizeof(float) * fe,
                                   hipMemcpyDeviceToDevice, s->st));
         HIPCHK(launch_set_step(s->d_step, n0, s->st));
         s->fused = true;

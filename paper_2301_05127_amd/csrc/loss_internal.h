@@ -189,10 +189,22 @@ struct RecDev {
     int64_t trace_off;                // offset of sample 0 in the trace pool
 };
 
+// elastic adjoint (adjoint_elastic.hip)
+hipError_t launch_el_normal_operand(float *w, const float *s11, const float *s22, const float *s33,
+                                    const float *l2m, const float *lam, int k, int nx, int64_t pitch,
+                                    int64_t per_shot, int S, hipStream_t st);
+hipError_t launch_el_grad_accum(double *gl, double *gm, const float *const *strain, const float *const *sbar,
+                                double dt, int nx, int64_t pitch, int64_t per_shot, int S, hipStream_t st);
+hipError_t launch_el_grad_unpad(const double *gl, const double *gm, double *g, int nx, int64_t pitch,
+                                const float *vp, const float *vs, const float *rho, int to_velocity,
+                                int64_t nodes, hipStream_t st);
+
 hipError_t launch_inject(const SrcDev *src, int nsrc, float *const *fields, const float *b,
                          const float *wpool, const float *wavpool, int64_t shot_stride, int64_t pitch,
                          int64_t plane, const int64_t *d_step, int time_offset, float scale,
                          int want_force, hipStream_t st);
+hipError_t launch_el_residual_inject(const RecDev *rec, int nrec, float *const *adj, int64_t shot_stride,
+                                     const double *res, int64_t n, float w, hipStream_t st);
 hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields, int64_t shot_stride,
                          double *traces, const int64_t *d_step, int64_t trace_len, float weight,
                          int accumulate, hipStream_t st);

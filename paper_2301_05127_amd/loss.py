@@ -22,7 +22,7 @@ F_EV1, F_EV2, F_EV3, F_S11, F_S22, F_S33, F_S12, F_S13, F_S23 = range(9)
 SRC_PRESSURE, SRC_EXPLOSIVE, SRC_FORCE_X, SRC_FORCE_Y, SRC_FORCE_Z = range(5)
 FLAG_NO_GRAPH = 1
 FLAG_NO_FUSE_X = 2
-GRAD_K, GRAD_VP = 0, 1
+GRAD_K, GRAD_VP, GRAD_LAME, GRAD_VPVS = 0, 1, 2, 3
 
 EXPORTS = [
     "loss_create", "loss_destroy", "loss_set_media", "loss_add_source", "loss_add_receivers",
@@ -205,8 +205,8 @@ class Simulation:
         _check(lib().loss_reset(self._h))
 
     def set_pml(self, width, reflection=1e-6, kmax=1.0, f0=15.0):
-        """Absorbing layer of `width` nodes on both ends of x and z (acoustic; see
-        loss_set_pml).  Call after the media are set; width 0 removes it."""
+        """Absorbing layer of `width` nodes on both ends of every axis (acoustic or
+        elastic; see loss_set_pml).  Call after the media are set; width 0 removes it."""
         _check(lib().loss_set_pml(self._h, int(width), float(reflection), float(kmax), float(f0)))
 
     def step(self, n=1):
@@ -261,22 +261,29 @@ class Simulation:
     def forward_ckpt(self, nsteps, ckpt_every):
         _check(lib().loss_forward_ckpt(self._h, int(nsteps), int(ckpt_every)))
 
-    def adjoint(self, residual, param=GRAD_VP):
-        """Gradient of sum(residual * traces) with respect to K or c over the run of the
-        last forward_ckpt.  residual [S][nrec][nt] FP64: a host array (the gradient comes
-        back as a numpy array) or a contiguous CUDA tensor (the gradient is a CUDA tensor)."""
+    def adjoint(self, residual, param=None):
+        """Gradient of sum(residual * traces) over the run of the last forward_ckpt:
+        acoustic with respect to K or c (GRAD_K, GRAD_VP, default GRAD_VP; shape of a
+        field), elastic with respect to (lambda, mu) or (vp, vs) (GRAD_LAME, GRAD_VPVS,
+        default GRAD_VPVS; shape (2, *field)).  residual [S][nrec][nt] FP64: a host array
+        (the gradient comes back as a numpy array) or a contiguous CUDA tensor (the
+        gradient is a CUDA tensor)."""
+        elastic = self.physics == ELASTIC
+        if param is None:
+            param = GRAD_VPVS if elastic else GRAD_VP
+        gshape = ((2,) if elastic else ()) + tuple(self.shape)
         if _is_torch(residual) and residual.is_cuda:
             import torch
             if residual.dtype != torch.float64 or not residual.is_contiguous():
                 raise TypeError("residual must be a contiguous float64 tensor")
-            g = torch.empty(self.shape, dtype=torch.float64, device=residual.device)
+            g = torch.empty(gshape, dtype=torch.float64, device=residual.device)
             # the library runs on its own stream: the residual must be complete first
             torch.cuda.current_stream(residual.device).synchronize()
             _check(lib().loss_adjoint(self._h, ctypes.c_void_p(residual.data_ptr()), param,
                                       ctypes.c_void_p(g.data_ptr()), MEM_DEVICE))
             return g
         r = np.ascontiguousarray(residual, dtype=np.float64)
-        g = np.zeros(self.shape, dtype=np.float64)
+        g = np.zeros(gshape, dtype=np.float64)
         _check(lib().loss_adjoint(self._h, r.ctypes.data_as(ctypes.c_void_p), param,
                                   g.ctypes.data_as(ctypes.c_void_p), MEM_HOST))
         return g

@@ -49,6 +49,10 @@ def interior(a, band):
 
 def oracle_step(orc, w, shot, k, fields, step0, pml):
     sh = w["shots"][shot]
+    if pml and w["physics"] == 1:
+        return orc.run_pml_elastic(w["grid"], pml, w["dt"], k, w["vp"], w["vs"], w["rho"], sources=sh["sources"],
+                                   receivers=sh["receivers"], rec_comp=sh.get("rec_comp", 0), fields_in=fields,
+                                   step0=step0)
     if pml:
         return orc.run_pml(w["grid"], pml, w["dt"], k, w["vp"], w["rho"], sources=sh["sources"],
                            receivers=sh["receivers"], fields_in=fields, step0=step0)
@@ -80,7 +84,7 @@ def main():
                    help="acoustic: also compare the batched adjoint gradient dJ/dK with the oracle's, for the "
                         "residual = the oracle's traces")
     p.add_argument("--pml", type=int, default=0,
-                   help="absorbing layer of this many nodes (acoustic; R = 1e-6, kmax = 1, f0 of the source)")
+                   help="absorbing layer of this many nodes on every side (R = 1e-6, kmax = 1, f0 of the source)")
     p.add_argument("--save-diff", default=None,
                    help="write the GPU - oracle difference of field 0, shot 0, at the end (.npy)")
     p.add_argument("--checkpoints", default="",

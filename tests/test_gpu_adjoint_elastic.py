@@ -1,0 +1,153 @@
+"""GPU elastic adjoint (gradients of a trace misfit with respect to the Lame parameters
+or to vp, vs) against the FP64 oracle's discrete adjoint and FP64 finite differences of
+the oracle's misfit, through the C ABI: batched shots with velocity and stress
+receivers, checkpoints with a ragged last segment."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def _small_elastic_fwi(nsteps=60):
+    """26 x 20 x 22 intervals (patches 12 / 8 / 10 with remainders), halo 5, h = 10 m,
+    smooth vp 2800-3300 m/s, vs near vp / sqrt 3, rho 2000-2400; shot 0 an explosive
+    source with v3 receivers, shot 1 a y force with sigma12 receivers."""
+    from paper_2301_05127_amd import inputs
+    g = inputs.grid(3, (26, 20, 22), (10.0, 10.0, 10.0), (12, 8, 10), 5)
+    shape = (23, 21, 27)
+    vp = _f32(inputs.gaussian_random_field(shape, 10.0, 40.0, 31, 2800.0, 3300.0))
+    vs = _f32(vp / np.sqrt(3.0) * (1.0 + 0.05 * inputs.gaussian_random_field(shape, 10.0, 40.0, 32, -1.0, 1.0)))
+    rho = _f32(inputs.gaussian_random_field(shape, 10.0, 40.0, 33, 2000.0, 2400.0))
+    dt = 1e-3
+
+    def src(kind, pos, shift):
+        return {"kind": kind, "pos": pos, "spread": 15.0,
+                "wavelet": _f32(inputs.ricker(50.0, 0.025, dt, nsteps + 1, shift))}
+
+    rec0 = np.array([[ix, 10, 18] for ix in range(2, 25, 3)], dtype=np.int32)
+    rec1 = np.array([[5, iy, 4] for iy in range(1, 20, 3)] + [[20, 15, iz] for iz in range(2, 21, 6)],
+                    dtype=np.int32)
+    shots = [{"sources": [src(1, (120.0, 90.0, 100.0), 0.5)], "receivers": rec0, "rec_comp": 2},
+             {"sources": [src(3, (150.0, 110.0, 80.0), 0.0)], "receivers": rec1, "rec_comp": 6}]
+    return dict(grid=g, physics=1, dt=dt, nsteps=nsteps, vp=vp, vs=vs, rho=rho, shots=shots)
+
+
+def _obs(orc, w):
+    # observed data from a medium 5 % off: the residual is then large against the FP32
+    # rounding of the traces it is formed from
+    return [orc.run(w["grid"], 1, w["dt"], w["nsteps"], w["vp"] * 1.05, w["rho"], vs=w["vs"] * 0.95,
+                    sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh["rec_comp"])[1]
+            for sh in w["shots"]]
+
+
+def _oracle_grad(orc, w, obs, vp=None, vs=None):
+    vp = w["vp"] if vp is None else vp
+    vs = w["vs"] if vs is None else vs
+    gl = np.zeros_like(vp)
+    gm = np.zeros_like(vp)
+    for s, sh in enumerate(w["shots"]):
+        d0 = orc.run(w["grid"], 1, w["dt"], w["nsteps"], vp, w["rho"], vs=vs, sources=sh["sources"],
+                     receivers=sh["receivers"], rec_comp=sh["rec_comp"])[1]
+        a, b = orc.elastic_adjoint(w["grid"], w["dt"], w["nsteps"], vp, vs, w["rho"], sh["sources"],
+                                   sh["receivers"], sh["rec_comp"], d0 - obs[s])
+        gl += a
+        gm += b
+    return gl, gm
+
+
+def _gpu_grad(w, obs, param, ckpt_every):
+    from paper_2301_05127_amd import loss
+    S, nsteps = len(w["shots"]), w["nsteps"]
+    sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=S, trace_len=nsteps)
+    sim.setup_workload(w)
+    sim.forward_ckpt(nsteps, ckpt_every)
+    tr = [sim.get_traces(s) for s in range(S)]
+    res = np.concatenate([(tr[s] - obs[s]).ravel() for s in range(S)])
+    g = sim.adjoint(res, param)
+    sim.close()
+    return g, tr
+
+
+@pytest.mark.parametrize("ckpt_every", [25, 60])
+def test_lame_gradient_matches_oracle_and_fd(orc, ckpt_every):
+    """Two shots, 60 steps (three checkpoint segments, the last one short, or one): dJ/dlambda
+    and dJ/dmu against the FP64 oracle adjoint, and their directional derivatives against
+    FP64 central differences of the oracle's misfit."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    w = _small_elastic_fwi()
+    announce("elastic gradient (lambda, mu), 2 shots, 60 steps, checkpoints every %d" % ckpt_every)
+    obs = _obs(orc, w)
+    g, tr = _gpu_grad(w, obs, loss.GRAD_LAME, ckpt_every)
+    assert g.shape == (2,) + w["vp"].shape
+    gl, gm = _oracle_grad(orc, w, obs)
+    el, em = rel_l2(g[0], gl), rel_l2(g[1], gm)
+    print("rel-L2 vs oracle: lambda %.2e mu %.2e" % (el, em))
+    assert el < 1e-4 and em < 1e-4, (el, em)
+    # the forward traces themselves
+    for s, sh in enumerate(w["shots"]):
+        d0 = orc.run(w["grid"], 1, w["dt"], w["nsteps"], w["vp"], w["rho"], vs=w["vs"], sources=sh["sources"],
+                     receivers=sh["receivers"], rec_comp=sh["rec_comp"])[1]
+        assert rel_l2(tr[s], d0) < 2e-5, s
+    if ckpt_every != 25:
+        return
+    rho = w["rho"]
+    mu = rho * w["vs"] ** 2
+    lam = rho * w["vp"] ** 2 - 2 * mu
+
+    def J(lm, mm):
+        tot = 0.0
+        for s, sh in enumerate(w["shots"]):
+            d = orc.run(w["grid"], 1, w["dt"], w["nsteps"], np.sqrt((lm + 2 * mm) / rho), rho,
+                        vs=np.sqrt(mm / rho), sources=sh["sources"], receivers=sh["receivers"],
+                        rec_comp=sh["rec_comp"])[1]
+            tot += 0.5 * np.sum((d - obs[s]) ** 2)
+        return tot
+
+    for k, seed in ((0, 7), (1, 8)):
+        dp = inputs.gaussian_random_field(lam.shape, 10.0, 60.0, seed, -1.0, 1.0) * 1e8
+        eps = 1e-3
+        if k == 0:
+            fd = (J(lam + eps * dp, mu) - J(lam - eps * dp, mu)) / (2 * eps)
+        else:
+            fd = (J(lam, mu + eps * dp) - J(lam, mu - eps * dp)) / (2 * eps)
+        an = float(np.sum(g[k] * dp))
+        assert abs(fd - an) <= 1e-4 * abs(fd), (k, fd, an)
+
+
+def test_velocity_gradient_is_the_chain_rule(orc):
+    """GRAD_VPVS: (dJ/dvp, dJ/dvs) with rho fixed equals the chain rule applied to the
+    oracle's Lame gradients: dJ/dvp = 2 rho vp dJ/dlambda,
+    dJ/dvs = 2 rho vs (dJ/dmu - 2 dJ/dlambda)."""
+    require_gpu()
+    from paper_2301_05127_amd import loss
+    w = _small_elastic_fwi()
+    announce("elastic gradient (vp, vs)")
+    obs = _obs(orc, w)
+    g, _ = _gpu_grad(w, obs, loss.GRAD_VPVS, 25)
+    gl, gm = _oracle_grad(orc, w, obs)
+    rho, vp, vs = w["rho"], w["vp"], w["vs"]
+    gvp = 2 * rho * vp * gl
+    gvs = 2 * rho * vs * (gm - 2 * gl)
+    e0, e1 = rel_l2(g[0], gvp), rel_l2(g[1], gvs)
+    print("rel-L2 vs oracle chain rule: vp %.2e vs %.2e" % (e0, e1))
+    assert e0 < 1e-4 and e1 < 1e-4, (e0, e1)
+
+
+def test_elastic_adjoint_refuses_acoustic_parameters():
+    require_gpu()
+    from paper_2301_05127_amd import loss
+    w = _small_elastic_fwi(nsteps=10)
+    sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=2, trace_len=10)
+    sim.setup_workload(w)
+    sim.forward_ckpt(10, 5)
+    res = np.zeros(sum(len(sh["receivers"]) for sh in w["shots"]) * 10)
+    with pytest.raises(loss.LossError):
+        sim.adjoint(res, loss.GRAD_K)
+    sim.close()
