@@ -113,3 +113,13 @@ def test_autograd_wrapper_rejects_host_model():
     m = torch.ones((5, 5), dtype=torch.float64, requires_grad=True)
     with pytest.raises(ValueError, match="CUDA"):
         autograd.seismograms(None, m, torch.ones((5, 5)), 3)
+
+
+def test_elastic_autograd_wrapper_rejects_host_model_and_bad_param():
+    import torch
+    from paper_2301_05127_amd import autograd, loss
+    a = torch.ones((3, 3, 3), dtype=torch.float64, requires_grad=True)
+    with pytest.raises(ValueError, match="CUDA"):
+        autograd.elastic_seismograms(None, a, a, torch.ones((3, 3, 3)), 3)
+    with pytest.raises(ValueError, match="GRAD_VPVS"):
+        autograd.elastic_seismograms(None, a, a, torch.ones((3, 3, 3)), 3, param=loss.GRAD_VP)
