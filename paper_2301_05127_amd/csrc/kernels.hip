@@ -369,30 +369,59 @@ __device__ __forceinline__ float interior_rhs(const AxisDev &ax, float um, float
 // of this pass frozen over tau, the memory variable psi of node j evolves exactly as
 //   psi(tau) = e^{-x} psi0 - (d/k^2) tau phi1(x) D          (x = beta tau)
 // and the field moves by -tau * coef * (D/k + phi1(x) psi0 - (d/k^2) tau phi2(x) D),
-// phi1(x) = (1 - e^{-x})/x, phi2(x) = (x - 1 + e^{-x})/x^2 (series near 0).  Returns that
-// effective derivative, so the epilogue keeps its plain form; stores psi(tau) if asked.
+// phi1(x) = (1 - e^{-x})/x, phi2(x) = (x - 1 + e^{-x})/x^2.  Every factor depends only on
+// the node and the pass's time span, so the host tabulates them (FP64, per step
+// fraction); a node costs two loads and four FMAs.  The pass uses the effective
+// derivative in place of D, so the epilogue keeps its plain form; psi(tau) is stored if
+// asked.
 __device__ __forceinline__ bool in_pml(const AxisDev &ax, int j)
 {
     return j < ax.pml_w || j > ax.N - ax.pml_w;
 }
 
-__device__ __forceinline__ float pml_adjust(const AxisDev &ax, float *__restrict__ mem, float tau, int store,
+// the sub-flow of one node from its table entry t = {e^{-x}, phi1, (d/k^2) tau phi1,
+// 1/k - (d/k^2) tau phi2} and memory value psi0; psi(tau) into *psi1, the effective
+// derivative returned
+__device__ __forceinline__ float pml_flow(float4 t, float D, float psi0, float *psi1)
+{
+    *psi1 = fmaf(t.x, psi0, -t.z * D);
+    return fmaf(t.w, D, t.y * psi0);
+}
+
+__device__ __forceinline__ float pml_adjust(const float4 *__restrict__ tab, float *__restrict__ mem, int store,
                                             int j, int64_t idx, float D)
 {
-    const float4 t = ax.pml[j];
-    const float x = t.x * tau;
-    float phi1, phi2;
-    if (fabsf(x) < 0.1f) {
-        phi1 = 1.f - x * (0.5f - x * (1.f / 6.f - x * (1.f / 24.f - x * (1.f / 120.f - x * (1.f / 720.f)))));
-        phi2 = 0.5f - x * (1.f / 6.f - x * (1.f / 24.f - x * (1.f / 120.f - x * (1.f / 720.f - x * (1.f / 5040.f)))));
-    } else {
-        const float em = expm1f(-x);
-        phi1 = -em / x;
-        phi2 = (x + em) / (x * x);
+    float psi1;
+    const float r = pml_flow(tab[j], D, mem[idx], &psi1);
+    if (store) mem[idx] = psi1;
+    return r;
+}
+
+// The layer on the C nodes q .. q+C-1 of one lane (those below e), node q at memory index
+// idx0 and the next ones `stride` apart: every table entry and memory value is loaded
+// before any flow is evaluated, so the loads of a lane overlap.  Lanes whose nodes miss
+// both bands return at once.
+template <int C>
+__device__ __forceinline__ void pml_run(const AxisDev &ax, const float4 *__restrict__ tab, float *__restrict__ mem,
+                                        int store, int q, int e, int64_t idx0, int64_t stride, float *w)
+{
+    if (q >= ax.pml_w && q + C - 1 <= ax.N - ax.pml_w) return;
+    float4 t[C];
+    float m[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = min(q + c, e - 1);   // a node of the line (e > 0) whatever c
+        t[c] = tab[j];
+        m[c] = mem[idx0 + (int64_t)(j - q) * stride];
     }
-    const float psi0 = mem[idx];
-    if (store) mem[idx] = fmaf(expf(-x), psi0, -t.y * tau * phi1 * D);
-    return fmaf(t.z - t.y * tau * phi2, D, phi1 * psi0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if (q + c < e && in_pml(ax, q + c)) {
+            float psi1;
+            w[c] = pml_flow(t[c], w[c], m[c], &psi1);
+            if (store) mem[idx0 + (int64_t)c * stride] = psi1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -604,11 +633,8 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
     if (uact) {
         const int kc = (e - 1 - s) / C;
         if (a.pml_mem) {
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (q + c < e && in_pml(ax, q + c))
-                    w[c] = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, q + c, base + q + c, w[c]);
-            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, N, base + N, we);
+            pml_run<C>(ax, a.pml_tab, a.pml_mem, a.pml_store, q, e, base + q, 1, w);
+            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(a.pml_tab, a.pml_mem, a.pml_store, N, base + N, we);
         }
         if (vec) {
 #pragma unroll
@@ -673,11 +699,8 @@ __global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__
         ax, k, G, l, true, [&](int i) { return in[i]; }, [&](int i) { return ld4(in + i); }, issue, w);
     if (uact) {
         if (a.pml_mem) {
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (q + c < e && in_pml(ax, q + c))
-                    w[c] = pml_adjust(ax, a.pml_mem, a.pml_tau, 1, q + c, base + q + c, w[c]);
-            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(ax, a.pml_mem, a.pml_tau, 1, N, base + N, we);
+            pml_run<C>(ax, a.pml_tab, a.pml_mem, 1, q, e, base + q, 1, w);
+            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(a.pml_tab, a.pml_mem, 1, N, base + N, we);
         }
         if (vec) {
 #pragma unroll
@@ -712,11 +735,8 @@ __global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__
     if (uact) {
         float *__restrict__ T = Tout + base;
         if (pml_t) {
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (q + c < e && in_pml(ax, q + c))
-                    w[c] = pml_adjust(ax, pml_t, a.pml_tau, 1, q + c, base + q + c, w[c]);
-            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(ax, pml_t, a.pml_tau, 1, N, base + N, we);
+            pml_run<C>(ax, a.pml_tab, pml_t, 1, q, e, base + q, 1, w);
+            if (e == N && k == kc && in_pml(ax, N)) we = pml_adjust(a.pml_tab, pml_t, 1, N, base + N, we);
         }
         if (vec) {
 #pragma unroll
@@ -933,6 +953,8 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
     }
 
     if (cact) {
+        if (a.pml_mem)
+            pml_run<C>(ax, a.pml_tab, a.pml_mem, a.pml_store, q, e, sbase + mbase + (int64_t)q * stride, stride, y);
         const int cy = axis == 1 ? 0 : o, cz = axis == 1 ? o : 0;
         const bool srcs = a.src && segment_has_source(a, shot, axis, col, cy, cz, q, min(q + C, N));
         // receivers of this column among the rows this lane updates: trace sample n
@@ -946,8 +968,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
             const int i = q + c;
             if (i < e) {
                 const int off = mbase + i * stride;
-                float D = y[c];
-                if (a.pml_mem && in_pml(ax, i)) D = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, i, sbase + off, D);
+                const float D = y[c];
                 float v;
                 if constexpr (kPre)
                     v = epilogue_pre<EPI>(a, sbase + off, off, shot, D, pre[c], col, axis == 1 ? i : cy,
@@ -961,7 +982,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
         if (e == N && chunk == kc) {
             const int off = mbase + N * stride;
             float D = we;
-            if (a.pml_mem && in_pml(ax, N)) D = pml_adjust(ax, a.pml_mem, a.pml_tau, a.pml_store, N, sbase + off, D);
+            if (a.pml_mem && in_pml(ax, N)) D = pml_adjust(a.pml_tab, a.pml_mem, a.pml_store, N, sbase + off, D);
             const float v = epilogue<EPI>(a, sbase + off, off, shot, D, col, axis == 1 ? N : cy,
                                           axis == 1 ? cz : N, srcs);
             if (rinfo.y > 0 && rinfo.w == N) {

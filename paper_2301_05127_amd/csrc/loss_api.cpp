@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -177,11 +178,26 @@ float *pml_var(const loss_sim *s, int k)
     return s->pml_mem ? s->pml_mem + (size_t)k * field_elems(s) : nullptr;
 }
 
-void set_pml(const loss_sim *s, LineArgs &a, int k, double tau, bool store)
+// Fractions of dt over which a pass advances the layer: full steps, the half step that
+// opens the fused schedule, the half step back to the integer time.
+constexpr float kPmlFrac[3] = {1.f, 0.5f, -0.5f};
+
+// Point a pass along `axis` at memory variable k, advancing it over frac * dt (one of
+// kPmlFrac; any other value is a programming error of this file).
+void set_pml(const loss_sim *s, LineArgs &a, int axis, int k, float frac, bool store)
 {
     a.pml_mem = pml_var(s, k);
-    a.pml_tau = (float)tau;
+    a.pml_tab = nullptr;
     a.pml_store = store ? 1 : 0;
+    if (!a.pml_mem) return;
+    int fi = -1;
+    for (int i = 0; i < 3; ++i)
+        if (frac == kPmlFrac[i]) fi = i;
+    if (fi < 0) {
+        std::fprintf(stderr, "loss: absorbing layer asked for an untabulated step fraction %g\n", (double)frac);
+        std::abort();
+    }
+    a.pml_tab = s->pml_tab[axis] + (size_t)fi * (s->d.n[axis] + 1);
 }
 
 // 3-D axis index of the grid axis for a 2-D acoustic grid: (x, z) -> (0, 2).
@@ -347,7 +363,7 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             if (base) { a.aux = base[c]; epi = EPI_BASE; }
             // the layer's memory variable advances with the state (an evaluation at
             // another time into a temporary leaves it unchanged)
-            set_pml(s, a, c, frac * s->d.dt, base == nullptr);
+            set_pml(s, a, axis, c, frac, base == nullptr);
             if (with_forces) {
                 const int fid = c == 0 ? LOSS_F_V1 : LOSS_F_V3;
                 attach_sources(s, a, 0, &fid, 1, true);
@@ -370,13 +386,13 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             LineArgs x = base_args(s, 0);
             x.in = s->f[sidx[i][0]];
             x.out[0] = T;
-            set_pml(s, x, 3 * i + 0, frac * s->d.dt, true);
+            set_pml(s, x, 0, 3 * i + 0, frac, true);
             if ((r = run_line(s, KC_VEL_X, 0, SOLVE_D1, EPI_STORE, x))) return r;
             LineArgs y = base_args(s, 1);
             y.in = s->f[sidx[i][1]];
             y.alpha = 1.f;
             y.out[0] = T;
-            set_pml(s, y, 3 * i + 1, frac * s->d.dt, true);
+            set_pml(s, y, 1, 3 * i + 1, frac, true);
             if ((r = run_line(s, KC_VEL_Y, 1, SOLVE_D1, EPI_AXPY, y))) return r;
             LineArgs z = base_args(s, 2);
             z.in = s->f[sidx[i][2]];
@@ -384,7 +400,7 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             z.out[0] = vel[i];
             z.coef[0] = b;
             z.aux = T;
-            set_pml(s, z, 3 * i + 2, frac * s->d.dt, true);
+            set_pml(s, z, 2, 3 * i + 2, frac, true);
             if (with_forces) {
                 const int fid = LOSS_F_EV1 + i;
                 attach_sources(s, z, 0, &fid, 1, true);
@@ -402,7 +418,7 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             a.coef[0] = b;
             int epi = EPI_AXPY;
             if (base && j == 0) { a.aux = base[i]; epi = EPI_BASE; }
-            set_pml(s, a, 3 * i + j, frac * s->d.dt, base == nullptr);
+            set_pml(s, a, j, 3 * i + j, frac, base == nullptr);
             if (with_forces && j == 2) {
                 const int fid = LOSS_F_EV1 + i;
                 attach_sources(s, a, 0, &fid, 1, true);
@@ -420,7 +436,7 @@ loss_status acoustic_stress_x(loss_sim *s)
     LineArgs a = base_args(s, 0);
     a.in = s->f[LOSS_F_V1];
     a.out[0] = s->tmp[0];
-    set_pml(s, a, 2, s->d.dt, true);
+    set_pml(s, a, 0, 2, 1.f, true);
     return run_line(s, KC_STRESS_X, 0, SOLVE_D1, EPI_STORE, a);
 }
 
@@ -435,7 +451,7 @@ loss_status acoustic_stress_z(loss_sim *s, float *div_store, int64_t div_shot_st
     c.alpha = -1.f;
     c.div = div_store;
     c.div_shot_stride = div_shot_stride;
-    set_pml(s, c, 3, s->d.dt, true);
+    set_pml(s, c, 2, 3, 1.f, true);
     const int fid = LOSS_F_SIGMA;
     attach_sources(s, c, -1, &fid, 1, false);
     if (s->d_rcol && s->d.trace_len > 0) {
@@ -457,7 +473,7 @@ loss_status acoustic_velocity(loss_sim *s, int c)
     a.alpha = -1.f;
     a.out[0] = s->f[c == 0 ? LOSS_F_V1 : LOSS_F_V3];
     a.coef[0] = s->med.back();
-    set_pml(s, a, c, s->d.dt, true);
+    set_pml(s, a, axis, c, 1.f, true);
     return run_line(s, c == 0 ? KC_VEL_X : KC_VEL_Z, axis, SOLVE_D1, EPI_AXPY, a);
 }
 
@@ -471,7 +487,7 @@ loss_status acoustic_velocity_stress_x(loss_sim *s)
     a.out[0] = s->f[LOSS_F_V1];
     a.coef[0] = s->med.back();
     a.step_inc = s->d_step;
-    set_pml(s, a, 0, s->d.dt, true);
+    set_pml(s, a, 0, 0, 1.f, true);
     s->pending_inc = false;
     loss_status r = timed_begin(s);
     if (r) return r;
@@ -515,7 +531,7 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         LineArgs a = base_args(s, i);
         a.in = F[LOSS_F_EV1 + i];
         a.out[0] = s->tmp[i];
-        set_pml(s, a, 9 + 4 * i, s->d.dt, true);
+        set_pml(s, a, i, 9 + 4 * i, 1.f, true);
         if ((r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_STORE, a))) return r;
         if (div_store)
             HIPCHK(hipMemcpyAsync(div_store + i * fe, s->tmp[i], sizeof(float) * fe, hipMemcpyDeviceToDevice,
@@ -537,7 +553,7 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         a.coef[1] = lam;
         a.aux = s->tmp[0];
         a.aux2 = s->tmp[1];
-        set_pml(s, a, 9 + 8, s->d.dt, true);
+        set_pml(s, a, 2, 9 + 8, 1.f, true);
         const int fid[3] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33};
         attach_sources(s, a, -1, fid, 3, false);
         if ((r = run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_NORMAL3, a))) return r;
@@ -549,7 +565,7 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         LineArgs t = base_args(s, i);
         t.in = F[LOSS_F_EV1 + j];
         t.out[0] = s->tmp[k];
-        set_pml(s, t, 9 + 3 * j + i, s->d.dt, true);
+        set_pml(s, t, i, 9 + 3 * j + i, 1.f, true);
         if ((r = run_line(s, KC_STRESS_X + i, i, SOLVE_D1, EPI_STORE, t))) return r;
     }
     for (int k = 0; k < 3; ++k) {
@@ -560,7 +576,7 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         a.out[0] = F[sij];
         a.coef[0] = mu;
         a.aux = s->tmp[k];
-        set_pml(s, a, 9 + 3 * i + j, s->d.dt, true);
+        set_pml(s, a, j, 9 + 3 * i + j, 1.f, true);
         if (div_store) {
             a.div = div_store + (3 + k) * fe;
             a.div_shot_stride = div_shot_stride;
@@ -1360,7 +1376,6 @@ loss_status loss_set_pml(loss_sim *s, int32_t width, double reflection, double k
     drop_graph(s);
     for (int a = 0; a < 3; ++a) {
         if (s->pml_tab[a]) { s->release(s->pml_tab[a]); s->pml_tab[a] = nullptr; }
-        s->axd[a].pml = nullptr;
         s->axd[a].pml_w = 0;
     }
     if (s->pml_mem) { s->release(s->pml_mem); s->pml_mem = nullptr; }
@@ -1378,18 +1393,37 @@ loss_status loss_set_pml(loss_sim *s, int32_t width, double reflection, double k
         const double h = s->d.h[a];
         const double d0 = -3.0 * s->cmax * std::log(reflection) / (2.0 * width * h);
         const double amax = 3.14159265358979323846 * f0;
-        std::vector<float4> tab(N + 1);
-        for (int j = 0; j <= N; ++j) {
-            int dist = 0;
-            if (j < width) dist = width - j;
-            if (j > N - width) dist = std::max(dist, j - (N - width));
-            const double del = (double)dist / width;
-            const double d = d0 * del * del, k = 1.0 + (kmax - 1.0) * del, al = amax * (1.0 - del);
-            tab[j] = make_float4((float)(d / k + al), (float)(d / (k * k)), (float)(1.0 / k), 0.f);
+        // per step fraction f and node: the exact sub-flow over tau = f dt with the
+        // derivative D frozen, x = beta tau, beta = d/k + alpha,
+        //   psi(tau) = e^{-x} psi0 - (d/k^2) tau phi1(x) D,
+        //   effective derivative = (1/k - (d/k^2) tau phi2(x)) D + phi1(x) psi0,
+        // phi1 = (1 - e^{-x})/x, phi2 = (x - 1 + e^{-x})/x^2 (series for small x), stored
+        // as {e^{-x}, phi1, (d/k^2) tau phi1, 1/k - (d/k^2) tau phi2} in FP64 -> FP32
+        std::vector<float4> tab(3 * (size_t)(N + 1));
+        for (int fi = 0; fi < 3; ++fi) {
+            const double tau = kPmlFrac[fi] * s->d.dt;
+            for (int j = 0; j <= N; ++j) {
+                int dist = 0;
+                if (j < width) dist = width - j;
+                if (j > N - width) dist = std::max(dist, j - (N - width));
+                const double del = (double)dist / width;
+                const double d = d0 * del * del, k = 1.0 + (kmax - 1.0) * del, al = amax * (1.0 - del);
+                const double x = (d / k + al) * tau, dk2 = d / (k * k);
+                double phi1, phi2;
+                if (std::fabs(x) < 1e-2) {
+                    phi1 = 1.0 - x / 2.0 + x * x / 6.0 - x * x * x / 24.0 + x * x * x * x / 120.0;
+                    phi2 = 0.5 - x / 6.0 + x * x / 24.0 - x * x * x / 120.0 + x * x * x * x / 720.0;
+                } else {
+                    phi1 = -std::expm1(-x) / x;
+                    phi2 = (x + std::expm1(-x)) / (x * x);
+                }
+                tab[(size_t)fi * (N + 1) + j] = make_float4((float)std::exp(-x), (float)phi1,
+                                                            (float)(dk2 * tau * phi1),
+                                                            (float)(1.0 / k - dk2 * tau * phi2));
+            }
         }
-        if ((r = s->alloc(&s->pml_tab[a], N + 1))) return r;
-        HIPCHK(hipMemcpy(s->pml_tab[a], tab.data(), sizeof(float4) * (N + 1), hipMemcpyHostToDevice));
-        s->axd[a].pml = s->pml_tab[a];
+        if ((r = s->alloc(&s->pml_tab[a], 3 * (size_t)(N + 1)))) return r;
+        HIPCHK(hipMemcpy(s->pml_tab[a], tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice));
         s->axd[a].pml_w = width;
     }
     HIPCHK(hipStreamSynchronize(s->st));

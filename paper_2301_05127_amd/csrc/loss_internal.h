@@ -91,8 +91,7 @@ struct AxisDev {
     float4 adjw_plain;     // that column
     const SpecialCol *spec;  // the other nodes, by row
     int nspec;
-    const float4 *pml;     // [N+1] absorbing layer {beta = d/k + alpha, d/k^2, 1/k, 0}, or null
-    int pml_w;             // layer width in nodes (nodes j < pml_w or j > N - pml_w)
+    int pml_w;             // absorbing layer width in nodes (nodes j < pml_w or j > N - pml_w)
 };
 
 // Epilogue of a line kernel.
@@ -151,11 +150,13 @@ struct LineArgs {
     const int64_t *rtoff;
     double *traces;
     int64_t trace_len;
-    // absorbing layer: memory variable of this pass (layout of the fields), the
-    // sub-flow time span (signed seconds), and whether the advanced variable is stored
-    // (a pass that only evaluates the field at another time leaves it unchanged)
+    // absorbing layer: memory variable of this pass (layout of the fields), the per-node
+    // exact sub-flow over this pass's time span, [N+1] {e^{-x}, phi1(x),
+    // (d/k^2) tau phi1(x), 1/k - (d/k^2) tau phi2(x)} with x = (d/k + alpha) tau, and
+    // whether the advanced variable is stored (a pass that only evaluates the field at
+    // another time leaves it unchanged)
     float *pml_mem;
-    float pml_tau;
+    const float4 *pml_tab;
     int pml_store;
 };
 
