@@ -161,3 +161,35 @@ def test_elastic_pml_full_size_few_steps(orc):
             assert e < 1e-5, (s, f, e)
         del rf
     sim.close()
+
+
+@pytest.mark.timeout(300)
+def test_elastic_pml_1000_steps(orc):
+    """1000 steps with the layer, both shots: the waves cross it, then what is left decays
+    by four to five orders of magnitude.  Every field within 1e-5 of the FP64 oracle's
+    layer relative to the largest norm it reached (checkpoints every 50 steps while the
+    fields peak, every 250 after)."""
+    require_gpu()
+    w = _workload(1000)
+    S = len(w["shots"])
+    announce("elastic pml 1000 steps, 2 shots")
+    sim = _gpu(w)
+    pml = dict(PML, cmax=float(w["vp"].max()))
+    of, peak, n0 = [None] * S, np.zeros((S, 9)), 0
+    err = []
+    for k in [50] * 5 + [250] * 3:
+        sim.step(k)
+        row = np.zeros((S, 9))
+        for s, sh in enumerate(w["shots"]):
+            of[s], _ = orc.run_pml_elastic(w["grid"], pml, w["dt"], k, w["vp"], w["vs"], w["rho"],
+                                           sources=sh["sources"], fields_in=of[s], step0=n0)
+            for f in range(9):
+                peak[s, f] = max(peak[s, f], np.linalg.norm(of[s][f]))
+                row[s, f] = np.linalg.norm(sim.get_field(f, shot=s) - of[s][f])
+        err.append(row)
+        n0 += k
+    err = np.array(err) / peak[None]
+    print("error / peak norm at steps 50..250, 500, 750, 1000 (worst field per shot):\n",
+          err.max(axis=2).T)
+    assert err.max() < 1e-5, err.max(axis=(0, 2))
+    sim.close()
