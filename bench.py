@@ -167,8 +167,8 @@ def gradient_ratio(sim, w, S, nsteps, t_fwd):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported (shots and "
-              "space would shard across GPUs, see DESIGN.md)" % a.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported (shots, then "
+              "blocks of patches, would be the units to shard across GPUs)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     if a.grad and a.pml:
         print("bench.py: the adjoint is built without the absorbing layer; drop --pml or --grad",
