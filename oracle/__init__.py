@@ -84,7 +84,7 @@ def lib():
             "or_pml_flow": (None, [c_double, c_double, c_double, c_double, c_double, c_double, D, D]),
             "or_run_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, c_int, S, c_int,
                                    I, D, D, D]),
-            "or_elastic_adjoint": (c_int, [G, c_double, c_int, D, D, D, c_int, S, c_int, I, c_int, D, D, D]),
+            "or_elastic_adjoint": (c_int, [G, c_double, c_int, D, D, D, c_int, S, c_int, I, c_int, D, D, D, D]),
             "or_run_pml_elastic": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, D, c_int, S,
                                            c_int, I, c_int, D, D, D]),
         }
@@ -302,22 +302,23 @@ def acoustic_adjoint(g, dt, nsteps, vp, rho, sources, receivers, residual):
     return grad
 
 
-def elastic_adjoint(g, dt, nsteps, vp, vs, rho, sources, receivers, rec_comp, residual):
+def elastic_adjoint(g, dt, nsteps, vp, vs, rho, sources, receivers, rec_comp, residual, with_b=False):
     """Gradients (dJ/dlambda, dJ/dmu) at every node for J = 1/2 sum residual^2 of the
-    traces of field rec_comp."""
+    traces of field rec_comp; with_b: also dJ/db (b = 1/rho, lambda and mu fixed)."""
     shape = field_shape(g)
     vp, vs, rho = _f64(vp), _f64(vs), _f64(rho)
     src, keep = _sources(list(sources))
     rec = np.ascontiguousarray(receivers, dtype=np.int32)
     res = _f64(residual)
     gl, gm = np.zeros(shape), np.zeros(shape)
+    gb = np.zeros(shape) if with_b else None
     gs = _grid(g)
     rc = lib().or_elastic_adjoint(ctypes.byref(gs), float(dt), int(nsteps), _dp(vp), _dp(vs), _dp(rho),
                                   len(keep), src, rec.shape[0], _ip(rec), int(rec_comp), _dp(res), _dp(gl),
-                                  _dp(gm))
+                                  _dp(gm), _dp(gb))
     if rc != 0:
         raise ValueError("oracle or_elastic_adjoint rejected its arguments (rc=%d)" % rc)
-    return gl, gm
+    return (gl, gm, gb) if with_b else (gl, gm)
 
 
 def rel_l2(x, ref):

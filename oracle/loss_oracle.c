@@ -1047,12 +1047,13 @@ int or_acoustic_adjoint(const or_grid *g, double dt, int nsteps,
  * the normal stress bars, and v_i-bar, v_j-bar gain dt D_j^T (mu sigma_ij-bar),
  * dt D_i^T (mu sigma_ij-bar).  Lambda and mu enter B only:
  *   dJ/dlambda += dt tr(e) S,  dJ/dmu += dt (2 sum_k e_kk sigma_kk-bar + sum g_ij sigma_ij-bar),
- * with the strains of the state B was applied to. */
+ * with the strains of the state B was applied to; b = 1/rho enters A only:
+ *   dJ/db += (dt/2) sum_i (sum_j D_j sigma_ij + f_i W) v_i-bar per velocity half step. */
 int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
                        const double *vp, const double *vs, const double *rho,
                        int nsrc, const or_source *src,
                        int nrec, const int *rec_idx, int rec_comp,
-                       const double *res, double *grad_lam, double *grad_mu)
+                       const double *res, double *grad_lam, double *grad_mu, double *grad_b)
 {
     /* sigma_ij as an index into the fields; shear pairs (i, j) */
     static const int sig_of[3][3] = {{OR_E_S11, OR_E_S12, OR_E_S13},
@@ -1063,7 +1064,7 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
     int n, r, k, a, ci, cj, half;
     double *Dm[3];
     dense_ctx dc[3];
-    double *F, *Fb, *lam, *mu, *b, *t0, *t1, *strain, **W;
+    double *F, *Fb, *lam, *mu, *b, *t0, *t1, *strain, *gsig, **W;
     if (check_grid(g, OR_ELASTIC) || rec_comp < 0 || rec_comp >= 9) return -1;
     grid_nodes(g, nn);
     tot = grid_total(g);
@@ -1077,7 +1078,9 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
     Fb = F + (size_t)9 * tot;
     lam = Fb + (size_t)9 * tot; mu = lam + tot; b = mu + tot; t0 = b + tot; t1 = t0 + tot;
     strain = (double *)malloc(sizeof(double) * (size_t)tot * 6 * nsteps);
-    if (!strain) { free(F); return -2; }
+    /* per velocity half step (2n + h): sum_j D_j sigma_ij + f_i W, what b multiplies */
+    gsig = (double *)calloc((size_t)tot * 3 * 2 * nsteps, sizeof(double));
+    if (!strain || !gsig) { free(strain); free(gsig); free(F); return -2; }
     for (i = 0; i < tot; ++i) {
         b[i] = 1.0 / rho[i];
         mu[i] = rho[i] * vs[i] * vs[i];
@@ -1092,10 +1095,14 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
     for (n = 0; n < nsteps; ++n) {
         for (half = 0; half < 2; ++half) {
             long fk = half == 0 ? n : n + 1;
+            double *gh = gsig + (size_t)(2 * n + half) * 3 * tot;
             for (ci = 0; ci < 3; ++ci)
                 for (cj = 0; cj < 3; ++cj) {
                     apply_lines(g, cj, F + (size_t)sig_of[ci][cj] * tot, t0, dense_op, &dc[cj], 0);
-                    for (i = 0; i < tot; ++i) F[(size_t)(OR_E_V1 + ci) * tot + i] += 0.5 * dt * b[i] * t0[i];
+                    for (i = 0; i < tot; ++i) {
+                        F[(size_t)(OR_E_V1 + ci) * tot + i] += 0.5 * dt * b[i] * t0[i];
+                        gh[(size_t)ci * tot + i] += t0[i];
+                    }
                 }
             for (k = 0; k < nsrc; ++k) {
                 int fld = src[k].kind == OR_SRC_FORCE_X ? OR_E_V1
@@ -1103,7 +1110,10 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
                         : src[k].kind == OR_SRC_FORCE_Z ? OR_E_V3 : -1;
                 double s = sample(&src[k], fk);
                 if (fld < 0) continue;
-                for (i = 0; i < tot; ++i) F[(size_t)fld * tot + i] += 0.5 * dt * b[i] * s * W[k][i];
+                for (i = 0; i < tot; ++i) {
+                    F[(size_t)fld * tot + i] += 0.5 * dt * b[i] * s * W[k][i];
+                    gh[(size_t)(fld - OR_E_V1) * tot + i] += s * W[k][i];
+                }
             }
             if (half == 1) break;
             {
@@ -1135,7 +1145,11 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
         }
     }
     /* reverse sweep */
-    for (i = 0; i < tot; ++i) { grad_lam[i] = 0.0; grad_mu[i] = 0.0; }
+    for (i = 0; i < tot; ++i) {
+        grad_lam[i] = 0.0;
+        grad_mu[i] = 0.0;
+        if (grad_b) grad_b[i] = 0.0;
+    }
     dc[0].transpose = dc[1].transpose = dc[2].transpose = 1;
     for (n = nsteps - 1; n >= 0; --n) {
         const double *e = strain + (size_t)n * 6 * tot;
@@ -1144,6 +1158,15 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
             Fb[(size_t)rec_comp * tot + (iz * nn[1] + iy) * nn[0] + ix] += res[(size_t)r * nsteps + n];
         }
         for (half = 0; half < 2; ++half) {
+            /* dJ/db: (dt/2) (sum_j D_j sigma_ij + f_i W) against v_i-bar, which the
+             * transpose of A leaves unchanged (reverse half 0 undoes the step's second
+             * velocity half step) */
+            if (grad_b) {
+                const double *gh = gsig + (size_t)(2 * n + 1 - half) * 3 * tot;
+                for (ci = 0; ci < 3; ++ci)
+                    for (i = 0; i < tot; ++i)
+                        grad_b[i] += 0.5 * dt * gh[(size_t)ci * tot + i] * Fb[(size_t)(OR_E_V1 + ci) * tot + i];
+            }
             /* transpose of A(dt/2) */
             for (ci = 0; ci < 3; ++ci) {
                 for (i = 0; i < tot; ++i) t1[i] = b[i] * Fb[(size_t)(OR_E_V1 + ci) * tot + i];
@@ -1184,6 +1207,7 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
     for (k = 0; k < nsrc; ++k) free(W[k]);
     free(W);
     free(strain);
+    free(gsig);
     free(F);
     for (a = 0; a < 3; ++a) free(Dm[a]);
     return 0;

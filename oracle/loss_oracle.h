@@ -170,14 +170,15 @@ void or_line_deriv_matrix(int N, double h, int M, int halo, int end_mode, double
 int or_num_fields(int physics);
 
 /* Gradient of J = 1/2 sum_n sum_r (trace - obs)^2 of one elastic 3-D shot with respect to
- * the Lame parameters lambda and mu at every node, given res[r*nsteps+n] = trace - obs
- * for receivers of field rec_comp.  Exact transpose of the canonical Strang scheme
- * (dense line matrices); forward strains kept in memory.  Returns 0 on success. */
+ * the Lame parameters lambda and mu and (grad_b, if not null) the buoyancy b = 1/rho at
+ * every node, given res[r*nsteps+n] = trace - obs for receivers of field rec_comp.
+ * Exact transpose of the canonical Strang scheme (dense line matrices); forward
+ * strains and velocity drives kept in memory.  Returns 0 on success. */
 int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
                        const double *vp, const double *vs, const double *rho,
                        int nsrc, const or_source *src,
                        int nrec, const int *rec_idx, int rec_comp,
-                       const double *res, double *grad_lam, double *grad_mu);
+                       const double *res, double *grad_lam, double *grad_mu, double *grad_b);
 
 #ifdef __cplusplus
 }

@@ -78,3 +78,30 @@ def test_elastic_adjoint_pointwise_fd(orc):
             else:
                 fd = (J(lam, mu + dp) - J(lam, mu - dp)) / (2 * dp[node])
             assert abs(fd - grad[node]) <= 1e-5 * abs(grad).max(), (node, which, fd, grad[node])
+
+
+@pytest.mark.parametrize("rec_comp", [2, 6])
+def test_elastic_adjoint_buoyancy_matches_fd(orc, rec_comp):
+    """dJ/db (b = 1/rho, lambda and mu held fixed), which takes the velocity sub-flow's
+    drive including the force source: its directional derivative along a smooth
+    perturbation of b against central differences of the forward run."""
+    g, dt, nsteps, vp, vs, rho, srcs, rec = _setup(rec_comp)
+    mu = rho * vs ** 2
+    lam = rho * vp ** 2 - 2 * mu
+    obs = orc.run(g, 1, dt, nsteps, vp * 1.01, rho, vs=vs * 0.99, sources=srcs, receivers=rec,
+                  rec_comp=rec_comp)[1]
+
+    def J(bb):
+        r = 1.0 / bb
+        d = orc.run(g, 1, dt, nsteps, np.sqrt((lam + 2 * mu) / r), r, vs=np.sqrt(mu / r), sources=srcs,
+                    receivers=rec, rec_comp=rec_comp)[1]
+        return 0.5 * np.sum((d - obs) ** 2)
+
+    d0 = orc.run(g, 1, dt, nsteps, vp, rho, vs=vs, sources=srcs, receivers=rec, rec_comp=rec_comp)[1]
+    _, _, gb = orc.elastic_adjoint(g, dt, nsteps, vp, vs, rho, srcs, rec, rec_comp, d0 - obs, with_b=True)
+    b = 1.0 / rho
+    db = inputs.gaussian_random_field(b.shape, 10.0, 50.0, 9, -1.0, 1.0) * 1e-5
+    eps = 1e-3
+    fd = (J(b + eps * db) - J(b - eps * db)) / (2 * eps)
+    an = float(np.sum(gb * db))
+    assert abs(fd - an) <= 1e-7 * abs(an), (fd, an)
