@@ -200,8 +200,9 @@ loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *
  * (float64).  Acoustic: param = LOSS_GRAD_K (bulk modulus K) or LOSS_GRAD_VP (c with rho
  * fixed: 2 rho c dJ/dK), grad = nodes values.  Elastic: param = LOSS_GRAD_LAME
  * (grad = dJ/dlambda then dJ/dmu, 2 x nodes) or LOSS_GRAD_VPVS (dJ/dvp then dJ/dvs with
- * rho fixed, 2 x nodes); the segment recompute keeps six strain fields per step
- * (6 x ckpt_every fields of device memory).  The adjoint applies the exact transpose
+ * rho fixed, 2 x nodes); LOSS_GRAD_LAME_RHO / LOSS_GRAD_VPVS_RHO append dJ/drho (with
+ * lambda, mu resp. vp, vs fixed; 3 x nodes).  The segment recompute keeps six strain
+ * fields per step, nine with the density (6 or 9 x ckpt_every fields of device memory).  The adjoint applies the exact transpose
  * of every discrete operator of the time-stepping scheme; forward states are
  * recomputed from the checkpoints segment by segment.  Afterwards the wavefields hold
  * an intermediate state (call loss_reset).  Errors: LOSS_EUNSUPPORTED (absorbing layer,
@@ -211,6 +212,8 @@ loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *
 #define LOSS_GRAD_VP   1
 #define LOSS_GRAD_LAME 2
 #define LOSS_GRAD_VPVS 3
+#define LOSS_GRAD_LAME_RHO 4
+#define LOSS_GRAD_VPVS_RHO 5
 loss_status loss_forward_ckpt(loss_sim *sim, int64_t nsteps, int64_t ckpt_every);
 loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, double *grad,
                          int32_t mem);

@@ -71,6 +71,47 @@ __global__ void k_el_grad_accum(double *__restrict__ gl, double *__restrict__ gm
     gm[p] += dt * am;
 }
 
+// dJ/db += dt sum_i ubar_i (sum_j D_j sigma_ij) per velocity step (b = 1/rho drives the
+// velocity sub-flow only), summed over shots in FP64; div: the three drives of the step,
+// ubar: the velocity bars after it.
+struct Three {
+    const float *p[3];
+};
+
+__global__ void k_el_grad_b(double *__restrict__ gb, Three ub, Three dv, double dt, int nx, int64_t pitch,
+                            int64_t per_shot, int S, int64_t total_one_shot)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total_one_shot) return;
+    int64_t so, p;
+    if (!valid_node(i, nx, pitch, per_shot, 1, &so, &p)) return;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const int64_t q = (int64_t)s * per_shot + p;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc += (double)ub.p[c][q] * (double)dv.p[c][q];
+    }
+    gb[p] += dt * acc;
+}
+
+// the body-force part of the same term: dJ/db += scale f(t_n) w(x) ubar_comp(x) over each
+// force source's footprint (one block per source, FP64 atomics: shots share nodes)
+__global__ void k_el_grad_force(double *gb, const SrcDev *__restrict__ src, float *const *adj,
+                                const float *__restrict__ wpool, const float *__restrict__ wavpool,
+                                int64_t shot_stride, int64_t pitch, int64_t plane, int64_t n, double scale)
+{
+    const SrcDev sd = src[blockIdx.x];
+    if (!sd.force || n < 0 || n >= sd.nt) return;
+    const double amp = scale * (double)wavpool[sd.wav_off + n];
+    const int tot = sd.bx * sd.by * sd.bz;
+    const float *ub = adj[sd.field0] + (int64_t)sd.shot * shot_stride;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        const int ix = t % sd.bx, iy = (t / sd.bx) % sd.by, iz = t / (sd.bx * sd.by);
+        const int64_t midx = (int64_t)(sd.z0 + iz) * plane + (int64_t)(sd.y0 + iy) * pitch + (sd.x0 + ix);
+        atomicAdd(gb + midx, amp * (double)wpool[sd.w_off + t] * (double)ub[midx]);
+    }
+}
+
 // adjoint field rec.comp += w * residual sample n, for every receiver
 __global__ void k_el_residual_inject(const RecDev *__restrict__ rec, int nrec, float *const *adj,
                                      int64_t shot_stride, const double *__restrict__ res, int64_t n, float w)
@@ -81,26 +122,28 @@ __global__ void k_el_residual_inject(const RecDev *__restrict__ rec, int nrec, f
     atomicAdd(adj[rd.comp] + (int64_t)rd.shot * shot_stride + rd.node, w * (float)res[rd.trace_off + n]);
 }
 
-// padded accumulators -> dense gradients: (dJ/dlambda, dJ/dmu) or, with rho fixed,
-// (dJ/dvp, dJ/dvs) from lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2
-__global__ void k_el_grad_unpad(const double *__restrict__ gl, const double *__restrict__ gm, double *g,
-                                int nx, int64_t pitch, const float *__restrict__ vp, const float *__restrict__ vs,
-                                const float *__restrict__ rho, int to_velocity, int64_t nodes)
+// padded accumulators -> dense gradients.  mode 0: (dJ/dlambda, dJ/dmu); 1: (dJ/dvp,
+// dJ/dvs) with rho fixed, from lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2; 2: mode 0 and
+// dJ/drho with lambda, mu fixed (= -b^2 dJ/db); 3: mode 1 and dJ/drho with vp, vs fixed
+// (= dJ/dlambda (vp^2 - 2 vs^2) + dJ/dmu vs^2 - b^2 dJ/db).
+__global__ void k_el_grad_unpad(const double *__restrict__ gl, const double *__restrict__ gm,
+                                const double *__restrict__ gb, double *g, int nx, int64_t pitch,
+                                const float *__restrict__ vp, const float *__restrict__ vs,
+                                const float *__restrict__ rho, int mode, int64_t nodes)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nodes) return;
     const int x = (int)(idx % nx);
     const int64_t p = (idx / nx) * pitch + x;
-    double a = gl[p], b = gm[p];
-    if (to_velocity) {
-        const double r = rho[idx], cp = vp[idx], cs = vs[idx];
-        const double dvp = a * 2.0 * r * cp;
-        const double dvs = a * (-4.0 * r * cs) + b * 2.0 * r * cs;
-        a = dvp;
-        b = dvs;
+    const double a = gl[p], b = gm[p];
+    const double r = rho[idx], cp = vp[idx], cs = vs[idx];
+    const bool vel = mode == 1 || mode == 3;
+    g[idx] = vel ? a * 2.0 * r * cp : a;
+    g[nodes + idx] = vel ? a * (-4.0 * r * cs) + b * 2.0 * r * cs : b;
+    if (mode >= 2) {
+        const double drho_lm = -gb[p] / (r * r);
+        g[2 * nodes + idx] = mode == 2 ? drho_lm : a * (cp * cp - 2.0 * cs * cs) + b * cs * cs + drho_lm;
     }
-    g[idx] = a;
-    g[nodes + idx] = b;
 }
 
 }  // namespace
@@ -127,6 +170,27 @@ hipError_t launch_el_grad_accum(double *gl, double *gm, const float *const *stra
     return hipGetLastError();
 }
 
+hipError_t launch_el_grad_b(double *gb, const float *const *ubar, const float *const *div, double dt, int nx,
+                            int64_t pitch, int64_t per_shot, int S, hipStream_t st)
+{
+    Three u, d;
+    for (int k = 0; k < 3; ++k) { u.p[k] = ubar[k]; d.p[k] = div[k]; }
+    const int64_t total = (per_shot / pitch) * nx;
+    hipLaunchKernelGGL(k_el_grad_b, (unsigned)((total + 255) / 256), 256, 0, st, gb, u, d, dt, nx, pitch, per_shot, S,
+                       total);
+    return hipGetLastError();
+}
+
+hipError_t launch_el_grad_force(double *gb, const SrcDev *src, int nsrc, float *const *adj, const float *wpool,
+                                const float *wavpool, int64_t shot_stride, int64_t pitch, int64_t plane, int64_t n,
+                                double scale, hipStream_t st)
+{
+    if (nsrc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_el_grad_force, nsrc, 256, 0, st, gb, src, adj, wpool, wavpool, shot_stride, pitch, plane, n,
+                       scale);
+    return hipGetLastError();
+}
+
 hipError_t launch_el_residual_inject(const RecDev *rec, int nrec, float *const *adj, int64_t shot_stride,
                                      const double *res, int64_t n, float w, hipStream_t st)
 {
@@ -136,12 +200,12 @@ hipError_t launch_el_residual_inject(const RecDev *rec, int nrec, float *const *
     return hipGetLastError();
 }
 
-hipError_t launch_el_grad_unpad(const double *gl, const double *gm, double *g, int nx, int64_t pitch,
-                                const float *vp, const float *vs, const float *rho, int to_velocity,
+hipError_t launch_el_grad_unpad(const double *gl, const double *gm, const double *gb, double *g, int nx,
+                                int64_t pitch, const float *vp, const float *vs, const float *rho, int mode,
                                 int64_t nodes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_el_grad_unpad, (unsigned)((nodes + 255) / 256), 256, 0, st, gl, gm, g, nx, pitch, vp,
-                       vs, rho, to_velocity, nodes);
+    hipLaunchKernelGGL(k_el_grad_unpad, (unsigned)((nodes + 255) / 256), 256, 0, st, gl, gm, gb, g, nx, pitch, vp,
+                       vs, rho, mode, nodes);
     return hipGetLastError();
 }
 

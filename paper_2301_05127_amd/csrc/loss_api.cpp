@@ -116,7 +116,9 @@ struct loss_sim {
     float *ckpt = nullptr;         // [nseg][nf fields][S][shot_stride] fused states
     int64_t ck_every = 0, ck_steps = 0, ck_nseg = 0;
     // per recomputed step, acoustic: div u; elastic: e11, e22, e33, g12, g13, g23
-    float *divstore = nullptr;     // [ck_every][1 or 6][S][shot_stride]
+    float *divstore = nullptr;     // [ck_every][1, 6 or 9][S][shot_stride]
+    int strain_slots = 6;          // elastic: strains, then the three velocity drives if 9
+    int divstore_slots = 0;        // slots per step divstore was allocated with
     float *adj[4] = {nullptr, nullptr, nullptr, nullptr};   // lambda, mu1, mu3, Y scratch
     float *adj_el[11] = {};        // elastic: the 9 field bars (field order), Y scratch, operand
     float **d_adjtab = nullptr;    // device copy of adj_el[0..8]
@@ -346,7 +348,7 @@ loss_status record(loss_sim *s, const RecDev *rec0, int nrec0, float w0, int acc
 // `vel` are the velocity destinations (state or a temporary), `base` optional source
 // for EPI_BASE on the first pass of each component.
 loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const float *const *base,
-                           bool with_forces = false)
+                           bool with_forces = false, float *div_store = nullptr, int64_t div_shot_stride = 0)
 {
     const float *b = s->med.back();
     loss_status r;
@@ -401,6 +403,10 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
             z.coef[0] = b;
             z.aux = T;
             set_pml(s, z, 2, 3 * i + 2, frac, true);
+            if (div_store) {   // the drive sum_j d_j sigma_ij of v_i, for the buoyancy gradient
+                z.div = div_store + i * field_elems(s);
+                z.div_shot_stride = div_shot_stride;
+            }
             if (with_forces) {
                 const int fid = LOSS_F_EV1 + i;
                 attach_sources(s, z, 0, &fid, 1, true);
@@ -843,7 +849,9 @@ loss_status one_step(loss_sim *s, float *div_store, int64_t div_shot_stride)
     std::vector<float *> vel;
     if (s->d.physics == LOSS_ACOUSTIC) vel = {s->f[LOSS_F_V1], s->f[LOSS_F_V3]};
     else vel = {s->f[LOSS_F_EV1], s->f[LOSS_F_EV2], s->f[LOSS_F_EV3]};
-    if ((r = velocity_stage(s, 1.0f, vel.data(), nullptr, true))) return r;
+    float *vdiv = (div_store && s->d.physics == LOSS_ELASTIC && s->strain_slots == 9)
+                      ? div_store + 6 * field_elems(s) : nullptr;
+    if ((r = velocity_stage(s, 1.0f, vel.data(), nullptr, true, vdiv, div_shot_stride))) return r;
     if ((r = record(s, s->d_rec_vel, s->nrec_vel, 0.5f, 1))) return r;
     return LOSS_OK;
 }
@@ -873,7 +881,7 @@ loss_status steps_eager(loss_sim *s, int64_t K, float *div_store = nullptr, int6
 {
     loss_status r;
     if (K > 0 && fused_x_ok(s)) return steps_fused_x(s, K, div_store, div_shot_stride);
-    const int64_t nslot = s->d.physics == LOSS_ACOUSTIC ? 1 : 6;
+    const int64_t nslot = s->d.physics == LOSS_ACOUSTIC ? 1 : s->strain_slots;
     for (int64_t done = 0; done < K; ++done) {
         float *ds = div_store ? div_store + done * nslot * s->S * div_shot_stride : nullptr;
         if ((r = one_step(s, ds, div_shot_stride))) return r;
@@ -1077,27 +1085,36 @@ loss_status upload_axis(loss_sim *s, int axis)
 //   shear pair i < j, u_i bar += D_j^T((dt mu) sbar_ij), u_j bar += D_i^T((dt mu) sbar_ij).
 loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, double *grad, int32_t mem)
 {
-    if (param != LOSS_GRAD_LAME && param != LOSS_GRAD_VPVS)
-        return fail(LOSS_EINVAL, "elastic gradients are LOSS_GRAD_LAME or LOSS_GRAD_VPVS");
+    if (param != LOSS_GRAD_LAME && param != LOSS_GRAD_VPVS && param != LOSS_GRAD_LAME_RHO &&
+        param != LOSS_GRAD_VPVS_RHO)
+        return fail(LOSS_EINVAL, "elastic gradients are LOSS_GRAD_LAME, LOSS_GRAD_VPVS or their _RHO forms");
+    const bool want_b = param == LOSS_GRAD_LAME_RHO || param == LOSS_GRAD_VPVS_RHO;
     loss_status r;
     const int64_t fe = field_elems(s), ss = s->shot_stride;
     const int S = s->S;
+    const int slots = want_b ? 9 : 6;
+    if (s->divstore && s->divstore_slots < slots) { s->release(s->divstore); s->divstore = nullptr; }
     for (int k = 0; k < 11; ++k)
         if (!s->adj_el[k] && (r = s->alloc(&s->adj_el[k], fe))) return r;
     if (!s->d_adjtab) {
         if ((r = s->alloc(&s->d_adjtab, 9))) return r;
         HIPCHK(hipMemcpy(s->d_adjtab, s->adj_el, sizeof(float *) * 9, hipMemcpyHostToDevice));
     }
-    if (!s->divstore && (r = s->alloc(&s->divstore, (size_t)(6 * s->ck_every * fe)))) return r;
-    if (!s->grad_pad && (r = s->alloc(&s->grad_pad, 2 * ss))) return r;
-    if (!s->grad_dense && (r = s->alloc(&s->grad_dense, 2 * s->nodes))) return r;
+    if (!s->divstore) {
+        if ((r = s->alloc(&s->divstore, (size_t)(slots * s->ck_every * fe)))) return r;
+        s->divstore_slots = slots;
+    }
+    s->strain_slots = slots;
+    if (!s->grad_pad && (r = s->alloc(&s->grad_pad, 3 * ss))) return r;
+    if (!s->grad_dense && (r = s->alloc(&s->grad_dense, 3 * s->nodes))) return r;
     if (!s->res_dev && (r = s->alloc(&s->res_dev, std::max<int64_t>(1, s->trace_total)))) return r;
     if (s->trace_total > 0)
         HIPCHK(hipMemcpyAsync(s->res_dev, residual, sizeof(double) * s->trace_total,
                               mem == LOSS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->st));
     for (int k = 0; k < 9; ++k)
         if (launch_fill(s->adj_el[k], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
-    HIPCHK(hipMemsetAsync(s->grad_pad, 0, sizeof(double) * 2 * ss, s->st));
+    HIPCHK(hipMemsetAsync(s->grad_pad, 0, sizeof(double) * 3 * ss, s->st));
+    double *gb = s->grad_pad + 2 * ss;
     float *const *A = s->adj_el;
     float *Y = s->adj_el[9], *Wop = s->adj_el[10];
     const float *lam = s->med[0], *mu = s->med[1], *l2m = s->med[2], *b = s->med[3];
@@ -1127,13 +1144,26 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
         for (int64_t k = nc - 1; k >= 0; --k) {
             const int64_t n = n0 + k;
             if ((r = inject_res(s->d_rec_vel, s->nrec_vel, n, 0.5f))) return r;
+            if (want_b) {
+                // the velocity step of step n drove u with (dt b)(sum_j D_j sigma_ij + f(t_{n+1}) w)
+                const float *ub[3] = {A[LOSS_F_EV1], A[LOSS_F_EV2], A[LOSS_F_EV3]};
+                const float *dv[3];
+                for (int q = 0; q < 3; ++q) dv[q] = s->divstore + (k * slots + 6 + q) * fe;
+                if ((r = timed_begin(s))) return r;
+                hipError_t e = launch_el_grad_b(gb, ub, dv, s->d.dt, s->nx, s->pitch, ss, S, s->st);
+                if (e == hipSuccess)
+                    e = launch_el_grad_force(gb, s->d_src, s->nsrc, s->d_adjtab, s->d_wpool, s->d_wavpool, ss,
+                                             s->pitch, s->plane, n + 1, s->d.dt, s->st);
+                if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+                if ((r = timed_end(s, KC_GRAD))) return r;
+            }
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j)
                     if ((r = adj_deriv(s, j, A[LOSS_F_EV1 + i], b, A[sidx[i][j]], 1.f, EPI_AXPY, Y, S))) return r;
             if ((r = inject_res(s->d_rec_str, s->nrec_str, n, 1.f))) return r;
             if ((r = inject_res(s->d_rec_vel, s->nrec_vel, n, 0.5f))) return r;
             const float *strain[6];
-            for (int q = 0; q < 6; ++q) strain[q] = s->divstore + (k * 6 + q) * fe;
+            for (int q = 0; q < 6; ++q) strain[q] = s->divstore + (k * slots + q) * fe;
             if ((r = timed_begin(s))) return r;
             hipError_t e = launch_el_grad_accum(s->grad_pad, s->grad_pad + ss, strain, sbar, s->d.dt, s->nx,
                                                 s->pitch, ss, S, s->st);
@@ -1152,10 +1182,17 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
             }
         }
     }
-    hipError_t e = launch_el_grad_unpad(s->grad_pad, s->grad_pad + ss, s->grad_dense, s->nx, s->pitch, s->d_vp,
-                                        s->d_vs, s->d_rho, param == LOSS_GRAD_VPVS ? 1 : 0, s->nodes, s->st);
+    hipError_t e = hipSuccess;
+    if (want_b)   // the opening half step drove u with (dt/2) b f(t_0) w (the state starts at rest)
+        e = launch_el_grad_force(gb, s->d_src, s->nsrc, s->d_adjtab, s->d_wpool, s->d_wavpool, ss, s->pitch,
+                                 s->plane, 0, 0.5 * s->d.dt, s->st);
+    if (e == hipSuccess) {
+        const int mode = param == LOSS_GRAD_LAME ? 0 : param == LOSS_GRAD_VPVS ? 1 : param == LOSS_GRAD_LAME_RHO ? 2 : 3;
+        e = launch_el_grad_unpad(s->grad_pad, s->grad_pad + ss, gb, s->grad_dense, s->nx, s->pitch, s->d_vp, s->d_vs,
+                                 s->d_rho, mode, s->nodes, s->st);
+    }
     if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
-    HIPCHK(hipMemcpyAsync(grad, s->grad_dense, sizeof(double) * 2 * s->nodes,
+    HIPCHK(hipMemcpyAsync(grad, s->grad_dense, sizeof(double) * (want_b ? 3 : 2) * s->nodes,
                           mem == LOSS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     s->step = s->ck_every < s->ck_steps ? s->ck_every : s->ck_steps;

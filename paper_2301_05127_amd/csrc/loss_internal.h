@@ -196,14 +196,19 @@ hipError_t launch_el_normal_operand(float *w, const float *s11, const float *s22
                                     int64_t per_shot, int S, hipStream_t st);
 hipError_t launch_el_grad_accum(double *gl, double *gm, const float *const *strain, const float *const *sbar,
                                 double dt, int nx, int64_t pitch, int64_t per_shot, int S, hipStream_t st);
-hipError_t launch_el_grad_unpad(const double *gl, const double *gm, double *g, int nx, int64_t pitch,
-                                const float *vp, const float *vs, const float *rho, int to_velocity,
+hipError_t launch_el_grad_unpad(const double *gl, const double *gm, const double *gb, double *g, int nx,
+                                int64_t pitch, const float *vp, const float *vs, const float *rho, int mode,
                                 int64_t nodes, hipStream_t st);
+hipError_t launch_el_grad_b(double *gb, const float *const *ubar, const float *const *div, double dt, int nx,
+                            int64_t pitch, int64_t per_shot, int S, hipStream_t st);
 
 hipError_t launch_inject(const SrcDev *src, int nsrc, float *const *fields, const float *b,
                          const float *wpool, const float *wavpool, int64_t shot_stride, int64_t pitch,
                          int64_t plane, const int64_t *d_step, int time_offset, float scale,
                          int want_force, hipStream_t st);
+hipError_t launch_el_grad_force(double *gb, const SrcDev *src, int nsrc, float *const *adj, const float *wpool,
+                                const float *wavpool, int64_t shot_stride, int64_t pitch, int64_t plane, int64_t n,
+                                double scale, hipStream_t st);
 hipError_t launch_el_residual_inject(const RecDev *rec, int nrec, float *const *adj, int64_t shot_stride,
                                      const double *res, int64_t n, float w, hipStream_t st);
 hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields, int64_t shot_stride,

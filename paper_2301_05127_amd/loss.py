@@ -22,7 +22,7 @@ F_EV1, F_EV2, F_EV3, F_S11, F_S22, F_S33, F_S12, F_S13, F_S23 = range(9)
 SRC_PRESSURE, SRC_EXPLOSIVE, SRC_FORCE_X, SRC_FORCE_Y, SRC_FORCE_Z = range(5)
 FLAG_NO_GRAPH = 1
 FLAG_NO_FUSE_X = 2
-GRAD_K, GRAD_VP, GRAD_LAME, GRAD_VPVS = 0, 1, 2, 3
+GRAD_K, GRAD_VP, GRAD_LAME, GRAD_VPVS, GRAD_LAME_RHO, GRAD_VPVS_RHO = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
     "loss_create", "loss_destroy", "loss_set_media", "loss_add_source", "loss_add_receivers",
@@ -265,13 +265,14 @@ class Simulation:
         """Gradient of sum(residual * traces) over the run of the last forward_ckpt:
         acoustic with respect to K or c (GRAD_K, GRAD_VP, default GRAD_VP; shape of a
         field), elastic with respect to (lambda, mu) or (vp, vs) (GRAD_LAME, GRAD_VPVS,
-        default GRAD_VPVS; shape (2, *field)).  residual [S][nrec][nt] FP64: a host array
+        default GRAD_VPVS; shape (2, *field)), or those and rho (GRAD_LAME_RHO,
+        GRAD_VPVS_RHO; shape (3, *field)).  residual [S][nrec][nt] FP64: a host array
         (the gradient comes back as a numpy array) or a contiguous CUDA tensor (the
         gradient is a CUDA tensor)."""
         elastic = self.physics == ELASTIC
         if param is None:
             param = GRAD_VPVS if elastic else GRAD_VP
-        gshape = ((2,) if elastic else ()) + tuple(self.shape)
+        gshape = (((3,) if param in (GRAD_LAME_RHO, GRAD_VPVS_RHO) else (2,)) if elastic else ()) + tuple(self.shape)
         if _is_torch(residual) and residual.is_cuda:
             import torch
             if residual.dtype != torch.float64 or not residual.is_contiguous():

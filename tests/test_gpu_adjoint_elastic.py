@@ -46,19 +46,22 @@ def _obs(orc, w):
             for sh in w["shots"]]
 
 
-def _oracle_grad(orc, w, obs, vp=None, vs=None):
+def _oracle_grad(orc, w, obs, vp=None, vs=None, with_b=False):
     vp = w["vp"] if vp is None else vp
     vs = w["vs"] if vs is None else vs
     gl = np.zeros_like(vp)
     gm = np.zeros_like(vp)
+    gb = np.zeros_like(vp)
     for s, sh in enumerate(w["shots"]):
         d0 = orc.run(w["grid"], 1, w["dt"], w["nsteps"], vp, w["rho"], vs=vs, sources=sh["sources"],
                      receivers=sh["receivers"], rec_comp=sh["rec_comp"])[1]
-        a, b = orc.elastic_adjoint(w["grid"], w["dt"], w["nsteps"], vp, vs, w["rho"], sh["sources"],
-                                   sh["receivers"], sh["rec_comp"], d0 - obs[s])
-        gl += a
-        gm += b
-    return gl, gm
+        out = orc.elastic_adjoint(w["grid"], w["dt"], w["nsteps"], vp, vs, w["rho"], sh["sources"],
+                                  sh["receivers"], sh["rec_comp"], d0 - obs[s], with_b=with_b)
+        gl += out[0]
+        gm += out[1]
+        if with_b:
+            gb += out[2]
+    return (gl, gm, gb) if with_b else (gl, gm)
 
 
 def _gpu_grad(w, obs, param, ckpt_every):
@@ -199,3 +202,43 @@ def test_elastic_autograd_matches_adjoint(orc, param):
     g = d.adjoint(tb - obs, param)
     assert rel_l2(ga, g[0]) < 1e-12 and rel_l2(gb, g[1]) < 1e-12
     sim.close(); d.close()
+
+
+def test_density_gradient_matches_oracle_and_fd(orc):
+    """GRAD_LAME_RHO: dJ/drho with lambda and mu fixed (= -dJ/db / rho^2, b = 1/rho drives
+    the velocity sub-flow and the body force) against the FP64 oracle, and its directional
+    derivative along the oracle's gradient against FP64 central differences; GRAD_VPVS_RHO
+    against the chain rule (dJ/drho with vp, vs fixed)."""
+    require_gpu()
+    from paper_2301_05127_amd import loss
+    w = _small_elastic_fwi()
+    announce("elastic gradient (lambda, mu, rho)")
+    obs = _obs(orc, w)
+    g, _ = _gpu_grad(w, obs, loss.GRAD_LAME_RHO, 25)
+    assert g.shape == (3,) + w["vp"].shape
+    gl, gm, gb = _oracle_grad(orc, w, obs, with_b=True)
+    rho, vp, vs = w["rho"], w["vp"], w["vs"]
+    grho = -gb / rho ** 2
+    e = [rel_l2(g[0], gl), rel_l2(g[1], gm), rel_l2(g[2], grho)]
+    print("rel-L2 vs oracle: lambda %.2e mu %.2e rho %.2e" % tuple(e))
+    assert max(e) < 1e-4, e
+    mu = rho * vs ** 2
+    lam = rho * vp ** 2 - 2 * mu
+
+    def J(r):
+        tot = 0.0
+        for s, sh in enumerate(w["shots"]):
+            d = orc.run(w["grid"], 1, w["dt"], w["nsteps"], np.sqrt((lam + 2 * mu) / r), r, vs=np.sqrt(mu / r),
+                        sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh["rec_comp"])[1]
+            tot += 0.5 * np.sum((d - obs[s]) ** 2)
+        return tot
+
+    dr = grho / np.abs(grho).max() * 0.2                 # at most 0.01 % of rho
+    fd = (J(rho + dr) - J(rho - dr)) / 2.0
+    an = float(np.sum(g[2] * dr))
+    assert abs(fd - an) <= 1e-4 * abs(fd), (fd, an)
+    gv, _ = _gpu_grad(w, obs, loss.GRAD_VPVS_RHO, 25)
+    ref = [2 * rho * vp * gl, 2 * rho * vs * (gm - 2 * gl), gl * (vp ** 2 - 2 * vs ** 2) + gm * vs ** 2 + grho]
+    ev = [rel_l2(gv[k], ref[k]) for k in range(3)]
+    print("rel-L2 vs oracle chain rule: vp %.2e vs %.2e rho %.2e" % tuple(ev))
+    assert max(ev) < 1e-4, ev
