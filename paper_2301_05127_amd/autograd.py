@@ -56,20 +56,25 @@ class _ElasticSeismograms(torch.autograd.Function):
         torch.cuda.current_stream(a.device).synchronize()
         sim.set_media(vp.contiguous(), r, vs.contiguous())
         sim.forward_ckpt(nsteps, ckpt_every)
-        ctx.sim, ctx.param, ctx.dtypes = sim, param, (a.dtype, b.dtype)
+        # the density's gradient comes with the _RHO form of the parameterisation
+        with_rho = ctx.needs_input_grad[3]
+        ctx.sim, ctx.dtypes, ctx.with_rho = sim, (a.dtype, b.dtype, rho.dtype), with_rho
+        ctx.param = param + 2 if with_rho else param
         return sim.traces_tensor(a.device)
 
     @staticmethod
     def backward(ctx, g):
         grad = ctx.sim.adjoint(g.detach().to(torch.float64).contiguous(), ctx.param)
-        return grad[0].to(ctx.dtypes[0]), grad[1].to(ctx.dtypes[1]), None, None, None, None, None
+        grho = grad[2].to(ctx.dtypes[2]) if ctx.with_rho else None
+        return grad[0].to(ctx.dtypes[0]), grad[1].to(ctx.dtypes[1]), None, grho, None, None, None
 
 
 def elastic_seismograms(sim, a, b, rho, nsteps, ckpt_every=20, param=loss.GRAD_VPVS):
     """Traces [S][nrec][trace_len] (FP64, CUDA) of every shot of the elastic `sim` for the
     model (a, b): (vp, vs) when param is GRAD_VPVS, (lambda, mu) when GRAD_LAME, CUDA
-    tensors of the field shape; rho is held fixed.  Differentiable with respect to a and
-    b through the discrete adjoint."""
+    tensors of the field shape, and the density rho.  Differentiable with respect to a
+    and b, and to rho when it requires a gradient (with (a, b) held fixed), through the
+    discrete adjoint."""
     if param not in (loss.GRAD_VPVS, loss.GRAD_LAME):
         raise ValueError("param must be GRAD_VPVS or GRAD_LAME")
     return _ElasticSeismograms.apply(a, b, sim, rho, int(nsteps), int(ckpt_every), int(param))

@@ -158,8 +158,8 @@ def test_elastic_adjoint_refuses_acoustic_parameters():
     sim.close()
 
 
-@pytest.mark.parametrize("param", [2, 3])
-def test_elastic_autograd_matches_adjoint(orc, param):
+@pytest.mark.parametrize("param,with_rho", [(2, False), (3, False), (2, True), (3, True)])
+def test_elastic_autograd_matches_adjoint(orc, param, with_rho):
     """torch.autograd over the elastic seismograms: J = 1/2 |traces - obs|^2 built in
     torch, its backward (the discrete adjoint fed the trace gradient from torch) equals
     the direct adjoint call with the same residual, for (lambda, mu) and for (vp, vs)."""
@@ -172,6 +172,7 @@ def test_elastic_autograd_matches_adjoint(orc, param):
     S = len(w["shots"])
     dev = "cuda"
     rho = torch.tensor(w["rho"], dtype=torch.float32, device=dev)
+    rho_in = rho.double().clone().requires_grad_(True) if with_rho else rho
     vp = torch.tensor(w["vp"], dtype=torch.float64, device=dev)
     vs = torch.tensor(w["vs"], dtype=torch.float64, device=dev)
     if param == loss.GRAD_VPVS:
@@ -183,7 +184,7 @@ def test_elastic_autograd_matches_adjoint(orc, param):
     b.requires_grad_(True)
     sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=S, trace_len=40)
     sim.setup_workload(w)
-    tr = autograd.elastic_seismograms(sim, a, b, rho, 40, ckpt_every=15, param=param)
+    tr = autograd.elastic_seismograms(sim, a, b, rho_in, 40, ckpt_every=15, param=param)
     J = 0.5 * ((tr - torch.tensor(obs, device=dev)) ** 2).sum()
     J.backward()
     ga, gb = a.grad.cpu().numpy(), b.grad.cpu().numpy()
@@ -199,8 +200,10 @@ def test_elastic_autograd_matches_adjoint(orc, param):
     d.forward_ckpt(40, 15)
     tb = np.stack([d.get_traces(s) for s in range(S)])
     assert np.array_equal(tr.detach().cpu().numpy(), tb)
-    g = d.adjoint(tb - obs, param)
+    g = d.adjoint(tb - obs, param + 2 if with_rho else param)
     assert rel_l2(ga, g[0]) < 1e-12 and rel_l2(gb, g[1]) < 1e-12
+    if with_rho:
+        assert rel_l2(rho_in.grad.cpu().numpy(), g[2]) < 1e-12
     sim.close(); d.close()
 
 
