@@ -193,3 +193,22 @@ def test_elastic_pml_1000_steps(orc):
           err.max(axis=2).T)
     assert err.max() < 1e-5, err.max(axis=(0, 2))
     sim.close()
+
+
+def test_layer_error_paths():
+    """The layer's argument checks and the adjoint's refusal of a run with a layer."""
+    require_gpu()
+    from paper_2301_05127_amd import loss
+    w = _workload(10)
+    sim = _gpu(w)
+    with pytest.raises(loss.LossError):
+        sim.forward_ckpt(10, 5)                # the adjoint is built without the layer
+    for bad in ((21, 1e-6, 1.0, 25.0),         # wider than half the 40-interval y axis
+                (10, 1.5, 1.0, 25.0),          # reflection outside (0, 1)
+                (10, 1e-6, 0.5, 25.0),         # kmax < 1
+                (10, 1e-6, 1.0, 0.0)):         # f0 <= 0
+        with pytest.raises(loss.LossError):
+            sim.set_pml(*bad)
+    sim.set_pml(0)                             # width 0 removes the layer
+    sim.forward_ckpt(10, 5)
+    sim.close()
