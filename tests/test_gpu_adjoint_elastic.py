@@ -245,3 +245,35 @@ def test_density_gradient_matches_oracle_and_fd(orc):
     ev = [rel_l2(gv[k], ref[k]) for k in range(3)]
     print("rel-L2 vs oracle chain rule: vp %.2e vs %.2e rho %.2e" % tuple(ev))
     assert max(ev) < 1e-4, ev
+
+
+@pytest.mark.timeout(400)
+def test_gradient_full_size_few_steps(orc):
+    """257^3 nodes, patches of 64, halo 10 (the two-shot elastic workload's grid), the
+    vertical-force shot with its line of v3 receivers through the source, 4 steps with
+    checkpoints every 2, in the benchmark's launch shape: dJ/dlambda, dJ/dmu and dJ/drho
+    against the FP64 oracle adjoint (dense line operators; about a minute of host time)
+    for J = 1/2 sum d^2."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    nsteps = 4
+    w = inputs.config("cfg3", nsteps=nsteps)
+    w["shots"] = w["shots"][1:]
+    sh = w["shots"][0]
+    sh["sources"][0]["wavelet"] = _f32(inputs.ricker(15.0, 0.004, w["dt"], nsteps + 1, 0.0))   # active at once
+    for k in ("vp", "vs", "rho"):
+        w[k] = _f32(w[k])
+    announce("elastic gradient full size, 1 shot, %d steps" % nsteps)
+    d = orc.run(w["grid"], 1, w["dt"], nsteps, w["vp"], w["rho"], vs=w["vs"], sources=sh["sources"],
+                receivers=sh["receivers"], rec_comp=sh["rec_comp"])[1]
+    gl, gm, gb = orc.elastic_adjoint(w["grid"], w["dt"], nsteps, w["vp"], w["vs"], w["rho"], sh["sources"],
+                                     sh["receivers"], sh["rec_comp"], d, with_b=True)
+    sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=1, trace_len=nsteps)
+    sim.setup_workload(w)
+    sim.set_shape([4, 3208, 3208])
+    sim.forward_ckpt(nsteps, 2)
+    g = sim.adjoint(d.ravel(), loss.GRAD_LAME_RHO)
+    e = [rel_l2(g[0], gl), rel_l2(g[1], gm), rel_l2(g[2], -gb / w["rho"] ** 2)]
+    print("rel-L2 vs oracle: lambda %.2e mu %.2e rho %.2e" % tuple(e))
+    assert np.abs(gl).max() > 0 and max(e) < 1e-4, e
+    sim.close()
