@@ -146,6 +146,17 @@ def gradient_ratio(sim, w, S, nsteps, t_fwd):
     (t_fwd); the residual is the recorded traces themselves (J = sum d^2 / 2)."""
     import torch
     every = int(w.get("ckpt_every", 100 if w["physics"] == 0 else 20))
+    if w["physics"] == 1:
+        # checkpoints (9 fields each) and the recompute's strain store (6 fields per step)
+        # trade against each other; take the interval that needs least device memory
+        nf, slots = 9, 6
+        field_bytes = 4 * S * sim.nodes * 1.02
+        need = lambda e: ((nsteps + e - 1) // e * nf + slots * e) * field_bytes
+        every = min(range(1, nsteps + 1), key=need)
+        free = torch.cuda.mem_get_info()[0]
+        if need(every) > 0.8 * free:
+            return {"steps": nsteps, "skipped": "checkpoints and strain store need %.0f GB, %.0f GB free"
+                    % (need(every) / 1e9, free / 1e9)}
     sim.reset()
     sim.sync()
     t0 = time.perf_counter()
