@@ -192,7 +192,9 @@ loss_status loss_get_traces(loss_sim *sim, int32_t shot, double *dst, int32_t me
 loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *in, float *out,
                        int64_t batch, int32_t mem);
 
-/* Adjoint-state gradient.  loss_forward_ckpt resets, runs nsteps (<= trace_len) steps
+/* Adjoint-state gradient (the discrete transpose of the Strang scheme of Sec. 3.3 applied
+ * to the systems of Sec. 2; the paper states the forward problem only, the gradient is
+ * the standard adjoint-state one).  loss_forward_ckpt resets, runs nsteps (<= trace_len) steps
  * from rest recording traces and keeping the state every ckpt_every steps in device
  * memory.  loss_adjoint then takes the trace residual of J = 1/2 sum residual^2, laid
  * out like the traces of all shots concatenated (residual[shot][rec][t], t < trace_len,
