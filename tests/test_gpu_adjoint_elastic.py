@@ -277,3 +277,30 @@ def test_gradient_full_size_few_steps(orc):
     print("rel-L2 vs oracle: lambda %.2e mu %.2e rho %.2e" % tuple(e))
     assert np.abs(gl).max() > 0 and max(e) < 1e-4, e
     sim.close()
+
+
+@pytest.mark.parametrize("end_mode", [1, 2])
+def test_gradient_other_end_modes(orc, end_mode):
+    """The paper's one-sided end stencil and periodic lines (24^3 intervals, patches of
+    12, halo 5, 30 steps, one explosive shot, checkpoints every 10): Lame gradients
+    against the FP64 oracle adjoint."""
+    require_gpu()
+    from paper_2301_05127_amd import inputs, loss
+    g = inputs.grid(3, (24, 24, 24), (10.0, 10.0, 10.0), (12, 12, 12), 5, end_mode=end_mode)
+    shape = (25, 25, 25)
+    vp = _f32(inputs.gaussian_random_field(shape, 10.0, 40.0, 41, 2800.0, 3300.0))
+    vs = _f32(vp / np.sqrt(3.0))
+    rho = np.full(shape, 2200.0)
+    nsteps = 30
+    src = {"kind": 1, "pos": (110.0, 120.0, 130.0), "spread": 15.0,
+           "wavelet": _f32(inputs.ricker(50.0, 0.02, 1e-3, nsteps + 1, 0.5))}
+    rec = np.array([[ix, 12, 6] for ix in range(0, 25, 3)], dtype=np.int32)
+    w = dict(grid=g, physics=1, dt=1e-3, nsteps=nsteps, vp=vp, vs=vs, rho=rho,
+             shots=[{"sources": [src], "receivers": rec, "rec_comp": 5}])
+    announce("elastic gradient, end mode %d" % end_mode)
+    obs = [orc.run(g, 1, 1e-3, nsteps, vp * 1.05, rho, vs=vs * 0.95, sources=[src], receivers=rec, rec_comp=5)[1]]
+    gpu, _ = _gpu_grad(w, obs, loss.GRAD_LAME, 10)
+    gl, gm = _oracle_grad(orc, w, obs)
+    e = [rel_l2(gpu[0], gl), rel_l2(gpu[1], gm)]
+    print("end mode %d rel-L2 vs oracle: lambda %.2e mu %.2e" % ((end_mode,) + tuple(e)))
+    assert np.abs(gl).max() > 0 and max(e) < 1e-4, e
