@@ -84,6 +84,8 @@ def lib():
             "or_pml_flow": (None, [c_double, c_double, c_double, c_double, c_double, c_double, D, D]),
             "or_run_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, c_int, S, c_int,
                                    I, D, D, D]),
+            "or_acoustic_adjoint_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, D, D, c_int, S, c_int, I,
+                                                D, D]),
             "or_elastic_adjoint": (c_int, [G, c_double, c_int, D, D, D, c_int, S, c_int, I, c_int, D, D, D, D]),
             "or_run_pml_elastic": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, D, c_int, S,
                                            c_int, I, c_int, D, D, D]),
@@ -299,6 +301,24 @@ def acoustic_adjoint(g, dt, nsteps, vp, rho, sources, receivers, residual):
                                    len(keep), src, rec.shape[0], _ip(rec), _dp(res), _dp(grad))
     if rc != 0:
         raise ValueError("oracle or_acoustic_adjoint rejected its arguments (rc=%d)" % rc)
+    return grad
+
+
+def acoustic_adjoint_pml(g, pml, dt, nsteps, vp, rho, sources, receivers, residual):
+    """Gradient dJ/dK at every node of a run with the ADE-PML layer (pml: dict(width, R,
+    kmax, f0, cmax)) for J = 1/2 sum residual^2 of the sigma traces."""
+    shape = field_shape(g)
+    vp, rho = _f64(vp), _f64(rho)
+    src, keep = _sources(list(sources))
+    rec = np.ascontiguousarray(receivers, dtype=np.int32)
+    res = _f64(residual)
+    grad = np.zeros(shape)
+    p = _Pml(int(pml["width"]), float(pml["R"]), float(pml["kmax"]), float(pml["f0"]), float(pml["cmax"]))
+    gs = _grid(g)
+    rc = lib().or_acoustic_adjoint_pml(ctypes.byref(gs), ctypes.byref(p), float(dt), int(nsteps), _dp(vp), _dp(rho),
+                                       len(keep), src, rec.shape[0], _ip(rec), _dp(res), _dp(grad))
+    if rc != 0:
+        raise ValueError("oracle or_acoustic_adjoint_pml rejected its arguments (rc=%d)" % rc)
     return grad
 
 

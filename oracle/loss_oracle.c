@@ -1212,3 +1212,154 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
     for (a = 0; a < 3; ++a) free(Dm[a]);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of the acoustic 2-D scheme with the absorbing layer      */
+/* ------------------------------------------------------------------------ */
+/* Every sub-flow of or_run_pml is linear in (D, psi): with the flow's own outputs for
+ * unit inputs, psi' = Ep psi + Dp D and field += c (Dv D + Pv psi) (c = b or K).  Its
+ * transpose, given the field's bar fb (unchanged) and psi'-bar mb:
+ *   D-bar = c Dv fb + Dp mb,  psi-bar = c Pv fb + Ep mb,  input-bar += D^T (D-bar).
+ * dJ/dK gathers sigma-bar times the stress sub-flow's drive (Dv D + Pv phi, both axes). */
+typedef struct { double *Ep, *Dp, *Dv, *Pv; } flow_lin;
+
+static void flow_lin_build(const or_pml *pml, const or_grid *g, int a, double tau, flow_lin *L)
+{
+    int j, N = g->n[a];
+    double d0 = -3.0 * pml->cmax * log(pml->R) / (2.0 * pml->width * g->h[a]);
+    L->Ep = (double *)malloc(sizeof(double) * 4 * (N + 1));
+    L->Dp = L->Ep + N + 1; L->Dv = L->Dp + N + 1; L->Pv = L->Dv + N + 1;
+    for (j = 0; j <= N; ++j) {
+        double del = pml_delta(j, N, pml->width);
+        double d = d0 * del * del, k = 1.0 + (pml->kmax - 1.0) * del;
+        double al = 3.14159265358979323846 * pml->f0 * (1.0 - del);
+        or_pml_flow(d, k, al, tau, 1.0, 0.0, &L->Dp[j], &L->Dv[j]);
+        or_pml_flow(d, k, al, tau, 0.0, 1.0, &L->Ep[j], &L->Pv[j]);
+    }
+}
+
+int or_acoustic_adjoint_pml(const or_grid *g, const or_pml *pml, double dt, int nsteps,
+                            const double *vp, const double *rho, int nsrc, const or_source *src,
+                            int nrec, const int *rec_idx, const double *res, double *grad_K)
+{
+    long nn[3], tot, i;
+    int n, r, k, half, ax[2] = {0, 2};
+    double *Dm[2];
+    dense_ctx dc[2];
+    flow_lin Lh[2], Lf[2];        /* tau = dt/2 (velocity), dt (stress), per axis x, z */
+    double *F, *K, *b, *t0, *t1, *drive, **W;
+    double *sig, *v1, *v3, *psx, *psz, *phx, *phz;
+    double *sb, *m1, *m3, *bpsx, *bpsz, *bphx, *bphz;
+    if (check_grid(g, OR_ACOUSTIC) || pml->width < 1 || pml->width > g->n[0] / 2 ||
+        pml->width > g->n[2] / 2 || !(pml->R > 0.0 && pml->R < 1.0) || pml->kmax < 1.0 || pml->f0 <= 0.0)
+        return -1;
+    grid_nodes(g, nn);
+    tot = grid_total(g);
+    for (k = 0; k < 2; ++k) {
+        int N = g->n[ax[k]];
+        Dm[k] = (double *)malloc(sizeof(double) * (size_t)(N + 1) * (N + 1));
+        or_line_deriv_matrix(N, g->h[ax[k]], g->M[ax[k]], g->halo, g->end_mode, Dm[k]);
+        dc[k].D = Dm[k]; dc[k].n = N + 1; dc[k].transpose = 0;
+        flow_lin_build(pml, g, ax[k], 0.5 * dt, &Lh[k]);
+        flow_lin_build(pml, g, ax[k], dt, &Lf[k]);
+    }
+    F = (double *)calloc((size_t)tot * 18, sizeof(double));
+    sig = F; v1 = F + tot; v3 = F + 2 * tot; psx = F + 3 * tot; psz = F + 4 * tot; phx = F + 5 * tot;
+    phz = F + 6 * tot; K = F + 7 * tot; b = F + 8 * tot; t0 = F + 9 * tot; t1 = F + 10 * tot;
+    sb = F + 11 * tot; m1 = F + 12 * tot; m3 = F + 13 * tot; bpsx = F + 14 * tot; bpsz = F + 15 * tot;
+    bphx = F + 16 * tot; bphz = F + 17 * tot;
+    drive = (double *)malloc(sizeof(double) * (size_t)tot * nsteps);
+    if (!drive) { free(F); return -2; }
+    for (i = 0; i < tot; ++i) { K[i] = rho[i] * vp[i] * vp[i]; b[i] = 1.0 / rho[i]; }
+    W = (double **)malloc(sizeof(double *) * (nsrc > 0 ? nsrc : 1));
+    for (k = 0; k < nsrc; ++k) {
+        W[k] = (double *)malloc(sizeof(double) * tot);
+        or_source_weights(g, src[k].pos, src[k].spread, W[k]);
+    }
+    /* forward: the sequence of or_run_pml through the linear forms, keeping the stress
+     * sub-flow's drive per step */
+    for (n = 0; n < nsteps; ++n) {
+        for (half = 0; half < 2; ++half) {
+            long fk = half == 0 ? n : n + 1;
+            apply_lines(g, 0, sig, t0, dense_op, &dc[0], 0);
+            apply_lines(g, 2, sig, t1, dense_op, &dc[1], 0);
+            for (i = 0; i < tot; ++i) {
+                int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
+                double px = psx[i], pz = psz[i];
+                psx[i] = Lh[0].Ep[x] * px + Lh[0].Dp[x] * t0[i];
+                v1[i] += b[i] * (Lh[0].Dv[x] * t0[i] + Lh[0].Pv[x] * px);
+                psz[i] = Lh[1].Ep[z] * pz + Lh[1].Dp[z] * t1[i];
+                v3[i] += b[i] * (Lh[1].Dv[z] * t1[i] + Lh[1].Pv[z] * pz);
+            }
+            for (k = 0; k < nsrc; ++k) {
+                double *f = src[k].kind == OR_SRC_FORCE_X ? v1 : src[k].kind == OR_SRC_FORCE_Z ? v3 : NULL;
+                double s = sample(&src[k], fk);
+                if (!f) continue;
+                for (i = 0; i < tot; ++i) f[i] += 0.5 * dt * b[i] * s * W[k][i];
+            }
+            if (half == 1) break;
+            apply_lines(g, 0, v1, t0, dense_op, &dc[0], 0);
+            apply_lines(g, 2, v3, t1, dense_op, &dc[1], 0);
+            for (i = 0; i < tot; ++i) {
+                int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
+                double fx = phx[i], fz = phz[i];
+                double dr = Lf[0].Dv[x] * t0[i] + Lf[0].Pv[x] * fx + Lf[1].Dv[z] * t1[i] + Lf[1].Pv[z] * fz;
+                phx[i] = Lf[0].Ep[x] * fx + Lf[0].Dp[x] * t0[i];
+                phz[i] = Lf[1].Ep[z] * fz + Lf[1].Dp[z] * t1[i];
+                drive[(size_t)n * tot + i] = dr;
+                sig[i] += K[i] * dr;
+            }
+            for (k = 0; k < nsrc; ++k) {
+                double s = sample(&src[k], n);
+                if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                for (i = 0; i < tot; ++i) sig[i] += dt * s * W[k][i];
+            }
+        }
+    }
+    /* reverse sweep */
+    for (i = 0; i < tot; ++i) grad_K[i] = 0.0;
+    dc[0].transpose = dc[1].transpose = 1;
+    for (n = nsteps - 1; n >= 0; --n) {
+        for (r = 0; r < nrec; ++r) {
+            long ix = rec_idx[3 * r], iz = rec_idx[3 * r + 2];
+            sb[iz * nn[0] + ix] += res[(size_t)r * nsteps + n];
+        }
+        for (half = 0; half < 2; ++half) {
+            /* transpose of a velocity half step: (v1, psi_x) from sigma along x, (v3, psi_z)
+             * along z */
+            for (i = 0; i < tot; ++i) {
+                int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
+                double mx = bpsx[i], mz = bpsz[i];
+                t0[i] = b[i] * Lh[0].Dv[x] * m1[i] + Lh[0].Dp[x] * mx;
+                bpsx[i] = b[i] * Lh[0].Pv[x] * m1[i] + Lh[0].Ep[x] * mx;
+                t1[i] = b[i] * Lh[1].Dv[z] * m3[i] + Lh[1].Dp[z] * mz;
+                bpsz[i] = b[i] * Lh[1].Pv[z] * m3[i] + Lh[1].Ep[z] * mz;
+            }
+            apply_lines(g, 0, t0, t0, dense_op, &dc[0], 0);
+            for (i = 0; i < tot; ++i) sb[i] += t0[i];
+            apply_lines(g, 2, t1, t1, dense_op, &dc[1], 0);
+            for (i = 0; i < tot; ++i) sb[i] += t1[i];
+            if (half == 1) break;
+            /* dJ/dK, then the transpose of the stress sub-flow */
+            for (i = 0; i < tot; ++i) {
+                int x = (int)(i % nn[0]), z = (int)(i / nn[0]);
+                double fx = bphx[i], fz = bphz[i];
+                grad_K[i] += sb[i] * drive[(size_t)n * tot + i];
+                t0[i] = K[i] * Lf[0].Dv[x] * sb[i] + Lf[0].Dp[x] * fx;
+                bphx[i] = K[i] * Lf[0].Pv[x] * sb[i] + Lf[0].Ep[x] * fx;
+                t1[i] = K[i] * Lf[1].Dv[z] * sb[i] + Lf[1].Dp[z] * fz;
+                bphz[i] = K[i] * Lf[1].Pv[z] * sb[i] + Lf[1].Ep[z] * fz;
+            }
+            apply_lines(g, 0, t0, t0, dense_op, &dc[0], 0);
+            for (i = 0; i < tot; ++i) m1[i] += t0[i];
+            apply_lines(g, 2, t1, t1, dense_op, &dc[1], 0);
+            for (i = 0; i < tot; ++i) m3[i] += t1[i];
+        }
+    }
+    for (k = 0; k < nsrc; ++k) free(W[k]);
+    free(W);
+    free(drive);
+    free(F);
+    for (k = 0; k < 2; ++k) { free(Dm[k]); free(Lh[k].Ep); free(Lf[k].Ep); }
+    return 0;
+}

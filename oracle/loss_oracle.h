@@ -180,6 +180,14 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
                        int nrec, const int *rec_idx, int rec_comp,
                        const double *res, double *grad_lam, double *grad_mu, double *grad_b);
 
+/* Gradient dJ/dK of one acoustic 2-D shot run with the absorbing layer (or_run_pml's
+ * sequence, memory variables starting at zero), J = 1/2 sum residual^2: the exact
+ * transpose of every sub-flow, each linear in its frozen derivative and memory variable.
+ * grad_K: nodes.  Returns 0 on success. */
+int or_acoustic_adjoint_pml(const or_grid *g, const or_pml *pml, double dt, int nsteps,
+                            const double *vp, const double *rho, int nsrc, const or_source *src,
+                            int nrec, const int *rec_idx, const double *res, double *grad_K);
+
 #ifdef __cplusplus
 }
 #endif

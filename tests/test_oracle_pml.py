@@ -99,3 +99,49 @@ def test_pml_matches_wider_domain():
         # 100: the pulse has not reached the layer; 260: it has crossed it (what is left
         # inside the physical region is mostly reflection from the 12-node layer)
         assert err < (1e-6 if ns == 100 else 2e-3), (ns, err)
+
+
+def _adj_setup():
+    from paper_2301_05127_amd import inputs
+    N, M, n, h, dt, nsteps = 40, 16, 6, 10.0, 1e-3, 120
+    g = inputs.grid(2, (N, 0, N), (h, h, h), (M, M, M), n)
+    shape = (N + 1, N + 1)
+    vp = inputs.gaussian_random_field(shape, h, 60.0, 12, 1800.0, 2600.0)
+    rho = np.full(shape, 1000.0)
+    srcs = [{"kind": 0, "pos": (150.0, 0.0, 120.0), "spread": 20.0,
+             "wavelet": inputs.ricker(40.0, 0.03, dt, nsteps + 1, 0.5)},
+            {"kind": 4, "pos": (250.0, 0.0, 200.0), "spread": 20.0,
+             "wavelet": inputs.ricker(40.0, 0.03, dt, nsteps + 1, 0.0)}]
+    rec = np.array([[ix, 0, 30] for ix in range(0, N + 1, 3)], dtype=np.int32)
+    return g, dt, nsteps, vp, rho, srcs, rec
+
+
+def test_pml_adjoint_without_damping_is_the_plain_adjoint():
+    g, dt, nsteps, vp, rho, srcs, rec = _adj_setup()
+    pml = dict(width=10, R=1.0 - 1e-12, kmax=1.0, f0=40.0, cmax=float(vp.max()))
+    d = oracle.run(g, 0, dt, nsteps, vp, rho, sources=srcs, receivers=rec)[1]
+    gp = oracle.acoustic_adjoint_pml(g, pml, dt, nsteps, vp, rho, srcs, rec, d)
+    gn = oracle.acoustic_adjoint(g, dt, nsteps, vp, rho, srcs, rec, d)
+    assert oracle.rel_l2(gp, gn) < 1e-9
+
+
+def test_pml_adjoint_matches_fd():
+    """dJ/dK with a 10-node layer the waves cross within the run: directional derivative
+    along a smooth K perturbation against central differences of the layer's forward."""
+    from paper_2301_05127_amd import inputs
+    g, dt, nsteps, vp, rho, srcs, rec = _adj_setup()
+    pml = dict(width=10, R=1e-6, kmax=1.0, f0=40.0, cmax=2700.0)
+    obs = oracle.run_pml(g, pml, dt, nsteps, vp * 1.03, rho, sources=srcs, receivers=rec)[1]
+
+    def J(K):
+        d = oracle.run_pml(g, pml, dt, nsteps, np.sqrt(K / rho), rho, sources=srcs, receivers=rec)[1]
+        return 0.5 * np.sum((d - obs) ** 2)
+
+    K = rho * vp ** 2
+    d0 = oracle.run_pml(g, pml, dt, nsteps, vp, rho, sources=srcs, receivers=rec)[1]
+    gK = oracle.acoustic_adjoint_pml(g, pml, dt, nsteps, vp, rho, srcs, rec, d0 - obs)
+    dK = inputs.gaussian_random_field(K.shape, 10.0, 80.0, 3, -1.0, 1.0) * 1e7
+    eps = 1e-2
+    fd = (J(K + eps * dK) - J(K - eps * dK)) / (2 * eps)
+    an = float(np.sum(gK * dK))
+    assert abs(fd - an) <= 1e-7 * abs(an), (fd, an)
