@@ -161,8 +161,9 @@ loss_status loss_reset(loss_sim *sim);
  * media set (call after loss_set_media; setting media again does not update d0).
  * Each sub-flow is solved exactly with its driving derivative frozen.  width = 0
  * removes the layer.  The memory variables (4 or 18 fields of device memory) start at
- * zero (and return to zero on loss_reset); loss_forward_ckpt / loss_adjoint refuse a
- * simulation with a layer (LOSS_EUNSUPPORTED).  Errors: LOSS_EINVAL (width < 0 or
+ * zero (and return to zero on loss_reset); the acoustic adjoint runs through the layer
+ * (checkpoints carry the memory variables), the elastic one refuses it
+ * (LOSS_EUNSUPPORTED).  Errors: LOSS_EINVAL (width < 0 or
  * > n/2 on an axis, reflection outside (0, 1), kmax < 1, f0 <= 0), LOSS_ESTATE (no
  * media yet). */
 loss_status loss_set_pml(loss_sim *sim, int32_t width, double reflection, double kmax, double f0);
@@ -207,8 +208,8 @@ loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *
  * fields per step, nine with the density (6 or 9 x ckpt_every fields of device memory).  The adjoint applies the exact transpose
  * of every discrete operator of the time-stepping scheme; forward states are
  * recomputed from the checkpoints segment by segment.  Afterwards the wavefields hold
- * an intermediate state (call loss_reset).  Errors: LOSS_EUNSUPPORTED (absorbing layer,
- * patches shorter than 2 intervals), LOSS_EINVAL (param not of the physics),
+ * an intermediate state (call loss_reset).  Errors: LOSS_EUNSUPPORTED (elastic with the
+ * absorbing layer, patches shorter than 2 intervals), LOSS_EINVAL (param not of the physics),
  * LOSS_ESTATE (no loss_forward_ckpt). */
 #define LOSS_GRAD_K    0
 #define LOSS_GRAD_VP   1

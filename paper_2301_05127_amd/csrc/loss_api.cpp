@@ -121,6 +121,8 @@ struct loss_sim {
     int divstore_slots = 0;        // slots per step divstore was allocated with
     float *adj[4] = {nullptr, nullptr, nullptr, nullptr};   // lambda, mu1, mu3, Y scratch
     float *adj_el[11] = {};        // elastic: the 9 field bars (field order), Y scratch, operand
+    float *adj_pml[5] = {};        // acoustic with the layer: the 4 memory-variable bars, operand
+    int ck_fields = 0;             // fields per checkpoint (the state, and the layer's variables)
     float **d_adjtab = nullptr;    // device copy of adj_el[0..8]
     double *grad_pad = nullptr, *grad_dense = nullptr, *res_dev = nullptr;
     float *d_vp = nullptr, *d_rho = nullptr;   // dense copies of the media for the gradient map
@@ -1136,7 +1138,7 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
         const int64_t n0 = c * s->ck_every, nc = std::min(s->ck_every, s->ck_steps - n0);
         // restore the fused state at step n0 and recompute the segment, keeping the strains
         for (int k = 0; k < s->nf; ++k)
-            HIPCHK(hipMemcpyAsync(s->f[k], s->ckpt + (c * s->nf + k) * fe, sizeof(float) * fe,
+            HIPCHK(hipMemcpyAsync(s->f[k], s->ckpt + (c * s->ck_fields + k) * fe, sizeof(float) * fe,
                                   hipMemcpyDeviceToDevice, s->st));
         HIPCHK(launch_set_step(s->d_step, n0, s->st));
         s->fused = true;
@@ -1679,7 +1681,8 @@ loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
 {
     if (!s) return fail(LOSS_EINVAL, "null argument");
     if (nsteps < 1 || ckpt_every < 1) return fail(LOSS_EINVAL, "nsteps and ckpt_every must be >= 1");
-    if (s->pml_mem) return fail(LOSS_EUNSUPPORTED, "the adjoint is built without the absorbing layer");
+    if (s->pml_mem && s->d.physics != LOSS_ACOUSTIC)
+        return fail(LOSS_EUNSUPPORTED, "the elastic adjoint is built without the absorbing layer");
     for (int a = 0; a < 3; ++a)
         if (!(a == 1 && s->d.ndim == 2) && s->d.patch[a] < 2)
             return fail(LOSS_EUNSUPPORTED, "the adjoint needs patches of at least 2 intervals");
@@ -1690,15 +1693,20 @@ loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
     if ((r = fuse(s))) return r;
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
     const int64_t fe = field_elems(s);
-    if (s->ckpt && s->ck_nseg != nseg) { s->release(s->ckpt); s->ckpt = nullptr; }
-    if (!s->ckpt && (r = s->alloc(&s->ckpt, (size_t)(nseg * s->nf * fe)))) return r;
+    const int ckf = s->nf + (s->pml_mem ? s->npml : 0);
+    if (s->ckpt && (s->ck_nseg != nseg || s->ck_fields != ckf)) { s->release(s->ckpt); s->ckpt = nullptr; }
+    if (!s->ckpt && (r = s->alloc(&s->ckpt, (size_t)(nseg * ckf * fe)))) return r;
+    s->ck_fields = ckf;
     if (s->divstore && s->ck_every != ckpt_every) { s->release(s->divstore); s->divstore = nullptr; }
     s->ck_nseg = nseg;
     s->ck_every = ckpt_every;
     s->ck_steps = 0;
     for (int64_t c = 0; c < nseg; ++c) {
         for (int k = 0; k < s->nf; ++k)
-            HIPCHK(hipMemcpyAsync(s->ckpt + (c * s->nf + k) * fe, s->f[k], sizeof(float) * fe,
+            HIPCHK(hipMemcpyAsync(s->ckpt + (c * ckf + k) * fe, s->f[k], sizeof(float) * fe,
+                                  hipMemcpyDeviceToDevice, s->st));
+        if (ckf > s->nf)   // the layer's memory variables go with the state
+            HIPCHK(hipMemcpyAsync(s->ckpt + (c * ckf + s->nf) * fe, s->pml_mem, sizeof(float) * (ckf - s->nf) * fe,
                                   hipMemcpyDeviceToDevice, s->st));
         const int64_t nc = std::min(ckpt_every, nsteps - c * ckpt_every);
         if ((r = run_steps(s, nc, nullptr, 0))) return r;
@@ -1730,16 +1738,54 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
     HIPCHK(hipMemsetAsync(s->grad_pad, 0, sizeof(double) * ss, s->st));
     float *lam = s->adj[0], *mu1 = s->adj[1], *mu3 = s->adj[2], *Y = s->adj[3];
     const float *K = s->med[0], *b = s->med[1];
+    const bool layer = s->pml_mem != nullptr;
+    if (layer) {
+        for (int k = 0; k < 5; ++k)
+            if (!s->adj_pml[k] && (r = s->alloc(&s->adj_pml[k], fe))) return r;
+        for (int k = 0; k < 4; ++k)
+            if (launch_fill(s->adj_pml[k], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    }
     bool lam_x_done = false;   // the coming step's lambda x pass already applied
     for (int64_t c = s->ck_nseg - 1; c >= 0; --c) {
         const int64_t n0 = c * s->ck_every, nc = std::min(s->ck_every, s->ck_steps - n0);
         // restore the fused state at step n0 and recompute the segment, keeping div u
         for (int k = 0; k < 3; ++k)
-            HIPCHK(hipMemcpyAsync(s->f[k], s->ckpt + (c * 3 + k) * fe, sizeof(float) * fe,
+            HIPCHK(hipMemcpyAsync(s->f[k], s->ckpt + (c * s->ck_fields + k) * fe, sizeof(float) * fe,
+                                  hipMemcpyDeviceToDevice, s->st));
+        if (layer)
+            HIPCHK(hipMemcpyAsync(s->pml_mem, s->ckpt + (c * s->ck_fields + 3) * fe, sizeof(float) * 4 * fe,
                                   hipMemcpyDeviceToDevice, s->st));
         HIPCHK(launch_set_step(s->d_step, n0, s->st));
         s->fused = true;
         if ((r = steps_eager(s, nc, s->divstore, ss))) return r;
+        if (layer) {
+            // every pass transposed through its layer operand (memory-variable bars 0 psi_x,
+            // 1 psi_z of the velocity passes, 2 phi_x, 3 phi_z of the stress passes), then
+            // the transposed derivative; the same order as the plain loop below
+            float *W = s->adj_pml[4];
+            auto pass_t = [&](int axis, const float *fbar, const float *coef, int mv, float *target) -> loss_status {
+                if ((r = timed_begin(s))) return r;
+                const hipError_t e = launch_pml_adj_operand(W, fbar, coef, -1.f, s->adj_pml[mv], s->pml_tab[axis], axis,
+                                                            s->pml_w, (int)s->d.n[axis], s->nx, s->ny, s->pitch, ss,
+                                                            (int)S, s->st);
+                if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+                if ((r = timed_end(s, KC_GRAD))) return r;
+                return adj_deriv(s, axis, W, nullptr, target, 1.f, EPI_AXPY, Y, (int)S);
+            };
+            for (int64_t k = nc - 1; k >= 0; --k) {
+                const int64_t n = n0 + k;
+                if ((r = pass_t(0, mu1, b, 0, lam))) return r;
+                if ((r = pass_t(2, mu3, b, 1, lam))) return r;
+                if ((r = timed_begin(s))) return r;
+                hipError_t e = launch_residual_inject(s->d_rec_str, s->nrec_str, lam, ss, s->res_dev, n, s->st);
+                if (e == hipSuccess) e = launch_grad_accum(s->grad_pad, lam, s->divstore + k * fe, -dt, (int)S, ss, ss, s->st);
+                if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+                if ((r = timed_end(s, KC_GRAD))) return r;
+                if ((r = pass_t(2, lam, K, 3, mu3))) return r;
+                if ((r = pass_t(0, lam, K, 2, mu1))) return r;
+            }
+            continue;
+        }
         // reverse sweep over the segment.  Per step: lambda^{n+1} += -dt Dx^T(b mu1) (done
         // by the previous step's paired x pass, except at the first reverse step), the
         // residual, -dt Dz^T(b mu3); dJ/dK += -dt lambda^{n+1} div u^n; then

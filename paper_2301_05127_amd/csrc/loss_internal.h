@@ -190,6 +190,11 @@ struct RecDev {
     int64_t trace_off;                // offset of sample 0 in the trace pool
 };
 
+// adjoint through the absorbing layer (adjoint_layer.hip)
+hipError_t launch_pml_adj_operand(float *w, const float *f, const float *coef, float alpha, float *m,
+                                  const float4 *tab, int axis, int pml_w, int N, int nx, int ny, int64_t pitch,
+                                  int64_t per_shot, int S, hipStream_t st);
+
 // elastic adjoint (adjoint_elastic.hip)
 hipError_t launch_el_normal_operand(float *w, const float *s11, const float *s22, const float *s33,
                                     const float *l2m, const float *lam, int k, int nx, int64_t pitch,
