@@ -181,8 +181,8 @@ def main():
         print("bench.py: the library runs on one GPU; --gpus %d is not supported (shots, then "
               "blocks of patches, would be the units to shard across GPUs)" % a.gpus, file=sys.stderr)
         sys.exit(2)
-    if a.grad and a.pml:
-        print("bench.py: the adjoint is built without the absorbing layer; drop --pml or --grad",
+    if a.grad and a.pml and a.workload in ("cfg3", "cfg4"):
+        print("bench.py: the elastic adjoint is built without the absorbing layer; drop --pml or --grad",
               file=sys.stderr)
         sys.exit(2)
     import torch
