@@ -62,39 +62,74 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
-        D = ctypes.POINTER(ctypes.c_double)
-        I = ctypes.POINTER(ctypes.c_int)
-        G = ctypes.POINTER(_Grid)
-        S = ctypes.POINTER(_Source)
-        c_int, c_double = ctypes.c_int, ctypes.c_double
-        sig = {
-            "or_global_spline": (None, [c_int, c_double, D, D]),
-            "or_global_inverse_column": (None, [c_int, c_double, c_int, D]),
-            "or_patch_lu": (None, [c_int, D, D]),
-            "or_pmbc_row": (c_int, [c_int, c_double, c_int, c_int, c_int, c_int, D, I]),
-            "or_line_deriv": (None, [c_int, c_double, c_int, c_int, c_int, D, D, D]),
-            "or_line_deriv_matrix": (None, [c_int, c_double, c_int, c_int, c_int, D]),
-            "or_field_deriv": (None, [G, c_int, c_int, D, D]),
-            "or_source_weights": (None, [G, D, c_double, D]),
-            "or_run_from": (c_int, [G, c_int, c_double, c_int, c_int, D, D, D, c_int, S, c_int, I,
-                                    c_int, D, D, D]),
-            "or_acoustic_adjoint": (c_int, [G, c_double, c_int, D, D, c_int, S, c_int, I, D, D]),
-            "or_num_fields": (c_int, [c_int]),
-            "or_pml_flow": (None, [c_double, c_double, c_double, c_double, c_double, c_double, D, D]),
-            "or_run_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, c_int, S, c_int,
-                                   I, D, D, D]),
-            "or_acoustic_adjoint_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, D, D, c_int, S, c_int, I,
-                                                D, D]),
-            "or_elastic_adjoint": (c_int, [G, c_double, c_int, D, D, D, c_int, S, c_int, I, c_int, D, D, D, D]),
-            "or_run_pml_elastic": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, D, c_int, S,
-                                           c_int, I, c_int, D, D, D]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(_lib, name)
-            f.restype = res
-            f.argtypes = args
+        _lib = _load(build())
     return _lib
+
+
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile another text of ``loss_oracle.c`` (the pin tests plant a mistake in a copy
+    to show that a pin catches it) into ``out_path``."""
+    d = os.path.dirname(out_path)
+    src = os.path.join(d, "loss_oracle_variant.c")
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-I", _HERE, src,
+                           "-o", out_path, "-lm"])
+    return out_path
+
+
+class use_library:
+    """Context manager: route every oracle call through the library at ``path``."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.prev = _lib
+        _lib = _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.prev
+
+
+def _load(path):
+    """Open an oracle library and declare the signatures of its entry points."""
+    L = ctypes.CDLL(path)
+    D = ctypes.POINTER(ctypes.c_double)
+    I = ctypes.POINTER(ctypes.c_int)
+    G = ctypes.POINTER(_Grid)
+    S = ctypes.POINTER(_Source)
+    c_int, c_double = ctypes.c_int, ctypes.c_double
+    sig = {
+        "or_global_spline": (None, [c_int, c_double, D, D]),
+        "or_global_inverse_column": (None, [c_int, c_double, c_int, D]),
+        "or_patch_lu": (None, [c_int, D, D]),
+        "or_pmbc_row": (c_int, [c_int, c_double, c_int, c_int, c_int, c_int, D, I]),
+        "or_line_deriv": (None, [c_int, c_double, c_int, c_int, c_int, D, D, D]),
+        "or_line_deriv_matrix": (None, [c_int, c_double, c_int, c_int, c_int, D]),
+        "or_field_deriv": (None, [G, c_int, c_int, D, D]),
+        "or_source_weights": (None, [G, D, c_double, D]),
+        "or_run_from": (c_int, [G, c_int, c_double, c_int, c_int, D, D, D, c_int, S, c_int, I,
+                                c_int, D, D, D]),
+        "or_acoustic_adjoint": (c_int, [G, c_double, c_int, D, D, c_int, S, c_int, I, D, D]),
+        "or_num_fields": (c_int, [c_int]),
+        "or_pml_flow": (None, [c_double, c_double, c_double, c_double, c_double, c_double, D, D]),
+        "or_run_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, c_int, S, c_int,
+                               I, D, D, D]),
+        "or_acoustic_adjoint_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, D, D, c_int, S, c_int, I,
+                                            D, D]),
+        "or_elastic_adjoint": (c_int, [G, c_double, c_int, D, D, D, c_int, S, c_int, I, c_int, D, D, D, D]),
+        "or_run_pml_elastic": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, D, c_int, S,
+                                       c_int, I, c_int, D, D, D]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 def _dp(a):
