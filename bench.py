@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the LOSS hot path on one MI355X.
 
-Workload (default cfg2): 2-D acoustic, 2048x2048 intervals (2049^2 nodes), h = 10 m,
-dt = 1 ms, 8x8 patches of 256 intervals, PMBC halo 12, velocity = smooth Gaussian
-random field in [1500, 4500] m/s (seed 2301, correlation 200 m), 20 Hz Ricker at the
-centre, receivers on every node of row z = 20 m; synthetic inputs.  Other workloads
-(--workload): cfg1 (129^2 acoustic), cfg3 (257^3 elastic, two shots in one batch),
-cfg4 (513^3 layered elastic), cfg5 (1025^2 acoustic, 64 shots; --grad also times the
-checkpointed forward and the adjoint and reports the gradient/forward ratio).
+Workload (default cfg4, the largest single-GPU configuration): 3-D elastic
+velocity-stress, 512^3 intervals (513^3 nodes), h = 10 m, dt = 0.8 ms, 8^3 patches of
+64 intervals, PMBC halo 12, four flat layers Vp 1800..5000 m/s with a +-5 % Gaussian
+perturbation (seed 5127), Vs = Vp/sqrt(3), Gardner density, explosive 15 Hz Ricker,
+receivers along a vertical line; synthetic inputs.  Other workloads (--workload): cfg1
+(129^2 acoustic), cfg2 (2049^2 acoustic, smooth random velocity), cfg3 (257^3 elastic,
+two shots in one batch), cfg5 (1025^2 acoustic, 64 shots).  --grad also times the
+checkpointed forward and the adjoint of the workload itself.
+
+Extra keys of the default run (--no-extras drops them): "gradient", the
+gradient/forward time ratio of the batched acoustic adjoint (1025^2, 64 shots, 200
+steps, checkpoints every 100), and "acoustic_2049", the 2049^2 acoustic rate.
 
 One step = one Strang step of the whole hot path: PMBC junction slopes, patch
 tridiagonal solves and derivative epilogues along every axis for the stress and the
 velocity sub-flows, source injection, receiver recording.  Inputs are resident in
-device memory before the timed region; the timed region replays the step graph.
+device memory before the timed region; the timed region replays the step graphs
+(captured during the warm-up for every power-of-two step count up to 32).
 
 Prints one JSON line.  value = Mcell-updates/s (nodes x shots x steps / time).
 """
@@ -61,7 +67,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's length)")
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--workload", default="cfg2", choices=sorted(DEFAULT_STEPS))
+    p.add_argument("--workload", default="cfg4", choices=sorted(DEFAULT_STEPS))
     p.add_argument("--shots", type=int, default=None, help="shots per batch (default: the workload's)")
     p.add_argument("--timing-steps", type=int, default=200)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -73,6 +79,9 @@ def parse():
                    help="launch shape per axis 'x,y,z' (loss_set_shape encoding); skips autotuning")
     p.add_argument("--pml", type=int, default=0,
                    help="absorbing layer of this many nodes on every side (R 1e-6, kmax 1, f0 of the source)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the gradient/forward ratio and the 2049^2 acoustic rate of the default run")
+    p.add_argument("--grad-steps", type=int, default=200, help="steps of the extra gradient/forward timing")
     p.add_argument("--copy-probe", action="store_true",
                    help="accepted for compatibility: the 1 GiB copy probe always runs")
     return p.parse_args()
@@ -173,6 +182,56 @@ def gradient_ratio(sim, w, S, nsteps, t_fwd):
             "forward_ckpt_s": round(t_ck, 4), "adjoint_s": round(t_adj, 4),
             "ratio": round((t_ck + t_adj) / t_fwd, 3), "finite": bool(np.isfinite(g).all()),
             "note": "adjoint time includes the host residual upload and gradient download"}
+
+
+def timed_rate(name, steps, warmup):
+    """Mcell-updates/s of one more workload (graphs replayed, autotuned launch shape)."""
+    import torch
+    from paper_2301_05127_amd import inputs, loss
+    w = inputs.config(name, nsteps=steps + warmup)
+    S = len(w["shots"])
+    sim = loss.Simulation(w["grid"], w["physics"], w["dt"], nshots=S, trace_len=steps + warmup)
+    sim.setup_workload(w)
+    cw = sim.autotune(3)
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.close()
+    return {"workload": workload_desc(w, S), "value": round(sim.nodes * S * steps / el / 1e6, 2),
+            "unit": "Mcell-updates/s", "steps": steps, "ms_per_step": round(1e3 * el / steps, 5),
+            "columns_per_wave": cw,
+            "hbm_effective_frac": round(sim.nodes * S * steps / el * STEP_BYTES[w["physics"]] / 1e9
+                                        / HBM_PEAK_GBS, 4)}
+
+
+def extra_gradient(steps, warmup=10):
+    """Gradient/forward time ratio of the batched acoustic adjoint (1025^2 nodes, 64 shots,
+    checkpoints every 100 steps): plain forward, then checkpointed forward + adjoint."""
+    import torch
+    from paper_2301_05127_amd import inputs, loss
+    w = inputs.config("cfg5", nsteps=steps)
+    S = len(w["shots"])
+    sim = loss.Simulation(w["grid"], w["physics"], w["dt"], nshots=S, trace_len=steps)
+    sim.setup_workload(w)
+    sim.autotune(3)
+    sim.step(warmup)
+    sim.reset()
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    out = gradient_ratio(sim, w, S, steps, t_fwd)
+    out["workload"] = workload_desc(w, S)
+    sim.close()
+    return out
 
 
 def main():
@@ -290,10 +349,15 @@ def main():
     }
     if grad:
         res["gradient"] = grad
+    sim.close()
+    del sim
+    if not a.no_extras and a.workload == "cfg4" and not a.pml:
+        if "gradient" not in res:
+            res["gradient"] = extra_gradient(a.grad_steps)
+        res["acoustic_2049"] = timed_rate("cfg2", 200, 20)
     if not a.no_cpu_baseline:
         cs = a.cpu_sample_steps or CPU_SAMPLE_STEPS[a.workload]
         res["cpu_baseline"] = cpu_baseline(inputs.config(a.workload, nsteps=cs), cs, a.pml)
-    sim.close()
     print(json.dumps(res), flush=True)
 
 

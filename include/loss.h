@@ -24,7 +24,8 @@
  * Spatial derivatives (Sec. 3.1-3.2): patched cubic B-splines with the perfectly
  * matched boundary condition at patch junctions; time (Sec. 3.3): Strang splitting
  * of the velocity sub-flow (A) and the stress sub-flow (B), A(dt/2) B(dt) A(dt/2).
- * No absorbing layer: the outer ends use the end mode below.
+ * Outer ends: the end rows below (LOSS_END_*), optionally with the absorbing layer of
+ * Sec. 3.3 on the outermost nodes (loss_set_pml).
  */
 #ifndef LOSS_H
 #define LOSS_H
@@ -92,6 +93,13 @@ typedef int32_t loss_status;
                                   stress pass in separate kernels (by default one kernel
                                   runs both when a whole x line fits one workgroup and
                                   there are no body forces or velocity receivers) */
+#define LOSS_FLAG_LINE_PASSES 4 /* elastic: one kernel per derivative along one axis (18 per
+                                  step) instead of the plane schedule (per sub-flow: the z
+                                  derivatives of its inputs, then one pass that solves the x
+                                  and y lines of each patch tile of a plane from LDS and
+                                  updates every output once); the plane schedule applies to
+                                  x and y patches of at most 64 intervals without the
+                                  absorbing layer */
 
 typedef struct {
     int32_t physics;      /* LOSS_ACOUSTIC (ndim 2) or LOSS_ELASTIC (ndim 3) */
@@ -135,7 +143,10 @@ loss_status loss_set_media(loss_sim *sim, const float *vp, const float *vs, cons
 loss_status loss_add_source(loss_sim *sim, int32_t shot, const double pos[3], int32_t kind,
                             const float *wavelet, int64_t nt, double spread_m);
 
-/* Add receivers to `shot`: node_idx (host) = nrec triples (ix, iy, iz).  After every
+/* Receivers (Sec. 4.3: the synthetic traces are the time series of a field sampled at
+ * fixed nodes, there v_3 along a vertical line; Sec. 2 lists the wavefields and traces as
+ * the outputs of the forward problem).
+ * Add receivers to `shot`: node_idx (host) = nrec triples (ix, iy, iz).  After every
  * step n (counted from the last reset) sample n of each trace receives the field
  * `component` at t_{n+1} (acoustic: LOSS_F_SIGMA only; elastic: any field id),
  * accumulated in float64.  A velocity at t_{n+1} is the mean of the half-step-ahead
@@ -146,7 +157,8 @@ loss_status loss_add_source(loss_sim *sim, int32_t shot, const double pos[3], in
 loss_status loss_add_receivers(loss_sim *sim, int32_t shot, int64_t nrec, const int32_t *node_idx,
                                int32_t component);
 
-/* Zero every wavefield, trace and the step counter (media and sources are kept). */
+/* Zero every wavefield, trace, memory variable, the step counter and the non-finite
+ * sentinel (media and sources are kept). */
 loss_status loss_reset(loss_sim *sim);
 
 /* Absorbing layer (paper Sec. 3.3: ADE-PML with the exponential operator splitting):
@@ -168,20 +180,28 @@ loss_status loss_reset(loss_sim *sim);
  * media yet). */
 loss_status loss_set_pml(loss_sim *sim, int32_t width, double reflection, double kmax, double f0);
 
-/* Advance all shots by nsteps Strang steps, asynchronously on the sim stream.
+/* Advance all shots by nsteps Strang steps (Sec. 3.3), asynchronously on the sim stream.
  * Per step: stress sub-flow B(dt) then the velocity sub-flow, the two velocity half
  * steps of consecutive steps fused into one (the state holds the velocity half a
- * step ahead; loss_get_field returns it at the integer time). */
+ * step ahead; loss_get_field returns it at the integer time).  Steps are replayed from
+ * hipGraphs of 1, 2, 4, ..., 32 steps captured on the first call after a change of
+ * configuration (LOSS_FLAG_NO_GRAPH: eager launches).
+ * Non-finite sentinel: every 32 steps and at the end of each call, field 0 of every
+ * shot (sigma; v1 when elastic) is checked for NaN or infinity on the device; the
+ * result reaches the host without a wait, and once a check has seen one, loss_step and
+ * loss_sync return LOSS_EUNSTABLE until loss_reset. */
 loss_status loss_step(loss_sim *sim, int64_t nsteps);
 
-/* Copy one field of one shot at the current integer time into dst (nodes floats). */
+/* Wavefields (the outputs of the forward problem, Sec. 2).
+ * Copy one field of one shot at the current integer time into dst (nodes floats). */
 loss_status loss_get_field(loss_sim *sim, int32_t shot, int32_t field, float *dst, int32_t mem);
 
 /* Overwrite one field of one shot at the current integer time. */
 loss_status loss_set_field(loss_sim *sim, int32_t shot, int32_t field, const float *src,
                            int32_t mem);
 
-/* Receiver traces of one shot: dst = nrec x trace_len doubles, receiver-major. */
+/* Receiver traces of one shot (Sec. 4.3): dst = nrec x trace_len doubles,
+ * receiver-major; sample n holds the field at t_{n+1}. */
 loss_status loss_get_traces(loss_sim *sim, int32_t shot, double *dst, int32_t mem);
 
 /* Hot-path primitive: the patched spline derivative of order 1 (eq.
@@ -197,8 +217,10 @@ loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *
  * to the systems of Sec. 2; the paper states the forward problem only, the gradient is
  * the standard adjoint-state one).  loss_forward_ckpt resets, runs nsteps (<= trace_len) steps
  * from rest recording traces and keeping the state every ckpt_every steps in device
- * memory.  loss_adjoint then takes the trace residual of J = 1/2 sum residual^2, laid
- * out like the traces of all shots concatenated (residual[shot][rec][t], t < trace_len,
+ * memory (3 fields per checkpoint acoustic, 9 elastic; with the absorbing layer the
+ * acoustic checkpoint also carries its 4 memory variables, and the adjoint allocates 5
+ * more fields for their bars and its operand).  loss_adjoint then takes the trace
+ * residual of J = 1/2 sum residual^2, laid out like the traces of all shots concatenated (residual[shot][rec][t], t < trace_len,
  * float64; samples t >= nsteps are ignored) and returns dJ/dparam summed over shots
  * (float64).  Acoustic: param = LOSS_GRAD_K (bulk modulus K) or LOSS_GRAD_VP (c with rho
  * fixed: 2 rho c dJ/dK), grad = nodes values.  Elastic: param = LOSS_GRAD_LAME
@@ -210,7 +232,8 @@ loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *
  * recomputed from the checkpoints segment by segment.  Afterwards the wavefields hold
  * an intermediate state (call loss_reset).  Errors: LOSS_EUNSUPPORTED (elastic with the
  * absorbing layer, patches shorter than 2 intervals), LOSS_EINVAL (param not of the physics),
- * LOSS_ESTATE (no loss_forward_ckpt). */
+ * LOSS_ESTATE (no loss_forward_ckpt since the last loss_set_media or loss_set_pml: the
+ * checkpoints must belong to the media and layer the adjoint runs with). */
 #define LOSS_GRAD_K    0
 #define LOSS_GRAD_VP   1
 #define LOSS_GRAD_LAME 2
@@ -224,21 +247,26 @@ loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, d
 /* Autotune the launch shape of the line kernels: along x the nodes per lane (4, 8 or
  * 16); along y and z the columns per wave (16, 32 or 64 x-columns; the rest of the
  * wave's lanes take further chunks of the same lines) and the nodes per lane (8 or
- * 16); each candidate timed over `trial_steps` steps, the fastest kept.  A shape
- * changes only how the carries of the scan are grouped (rounding-level
- * differences).  Wavefields, traces and the step counter are restored afterwards. */
+ * 16); each candidate timed over `trial_steps` steps, the fastest kept.  Elastic grids
+ * that admit the plane schedule (LOSS_FLAG_LINE_PASSES) have it timed against the line
+ * passes and the faster one kept.  A shape or schedule changes only how the carries of
+ * the scan are grouped and the order in which derivative terms are summed
+ * (rounding-level differences).  Wavefields, traces and the step counter are restored
+ * afterwards. */
 loss_status loss_autotune(loss_sim *sim, int32_t trial_steps);
 
 /* The launch shape in use along `axis`: nodes per lane for x; for y and z,
- * 100 * columns per wave + nodes per lane (0 = automatic choice). */
+ * 100 * columns per wave + nodes per lane (0 = automatic choice); axis 3: the elastic
+ * schedule in use (0 plane passes, 1 line passes). */
 loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
 
 /* Set the launch shape along `axis` in the encoding of loss_autotune_choice
- * (x: 4, 8 or 16; y/z: 100 * {8, 16, 32, 64} + {8, 16}; 0 = automatic).  LOSS_EINVAL
- * for any other value. */
+ * (x: 4, 8 or 16; y/z: 100 * {8, 16, 32, 64} + {8, 16}; 0 = automatic; axis 3: 0 plane
+ * schedule where it applies, 1 line passes).  LOSS_EINVAL for any other value. */
 loss_status loss_set_shape(loss_sim *sim, int32_t axis, int32_t shape);
 
-/* Wait for all work queued on the sim stream. */
+/* Wait for all work queued on the sim stream; LOSS_EUNSTABLE if the non-finite sentinel
+ * (see loss_step) has fired. */
 loss_status loss_sync(loss_sim *sim);
 
 /* Per-kernel timing (for roofline accounting): when on, loss_step launches every

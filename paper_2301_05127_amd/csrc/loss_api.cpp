@@ -47,12 +47,14 @@ struct RecHost {
 // Kernel classes reported by loss_kernel_timing.
 enum KClass {
     KC_STRESS_X, KC_STRESS_Y, KC_STRESS_Z, KC_VEL_X, KC_VEL_Y, KC_VEL_Z, KC_SOURCE, KC_RECEIVER,
-    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_VEL_STRESS_X, KC_ADJ_X, KC_ADJ_XX, KC_COUNT
+    KC_ADVANCE, KC_ADJ_SOLVE, KC_ADJ_GATHER, KC_GRAD, KC_VEL_STRESS_X, KC_ADJ_X, KC_ADJ_XX, KC_STRESS_XY,
+    KC_VEL_XY, KC_COUNT
 };
 const char *kKClassName[KC_COUNT] = {
     "stress_line_x", "stress_line_y", "stress_line_z", "velocity_line_x", "velocity_line_y",
     "velocity_line_z", "source_inject", "receiver_record", "step_advance", "adjoint_line_solve",
-    "adjoint_gather", "gradient_accumulate", "velocity_stress_x", "adjoint_line_x", "adjoint_line_x_pair"};
+    "adjoint_gather", "gradient_accumulate", "velocity_stress_x", "adjoint_line_x", "adjoint_line_x_pair",
+    "stress_plane_xy", "velocity_plane_xy"};
 
 }  // namespace
 
@@ -99,9 +101,15 @@ struct loss_sim {
     // step counter
     int64_t *d_step = nullptr;
     int64_t step = 0;
-    // graphs
-    hipGraphExec_t gexec = nullptr;
-    int gsteps = 0;
+    // non-finite sentinel: a device flag set when the checked field holds a NaN or an
+    // infinity, copied in stream order into pinned host memory that the host reads
+    // without waiting
+    int *d_bad = nullptr;
+    int *h_bad = nullptr;
+    // graphs: gexec[k] replays 2^k steps (k = 0 .. kGraphLevels - 1), all built together
+    static constexpr int kGraphLevels = 6;
+    hipGraphExec_t gexec[kGraphLevels] = {};
+    bool graphs_built = false;
     // timing
     bool timing = false;
     double kms[KC_COUNT] = {0};
@@ -112,6 +120,8 @@ struct loss_sim {
     int4 *d_rcol = nullptr;
     int *d_rrow = nullptr;
     int64_t *d_rtoff = nullptr;
+    // elastic schedule: 0 plane passes where they apply, 1 line passes (autotune's choice)
+    int elastic_schedule = 0;
     // adjoint
     float *ckpt = nullptr;         // [nseg][nf fields][S][shot_stride] fused states
     int64_t ck_every = 0, ck_steps = 0, ck_nseg = 0;
@@ -345,6 +355,91 @@ loss_status record(loss_sim *s, const RecDev *rec0, int nrec0, float w0, int acc
     return timed_end(s, KC_RECEIVER);
 }
 
+// ---- elastic plane schedule ------------------------------------------------------
+// Per stage: three z passes store the z derivatives T of the stage's inputs, then the
+// plane kernel adds the x and y derivatives from LDS tiles and updates every output
+// once (see plane_xy.hip).  Used for elastic runs without the absorbing layer whose x
+// and y patches are at most kPlaneMaxM long, unless the line-pass schedule is asked for.
+bool plane_ok(const loss_sim *s)
+{
+    return s->d.physics == LOSS_ELASTIC && !s->pml_mem && !(s->d.flags & LOSS_FLAG_LINE_PASSES) &&
+           s->elastic_schedule != 1 && s->d.patch[0] <= kPlaneMaxM && s->d.patch[1] <= kPlaneMaxM &&
+           s->d.halo <= kPlaneMaxHalo;
+}
+
+PlaneArgs plane_args(const loss_sim *s)
+{
+    PlaneArgs p{};
+    p.S = s->S;
+    p.nx = s->nx; p.ny = s->ny; p.nz = s->nz;
+    p.pitch = s->pitch; p.plane = s->plane; p.shot_stride = s->shot_stride;
+    p.ax = s->axd[0];
+    p.ay = s->axd[1];
+    p.lam = s->med[0]; p.mu = s->med[1]; p.l2m = s->med[2]; p.b = s->med[3];
+    for (int i = 0; i < 3; ++i) p.T[i] = s->tmp[i];
+    return p;
+}
+
+loss_status run_plane(loss_sim *s, int kc, int mode, const PlaneArgs &p)
+{
+    loss_status r = timed_begin(s);
+    if (r) return r;
+    const hipError_t e = launch_plane_xy(mode, p, s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("plane kernel launch: ") + hipGetErrorString(e));
+    return timed_end(s, kc);
+}
+
+// z derivatives of three fields into tmp[0..2] (the first kernel of a step when pending)
+loss_status z_stores(loss_sim *s, int kc, const float *const *in)
+{
+    for (int i = 0; i < 3; ++i) {
+        LineArgs z = base_args(s, 2);
+        z.in = in[i];
+        z.out[0] = s->tmp[i];
+        loss_status r = run_line(s, kc, 2, SOLVE_D1, EPI_STORE, z);
+        if (r) return r;
+    }
+    return LOSS_OK;
+}
+
+// stress sub-flow B(dt): T_i = d3 v_i, then the plane pass over the six stresses
+loss_status stress_stage_planes(loss_sim *s)
+{
+    float *const *F = s->f.data();
+    const float *v[3] = {F[LOSS_F_EV1], F[LOSS_F_EV2], F[LOSS_F_EV3]};
+    loss_status r = z_stores(s, KC_STRESS_Z, v);
+    if (r) return r;
+    PlaneArgs p = plane_args(s);
+    for (int i = 0; i < 3; ++i) p.in[i] = v[i];
+    const int outs[6] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33, LOSS_F_S12, LOSS_F_S13, LOSS_F_S23};
+    for (int i = 0; i < 6; ++i) p.out[i] = F[outs[i]];
+    p.alpha = 1.f;
+    p.src = base_args(s, 0);
+    const int fid[3] = {LOSS_F_S11, LOSS_F_S22, LOSS_F_S33};
+    attach_sources(s, p.src, -1, fid, 3, false);
+    return run_plane(s, KC_STRESS_XY, 0, p);
+}
+
+// velocity sub-flow over frac * dt: T_i = d3 sigma_i3, then the plane pass over v
+loss_status velocity_stage_planes(loss_sim *s, float frac, float *const *vel, bool with_forces)
+{
+    float *const *F = s->f.data();
+    const float *t3[3] = {F[LOSS_F_S13], F[LOSS_F_S23], F[LOSS_F_S33]};
+    loss_status r = z_stores(s, KC_VEL_Z, t3);
+    if (r) return r;
+    PlaneArgs p = plane_args(s);
+    const int ins[5] = {LOSS_F_S11, LOSS_F_S12, LOSS_F_S22, LOSS_F_S13, LOSS_F_S23};
+    for (int i = 0; i < 5; ++i) p.in[i] = F[ins[i]];
+    for (int i = 0; i < 3; ++i) p.out[i] = vel[i];
+    p.alpha = frac;
+    p.src = base_args(s, 0);
+    if (with_forces) {
+        const int fid[3] = {LOSS_F_EV1, LOSS_F_EV2, LOSS_F_EV3};
+        attach_sources(s, p.src, 0, fid, 3, true);
+    }
+    return run_plane(s, KC_VEL_XY, 1, p);
+}
+
 // ---- velocity sub-flow (A) over frac * dt with the stress frozen -------------
 // acoustic: v1 -= a b dsigma/dx, v3 -= a b dsigma/dz ; elastic: v_i += a b d_j sigma_ij
 // `vel` are the velocity destinations (state or a temporary), `base` optional source
@@ -381,6 +476,7 @@ loss_status velocity_stage(loss_sim *s, float frac, float *const *vel, const flo
     static const int sidx[3][3] = {{LOSS_F_S11, LOSS_F_S12, LOSS_F_S13},
                                    {LOSS_F_S12, LOSS_F_S22, LOSS_F_S23},
                                    {LOSS_F_S13, LOSS_F_S23, LOSS_F_S33}};
+    if (!base && !div_store && plane_ok(s)) return velocity_stage_planes(s, frac, vel, with_forces);
     if (!base) {
         // T = d_x sigma_{i1} (stored), T += d_y sigma_{i2}, v_i += frac b (T + d_z sigma_{i3})
         for (int i = 0; i < 3; ++i) {
@@ -525,6 +621,7 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
         if ((r = acoustic_stress_x(s))) return r;
         return acoustic_stress_z(s, div_store, div_shot_stride);
     }
+    if (!div_store && plane_ok(s)) return stress_stage_planes(s);
     float *const *F = s->f.data();
     const float *lam = s->med[0], *mu = s->med[1], *l2m = s->med[2];
     // normal components: T1 = d1 v1 and T2 = d2 v2 stored, then the z pass updates all
@@ -756,9 +853,11 @@ loss_status upload_receivers(loss_sim *s)
 
 void drop_graph(loss_sim *s)
 {
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    s->gexec = nullptr;
-    s->gsteps = 0;
+    for (auto &g : s->gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    s->graphs_built = false;
 }
 
 // Convert (v at integer time) -> fused state (u half a step ahead), in place.
@@ -900,22 +999,48 @@ loss_status ensure_ready(loss_sim *s)
     return LOSS_OK;
 }
 
-constexpr int kGraphSteps = 32;
+// Queue the sentinel: every shot of field 0 (sigma, or v1 when elastic) checked for
+// non-finite values; a NaN anywhere reaches every field within a step, since every
+// derivative couples the nodes of a patch line.
+loss_status queue_sentinel(loss_sim *s)
+{
+    if (launch_nonfinite(s->f[0], field_elems(s), s->d_bad, s->st) != hipSuccess)
+        return fail(LOSS_EHIP, "non-finite check launch");
+    HIPCHK(hipMemcpyAsync(s->h_bad, s->d_bad, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    return LOSS_OK;
+}
 
-loss_status build_graph(loss_sim *s)
+// LOSS_EUNSTABLE once a queued check has seen a non-finite value
+loss_status check_sentinel(const loss_sim *s)
+{
+    if (*(volatile int *)s->h_bad)
+        return fail(LOSS_EUNSTABLE, "a wavefield holds NaN or infinity (the time step or the media may be "
+                                    "unstable); loss_reset clears the state");
+    return LOSS_OK;
+}
+
+// One graph per power of two up to 2^(kGraphLevels-1) steps, captured together the
+// first time steps run on the current configuration: any step count is then replayed
+// from at most a few graph launches and never captures inside a caller's timed loop.
+loss_status build_graphs(loss_sim *s)
 {
     drop_graph(s);
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
-    loss_status r = LOSS_OK;
-    r = steps_eager(s, kGraphSteps);
-    hipError_t e = hipStreamEndCapture(s->st, &g);
-    if (r) { if (g) (void)hipGraphDestroy(g); return r; }
-    if (e != hipSuccess) return fail(LOSS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) { s->gexec = nullptr; return fail(LOSS_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e)); }
-    s->gsteps = kGraphSteps;
+    for (int k = 0; k < loss_sim::kGraphLevels; ++k) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+        loss_status r = steps_eager(s, int64_t(1) << k);
+        hipError_t e = hipStreamEndCapture(s->st, &g);
+        if (r) { if (g) (void)hipGraphDestroy(g); drop_graph(s); return r; }
+        if (e != hipSuccess) { drop_graph(s); return fail(LOSS_EHIP, std::string("graph capture: ") + hipGetErrorString(e)); }
+        e = hipGraphInstantiate(&s->gexec[k], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            s->gexec[k] = nullptr;
+            drop_graph(s);
+            return fail(LOSS_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+    }
+    s->graphs_built = true;
     return LOSS_OK;
 }
 
@@ -925,15 +1050,21 @@ loss_status run_steps(loss_sim *s, int64_t nsteps, float *div_store, int64_t div
     if ((r = ensure_ready(s))) return r;
     if ((r = fuse(s))) return r;
     const bool use_graph = !(s->d.flags & LOSS_FLAG_NO_GRAPH) && !s->timing && div_store == nullptr;
-    int64_t done = 0;
-    if (use_graph && nsteps >= kGraphSteps) {
-        if (!s->gexec && (r = build_graph(s))) return r;
-        while (nsteps - done >= s->gsteps) {
-            HIPCHK(hipGraphLaunch(s->gexec, s->st));
-            done += s->gsteps;
+    if (use_graph && nsteps > 0) {
+        if (!s->graphs_built && (r = build_graphs(s))) return r;
+        const int top = loss_sim::kGraphLevels - 1;
+        int64_t left = nsteps;
+        while (left >= (int64_t(1) << top)) {
+            HIPCHK(hipGraphLaunch(s->gexec[top], s->st));
+            left -= int64_t(1) << top;
+            if (left > 0 && (r = queue_sentinel(s))) return r;
         }
+        for (int k = top - 1; k >= 0; --k)
+            if (left & (int64_t(1) << k)) HIPCHK(hipGraphLaunch(s->gexec[k], s->st));
+    } else if ((r = steps_eager(s, nsteps, div_store, div_shot_stride))) {
+        return r;
     }
-    if ((r = steps_eager(s, nsteps - done, div_store, div_shot_stride))) return r;
+    if (nsteps > 0 && (r = queue_sentinel(s))) return r;
     s->step += nsteps;
     return LOSS_OK;
 }
@@ -1273,8 +1404,15 @@ loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out)
     for (int i = 0; i < nmed; ++i)
         if ((r = s->alloc(&s->med[i], s->shot_stride))) return bail(r);
     if ((r = s->alloc(&s->d_fields, s->nf)) || (r = s->alloc(&s->d_tmpfields, s->nf)) ||
-        (r = s->alloc(&s->d_step, 1)))
+        (r = s->alloc(&s->d_step, 1)) || (r = s->alloc(&s->d_bad, 1)))
         return bail(r);
+    if (hipHostMalloc((void **)&s->h_bad, sizeof(int), 0) != hipSuccess) {
+        s->h_bad = nullptr;
+        return bail(fail(LOSS_ENOMEM, "hipHostMalloc of the sentinel flag"));
+    }
+    *s->h_bad = 0;
+    if (hipMemcpy(s->d_bad, s->h_bad, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(LOSS_EHIP, "sentinel flag"));
     for (int a = 0; a < 3; ++a) {
         if (a == 1 && d.ndim == 2) continue;
         if ((r = upload_axis(s, a))) return bail(r);
@@ -1309,6 +1447,7 @@ loss_status loss_destroy(loss_sim *s)
     s->allocs.clear();
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
+    if (s->h_bad) (void)hipHostFree(s->h_bad);
     if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
     delete s;
     return LOSS_OK;
@@ -1350,6 +1489,7 @@ loss_status loss_set_media(loss_sim *s, const float *vp, const float *vs, const 
     if (s->d.ndim == 3) hmin = std::min(hmin, s->d.h[1]);
     s->media_set = true;
     drop_graph(s);
+    s->ck_steps = 0;   // checkpoints belong to the previous media
     const double bound = 2.0 * hmin / (std::sqrt(3.0) * std::sqrt((double)s->d.ndim) * cmax);
     if (s->d.dt > bound)
         return fail(LOSS_EUNSTABLE, "dt " + std::to_string(s->d.dt) + " exceeds the stability bound " +
@@ -1413,6 +1553,8 @@ loss_status loss_set_pml(loss_sim *s, int32_t width, double reflection, double k
     loss_status r;
     if ((r = unfuse_in_place(s))) return r;
     drop_graph(s);
+    // checkpoints were taken under the previous layer: an adjoint must not reuse them
+    s->ck_steps = 0;
     for (int a = 0; a < 3; ++a) {
         if (s->pml_tab[a]) { s->release(s->pml_tab[a]); s->pml_tab[a] = nullptr; }
         s->axd[a].pml_w = 0;
@@ -1479,7 +1621,9 @@ loss_status loss_reset(loss_sim *s)
     if (s->traces && s->trace_total > 0)
         HIPCHK(hipMemsetAsync(s->traces, 0, sizeof(double) * s->trace_total, s->st));
     HIPCHK(launch_set_step(s->d_step, 0, s->st));
+    HIPCHK(hipMemsetAsync(s->d_bad, 0, sizeof(int), s->st));
     HIPCHK(hipStreamSynchronize(s->st));
+    *s->h_bad = 0;
     s->step = 0;
     s->fused = false;
     return LOSS_OK;
@@ -1489,6 +1633,8 @@ loss_status loss_step(loss_sim *s, int64_t nsteps)
 {
     if (!s) return fail(LOSS_EINVAL, "null argument");
     if (nsteps < 0) return fail(LOSS_EINVAL, "nsteps must be >= 0");
+    loss_status r = check_sentinel(s);
+    if (r) return r;
     return run_steps(s, nsteps, nullptr, 0);
 }
 
@@ -1565,7 +1711,7 @@ loss_status loss_sync(loss_sim *s)
 {
     if (!s) return fail(LOSS_EINVAL, "null argument");
     HIPCHK(hipStreamSynchronize(s->st));
-    return LOSS_OK;
+    return check_sentinel(s);
 }
 
 loss_status loss_set_timing(loss_sim *s, int32_t on)
@@ -1612,28 +1758,61 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     const bool timing0 = s->timing;
     s->timing = false;
     if ((r = fuse(s))) return r;
-    for (int axis = 0; axis < 3; ++axis) {
-        if (axis == 1 && s->d.ndim == 2) continue;
+    // time trial_steps steps of the current configuration
+    auto trial = [&](float &ms) -> loss_status {
+        loss_status q;
+        if ((q = steps_eager(s, 2))) return q;   // warm this shape up
+        HIPCHK(hipEventRecord(s->ev0, s->st));
+        if ((q = steps_eager(s, trial_steps))) return q;
+        HIPCHK(hipEventRecord(s->ev1, s->st));
+        HIPCHK(hipEventSynchronize(s->ev1));
+        HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+        return LOSS_OK;
+    };
+    // launch shapes of the line kernels along `axis`, the fastest kept; returns its time
+    auto tune_axis = [&](int axis, float &best) -> loss_status {
         // candidates: x -> nodes per lane; y, z -> (columns per wave, nodes per lane)
         std::vector<std::pair<int, int>> cands;
         if (axis == 0) cands = {{4, 0}, {8, 0}, {16, 0}};
         else cands = {{64, 16}, {32, 16}, {16, 16}, {32, 8}, {16, 8}};
-        float best = 1e30f;
+        best = 1e30f;
         std::pair<int, int> bestc = cands[0];
         for (const auto &cd : cands) {
             if (axis == 0) s->cx = cd.first;
             else { s->cw[axis] = cd.first; s->cs[axis] = cd.second; }
-            if ((r = steps_eager(s, 2))) return r;   // warm this shape up
-            HIPCHK(hipEventRecord(s->ev0, s->st));
-            if ((r = steps_eager(s, trial_steps))) return r;
-            HIPCHK(hipEventRecord(s->ev1, s->st));
-            HIPCHK(hipEventSynchronize(s->ev1));
             float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+            loss_status q = trial(ms);
+            if (q) return q;
             if (ms < best) { best = ms; bestc = cd; }
         }
         if (axis == 0) s->cx = bestc.first;
         else { s->cw[axis] = bestc.first; s->cs[axis] = bestc.second; }
+        return LOSS_OK;
+    };
+    float t_line = 0.f;
+    // the line-pass schedule (every axis), then for elastic grids that admit it the
+    // plane schedule (its line kernels run along z only); the faster schedule is kept
+    const int sched0 = s->elastic_schedule;
+    s->elastic_schedule = 1;
+    for (int axis = 0; axis < 3; ++axis) {
+        if (axis == 1 && s->d.ndim == 2) continue;
+        if ((r = tune_axis(axis, t_line))) return r;
+    }
+    s->elastic_schedule = sched0;
+    if (s->d.physics == LOSS_ELASTIC) {
+        s->elastic_schedule = 0;
+        if (plane_ok(s)) {
+            const int cw2 = s->cw[2], cs2 = s->cs[2];
+            float t_plane = 0.f;
+            if ((r = tune_axis(2, t_plane))) return r;
+            if (t_plane > t_line) {
+                s->elastic_schedule = 1;
+                s->cw[2] = cw2;
+                s->cs[2] = cs2;
+            }
+        } else {
+            s->elastic_schedule = sched0;
+        }
     }
     // restore
     for (int f = 0; f < s->nf; ++f)
@@ -1655,6 +1834,12 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
 
 loss_status loss_set_shape(loss_sim *s, int32_t axis, int32_t shape)
 {
+    if (s && axis == 3) {
+        if (shape != 0 && shape != 1) return fail(LOSS_EINVAL, "schedule must be 0 (plane) or 1 (line passes)");
+        s->elastic_schedule = shape;
+        drop_graph(s);
+        return LOSS_OK;
+    }
     if (!s || axis < 0 || axis > 2 || (axis == 1 && s->d.ndim == 2)) return fail(LOSS_EINVAL, "bad axis");
     if (axis == 0) {
         if (shape != 0 && shape != 4 && shape != 8 && shape != 16) return fail(LOSS_EINVAL, "bad x shape");
@@ -1672,7 +1857,11 @@ loss_status loss_set_shape(loss_sim *s, int32_t axis, int32_t shape)
 
 loss_status loss_autotune_choice(loss_sim *s, int32_t axis, int32_t *cw)
 {
-    if (!s || !cw || axis < 0 || axis > 2) return fail(LOSS_EINVAL, "bad argument");
+    if (!s || !cw || axis < 0 || axis > 3) return fail(LOSS_EINVAL, "bad argument");
+    if (axis == 3) {
+        *cw = plane_ok(s) ? 0 : 1;
+        return LOSS_OK;
+    }
     *cw = axis == 0 ? s->cx : s->cw[axis] * 100 + s->cs[axis];
     return LOSS_OK;
 }
@@ -1718,8 +1907,14 @@ loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
 loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, double *grad, int32_t mem)
 {
     if (!s || !residual || !grad) return fail(LOSS_EINVAL, "null argument");
-    if (s->ck_steps < 1) return fail(LOSS_ESTATE, "loss_forward_ckpt must run first");
-    if (s->d.physics == LOSS_ELASTIC) return elastic_adjoint(s, residual, param, grad, mem);
+    if (s->ck_steps < 1)
+        return fail(LOSS_ESTATE, "loss_forward_ckpt must run first (and again after loss_set_media or loss_set_pml)");
+    if ((s->pml_mem != nullptr) != (s->ck_fields > s->nf))
+        return fail(LOSS_ESTATE, "the checkpoints were taken with a different absorbing layer");
+    if (s->d.physics == LOSS_ELASTIC) {
+        if (s->pml_mem) return fail(LOSS_EUNSUPPORTED, "the elastic adjoint is built without the absorbing layer");
+        return elastic_adjoint(s, residual, param, grad, mem);
+    }
     if (param != LOSS_GRAD_K && param != LOSS_GRAD_VP) return fail(LOSS_EINVAL, "unknown gradient parameter");
     loss_status r;
     const int64_t fe = field_elems(s), S = s->S, ss = s->shot_stride;

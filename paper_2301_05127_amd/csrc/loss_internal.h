@@ -160,6 +160,35 @@ struct LineArgs {
     int pml_store;
 };
 
+// Elastic plane pass (plane_xy.hip): one workgroup per (shot, z plane, patch tile of
+// the x-y plane).  The tile's nodes sit in LDS; its x lines and y lines are solved from
+// there (PMBC taps outside the tile from global memory), and the epilogue combines the
+// x and y derivatives of every input with the z derivatives T stored by the z passes.
+//   stress (mode 0): in = v1, v2, v3; out = s11, s22, s33, s12, s13, s23;
+//     sigma_ii += (l2m) d_i v_i + (lam)(sum of the other two), sigma_ij += (mu)(d_i v_j + d_j v_i)
+//     with d3 v_i = T_i; explosive sources on the normal stresses.
+//   velocity (mode 1): in = s11, s12, s22, s13, s23; out = v1, v2, v3;
+//     v_i += alpha (b) (d1 sigma_i1 + d2 sigma_i2 + T_i) with T_i = d3 sigma_i3; body forces.
+// Media hold dt lambda, dt mu, dt (lambda + 2 mu), dt b.  Patch lengths along x and y
+// must be at most kPlaneMaxM and the halo at most kPlaneMaxHalo (the tile and its taps
+// sit in LDS).
+constexpr int kPlaneMaxM = 64;
+constexpr int kPlaneMaxHalo = 12;
+
+struct PlaneArgs {
+    const float *in[5];
+    const float *T[3];
+    float *out[6];
+    const float *lam, *mu, *l2m, *b;
+    float alpha;
+    int S, nx, ny, nz;
+    int64_t pitch, plane, shot_stride;
+    AxisDev ax, ay;
+    LineArgs src;          // source fields of the epilogue (src, src_begin, pools, d_step, out_field, ...)
+};
+
+hipError_t launch_plane_xy(int mode, const PlaneArgs &a, hipStream_t st);
+
 // Launch helpers (kernels.hip).  axis: 0 = x (contiguous), 1 = y, 2 = z.
 hipError_t launch_line(int axis, int solve, int epi, const LineArgs &a, hipStream_t st);
 // Adjoint phase 2: Y at the junction rows from the junction rows of T^T, then

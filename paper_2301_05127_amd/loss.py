@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libloss.so")
+# LOSS_LIBRARY names another build of the same library (A/B timing of kernel variants)
+LIB_PATH = os.environ.get("LOSS_LIBRARY", os.path.join(_HERE, "libloss.so"))
 
 ACOUSTIC, ELASTIC = 0, 1
 END_NATURAL, END_PAPER_STENCIL, END_PERIODIC = 0, 1, 2
@@ -22,6 +23,7 @@ F_EV1, F_EV2, F_EV3, F_S11, F_S22, F_S33, F_S12, F_S13, F_S23 = range(9)
 SRC_PRESSURE, SRC_EXPLOSIVE, SRC_FORCE_X, SRC_FORCE_Y, SRC_FORCE_Z = range(5)
 FLAG_NO_GRAPH = 1
 FLAG_NO_FUSE_X = 2
+FLAG_LINE_PASSES = 4
 GRAD_K, GRAD_VP, GRAD_LAME, GRAD_VPVS, GRAD_LAME_RHO, GRAD_VPVS_RHO = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
@@ -305,18 +307,20 @@ class Simulation:
 
     # ---- launch-shape autotuning ----------------------------------------------------
     def autotune(self, trial_steps=5):
-        """Pick the fastest launch shape of the strided line kernels; returns the
-        columns-per-wave choice per axis."""
+        """Pick the fastest launch shape of the line kernels (and, elastic, the faster of
+        the plane and line-pass schedules); returns the choice per axis (loss_set_shape
+        encoding), then the elastic schedule (0 plane, 1 line passes) when elastic."""
         _check(lib().loss_autotune(self._h, int(trial_steps)))
         out = []
-        for axis in range(3):
+        for axis in range(4 if self.physics == ELASTIC else 3):
             v = ctypes.c_int32()
             _check(lib().loss_autotune_choice(self._h, axis, ctypes.byref(v)))
             out.append(v.value)
         return out
 
     def set_shape(self, shapes):
-        """Set the launch shape per axis (see loss_set_shape); None entries are skipped."""
+        """Set the launch shape per axis (see loss_set_shape; a fourth entry is the elastic
+        schedule, 0 plane passes, 1 line passes); None entries are skipped."""
         for axis, v in enumerate(shapes):
             if v is None or (axis == 1 and self.grid["ndim"] == 2):
                 continue
