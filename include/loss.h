@@ -213,6 +213,24 @@ loss_status loss_get_traces(loss_sim *sim, int32_t shot, double *dst, int32_t me
 loss_status loss_deriv(loss_sim *sim, int32_t axis, int32_t order, const float *in, float *out,
                        int64_t batch, int32_t mem);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): loss_deriv on device arrays
+ * (in, out: batch dense fields on the simulation's device, x fastest) that allocates
+ * nothing.  Instead of the handle's temporaries its kernels stage the padded fields
+ * in a library-static device array of LOSS_STATIC_SCRATCH_FLOATS floats (3 slots;
+ * each GPU the library runs on holds its copy until the process ends), a slot's worth
+ * of fields per pass (loss_create looks up the array's address on its device, which
+ * is when the runtime sets the array up).  The work is queued on the simulation's stream (call loss_sync
+ * before reading out).  The array is shared by every call on that GPU and keeps the
+ * last call's contents: calls that overlap on one GPU (several handles, several
+ * streams or threads) race; serialise them.  The handle's state is not touched.
+ * Errors: LOSS_EINVAL (null pointer, axis, order, batch < 1, or one padded field of the
+ * grid above the slot size LOSS_STATIC_SCRATCH_FLOATS / 3), LOSS_ESTATE (the current
+ * device is not the simulation's), LOSS_EHIP. */
+#define LOSS_STATIC_SCRATCH_FLOATS (3 * 18 * 1024 * 1024)
+loss_status loss_deriv_static(loss_sim *sim, int32_t axis, int32_t order, const float *in, float *out,
+                              int64_t batch);
+
 /* Adjoint-state gradient (the discrete transpose of the Strang scheme of Sec. 3.3 applied
  * to the systems of Sec. 2; the paper states the forward problem only, the gradient is
  * the standard adjoint-state one).  loss_forward_ckpt resets, runs nsteps (<= trace_len) steps

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1332,6 +1333,36 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
     return LOSS_OK;
 }
 
+// ---- device scratch of loss_deriv_static ---------------------------------------
+// Three slots (padded input, padded output, the transposed solve's Y) of
+// LOSS_STATIC_SCRATCH_FLOATS / 3 floats each.  Each GPU the library runs on holds its own
+// copy of the array until the process ends; host code reaches it only through the
+// device address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kStaticSlot = LOSS_STATIC_SCRATCH_FLOATS / 3;
+static __device__ __align__(256) float scratch[LOSS_STATIC_SCRATCH_FLOATS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of the scratch array (looked up once per device).
+loss_status static_scratch(float **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LOSS_EUNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LOSS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LOSS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1385,6 +1416,13 @@ loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out)
             { loss_destroy(s); return fail(LOSS_EUNSUPPORTED, "patch length above 1024"); }
     }
     (void)hipGetDevice(&s->device);
+    {
+        // set-up of loss_deriv_static: the device address of the static scratch array
+        // (the runtime materialises the array on this first lookup, not in that call)
+        float *scr = nullptr;
+        loss_status rs = static_scratch(&scr);
+        if (rs) { loss_destroy(s); return rs; }
+    }
     if (hip_stream) {
         s->st = (hipStream_t)hip_stream;
     } else {
@@ -1703,6 +1741,44 @@ loss_status loss_deriv(loss_sim *s, int32_t axis, int32_t order, const float *in
                 return r;
         }
         if ((r = copy_field_out(s, out + b0 * dense, s->tmp[2], mem, nb))) return r;
+    }
+    return LOSS_OK;
+}
+
+loss_status loss_deriv_static(loss_sim *s, int32_t axis, int32_t order, const float *in, float *out,
+                              int64_t batch)
+{
+    if (!s || !in || !out) return fail(LOSS_EINVAL, "null argument");
+    if (axis < 0 || axis > 2 || (axis == 1 && s->d.ndim == 2)) return fail(LOSS_EINVAL, "bad axis");
+    if (order != 1 && order != 2 && order != -1) return fail(LOSS_EINVAL, "order must be 1, 2 or -1");
+    if (batch < 1) return fail(LOSS_EINVAL, "batch must be >= 1");
+    if (s->shot_stride > kStaticSlot)
+        return fail(LOSS_EINVAL, "a field of this grid takes " + std::to_string(s->shot_stride) +
+                                     " padded floats, above the static scratch slot of " + std::to_string(kStaticSlot));
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != s->device) return fail(LOSS_ESTATE, "the current device is not the simulation's");
+    float *base = nullptr;
+    loss_status r = static_scratch(&base);
+    if (r) return r;
+    float *pin = base, *pout = base + kStaticSlot, *Y = base + 2 * kStaticSlot;
+    const int64_t dense = s->nodes;
+    const int64_t chunk = kStaticSlot / s->shot_stride;   // fields per pass through the scratch
+    for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = (int)std::min<int64_t>(chunk, batch - b0);
+        hipError_t e = launch_pad_copy(in + b0 * dense, pin, s->nx, (int)(nb * s->ny * s->nz), s->pitch, 1, s->st);
+        if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+        if (order == -1) {
+            if ((r = adj_deriv(s, axis, pin, nullptr, pout, 1.f, EPI_STORE, Y, nb))) return r;
+        } else {
+            LineArgs a = base_args(s, axis);
+            a.S = nb;
+            a.in = pin;
+            a.out[0] = pout;
+            if ((r = run_line(s, KC_VEL_X + axis, axis, order == 1 ? SOLVE_D1 : SOLVE_D2, EPI_STORE, a))) return r;
+        }
+        e = launch_pad_copy(pout, out + b0 * dense, s->nx, (int)(nb * s->ny * s->nz), s->pitch, 0, s->st);
+        if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
     }
     return LOSS_OK;
 }

@@ -31,7 +31,7 @@ EXPORTS = [
     "loss_reset", "loss_step", "loss_get_field", "loss_set_field", "loss_get_traces", "loss_deriv",
     "loss_forward_ckpt", "loss_adjoint", "loss_sync", "loss_set_timing", "loss_kernel_timing",
     "loss_current_step", "loss_status_str", "loss_last_error", "loss_autotune",
-    "loss_autotune_choice", "loss_set_shape", "loss_set_pml",
+    "loss_autotune_choice", "loss_set_shape", "loss_set_pml", "loss_deriv_static",
 ]
 
 
@@ -75,6 +75,7 @@ def lib():
         "loss_set_field": (I32, [P, I32, I32, P, I32]),
         "loss_get_traces": (I32, [P, I32, P, I32]),
         "loss_deriv": (I32, [P, I32, I32, P, P, I64, I32]),
+        "loss_deriv_static": (I32, [P, I32, I32, P, P, I64]),
         "loss_forward_ckpt": (I32, [P, I64, I64]),
         "loss_adjoint": (I32, [P, P, I32, P, I32]),
         "loss_sync": (I32, [P]),
@@ -257,6 +258,22 @@ class Simulation:
         batch = a.size // self.nodes
         _check(lib().loss_deriv(self._h, axis, order, a.ctypes.data_as(ctypes.c_void_p),
                                 out.ctypes.data_as(ctypes.c_void_p), batch, MEM_HOST))
+        return out
+
+    def deriv_static(self, axis, order, data, out=None):
+        """loss_deriv on a CUDA tensor (batch, *shape) through the library-static device
+        scratch (allocates nothing in the library); returns `out` (a new tensor unless
+        given) after synchronising the simulation stream."""
+        import torch
+        if out is None:
+            out = torch.empty_like(data)
+        pi, mem, k1 = _ptr(data, np.float32)
+        po, mem2, k2 = _ptr(out, np.float32)
+        if mem != MEM_DEVICE or mem2 != MEM_DEVICE:
+            raise TypeError("deriv_static takes CUDA tensors")
+        torch.cuda.current_stream(data.device).synchronize()
+        _check(lib().loss_deriv_static(self._h, axis, order, pi, po, data.numel() // self.nodes))
+        self.sync()
         return out
 
     # ---- gradient ----------------------------------------------------------------
