@@ -94,32 +94,31 @@ __global__ void k_el_grad_b(double *__restrict__ gb, Three ub, Three dv, double 
     gb[p] += dt * acc;
 }
 
-// the body-force part of the same term: dJ/db += scale f(t_n) w(x) ubar_comp(x) over each
-// force source's footprint (one block per source, FP64 atomics: shots share nodes)
-__global__ void k_el_grad_force(double *gb, const SrcDev *__restrict__ src, float *const *adj,
+// the body-force part of the same term: dJ/db += scale f(t_n) w(x) ubar_comp(x) of every
+// force source; one thread per node of the box covering all force footprints, which sums
+// the sources in their order (shots may share nodes) and adds once: no atomics
+__global__ void k_el_grad_force(double *gb, const SrcDev *__restrict__ src, int nsrc, float *const *adj,
                                 const float *__restrict__ wpool, const float *__restrict__ wavpool,
-                                int64_t shot_stride, int64_t pitch, int64_t plane, int64_t n, double scale)
+                                int64_t shot_stride, int64_t pitch, int64_t plane, int64_t n, double scale, int x0,
+                                int y0, int z0, int bx, int by, int64_t total)
 {
-    const SrcDev sd = src[blockIdx.x];
-    if (!sd.force || n < 0 || n >= sd.nt) return;
-    const double amp = scale * (double)wavpool[sd.wav_off + n];
-    const int tot = sd.bx * sd.by * sd.bz;
-    const float *ub = adj[sd.field0] + (int64_t)sd.shot * shot_stride;
-    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-        const int ix = t % sd.bx, iy = (t / sd.bx) % sd.by, iz = t / (sd.bx * sd.by);
-        const int64_t midx = (int64_t)(sd.z0 + iz) * plane + (int64_t)(sd.y0 + iy) * pitch + (sd.x0 + ix);
-        atomicAdd(gb + midx, amp * (double)wpool[sd.w_off + t] * (double)ub[midx]);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int x = x0 + (int)(t % bx), y = y0 + (int)((t / bx) % by), z = z0 + (int)(t / ((int64_t)bx * by));
+    const int64_t midx = (int64_t)z * plane + (int64_t)y * pitch + x;
+    double acc = 0.0;
+    bool any = false;
+    for (int k = 0; k < nsrc; ++k) {
+        const SrcDev &sd = src[k];
+        if (!sd.force || n < 0 || n >= sd.nt) continue;
+        const unsigned ix = (unsigned)(x - sd.x0), iy = (unsigned)(y - sd.y0), iz = (unsigned)(z - sd.z0);
+        if (ix >= (unsigned)sd.bx || iy >= (unsigned)sd.by || iz >= (unsigned)sd.bz) continue;
+        const double amp = scale * (double)wavpool[sd.wav_off + n];
+        const float *ub = adj[sd.field0] + (int64_t)sd.shot * shot_stride;
+        acc += amp * (double)wpool[sd.w_off + ((int64_t)iz * sd.by + iy) * sd.bx + ix] * (double)ub[midx];
+        any = true;
     }
-}
-
-// adjoint field rec.comp += w * residual sample n, for every receiver
-__global__ void k_el_residual_inject(const RecDev *__restrict__ rec, int nrec, float *const *adj,
-                                     int64_t shot_stride, const double *__restrict__ res, int64_t n, float w)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrec) return;
-    const RecDev rd = rec[r];
-    atomicAdd(adj[rd.comp] + (int64_t)rd.shot * shot_stride + rd.node, w * (float)res[rd.trace_off + n]);
+    if (any) gb[midx] += acc;
 }
 
 // padded accumulators -> dense gradients.  mode 0: (dJ/dlambda, dJ/dmu); 1: (dJ/dvp,
@@ -183,20 +182,13 @@ hipError_t launch_el_grad_b(double *gb, const float *const *ubar, const float *c
 
 hipError_t launch_el_grad_force(double *gb, const SrcDev *src, int nsrc, float *const *adj, const float *wpool,
                                 const float *wavpool, int64_t shot_stride, int64_t pitch, int64_t plane, int64_t n,
-                                double scale, hipStream_t st)
+                                double scale, const int *box, hipStream_t st)
 {
-    if (nsrc <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_el_grad_force, nsrc, 256, 0, st, gb, src, adj, wpool, wavpool, shot_stride, pitch, plane, n,
-                       scale);
-    return hipGetLastError();
-}
-
-hipError_t launch_el_residual_inject(const RecDev *rec, int nrec, float *const *adj, int64_t shot_stride,
-                                     const double *res, int64_t n, float w, hipStream_t st)
-{
-    if (nrec <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_el_residual_inject, (unsigned)((nrec + 255) / 256), 256, 0, st, rec, nrec, adj,
-                       shot_stride, res, n, w);
+    if (nsrc <= 0 || box[1] <= box[0]) return hipSuccess;
+    const int bx = box[1] - box[0], by = box[3] - box[2], bz = box[5] - box[4];
+    const int64_t total = (int64_t)bx * by * bz;
+    hipLaunchKernelGGL(k_el_grad_force, (unsigned)((total + 255) / 256), 256, 0, st, gb, src, nsrc, adj, wpool,
+                       wavpool, shot_stride, pitch, plane, n, scale, box[0], box[2], box[4], bx, by, total);
     return hipGetLastError();
 }
 

@@ -527,10 +527,9 @@ __global__ void __launch_bounds__(256) k_adj_gather(LineArgs a, const float *__r
     float out = w.y * yl[j * stride];
     out = fmaf(w.x, yl[max(j - 1, 0) * stride], out);
     out = fmaf(w.z, yl[min(j + 1, ax.N) * stride], out);
-    const int *gn = ax.g_node + (int64_t)j * kMaxGatherTaps;
-    const float *gc = ax.g_c + (int64_t)j * kMaxGatherTaps;
-#pragma unroll
-    for (int t = 0; t < kMaxGatherTaps; ++t) {
+    const int *gn = ax.g_node + (int64_t)j * ax.gmax;
+    const float *gc = ax.g_c + (int64_t)j * ax.gmax;
+    for (int t = 0; t < ax.gmax; ++t) {
         const int J = gn[t];
         if (J >= 0) out = fmaf(gc[t], yl[J * stride], out);
     }
@@ -578,10 +577,9 @@ __global__ void __launch_bounds__(256) k_adj_gather_s(LineArgs a, const float *_
         float out = w.y * yv[i + 1];
         out = fmaf(w.x, yv[r > 0 ? i : i + 1], out);
         out = fmaf(w.z, yv[r < N ? i + 2 : i + 1], out);
-        const int *gn = ax.g_node + (int64_t)r * kMaxGatherTaps;
-        const float *gcf = ax.g_c + (int64_t)r * kMaxGatherTaps;
-#pragma unroll
-        for (int t = 0; t < kMaxGatherTaps; ++t) {
+        const int *gn = ax.g_node + (int64_t)r * ax.gmax;
+        const float *gcf = ax.g_c + (int64_t)r * ax.gmax;
+        for (int t = 0; t < ax.gmax; ++t) {
             const int J = gn[t];
             if (J >= 0) out = fmaf(gcf[t], yl[J * stride], out);
         }
@@ -646,29 +644,31 @@ __device__ __forceinline__ void adj_x_pass(const AxisDev &ax, int G, float *ys, 
         ys[s] = v;
     }
     __syncthreads();
-    auto col = [&](int i, float4 aw, int4 gn, float4 gc) {
+    // the stencil part of column i of G^T; the special columns add their junction rows
+    auto col = [&](int i, float4 aw) {
         float o = aw.y * ys[i];
         o = fmaf(aw.x, ys[max(i - 1, 0)], o);
         o = fmaf(aw.z, ys[min(i + 1, N)], o);
-        if (gn.x >= 0) o = fmaf(gc.x, ys[gn.x], o);
-        if (gn.y >= 0) o = fmaf(gc.y, ys[gn.y], o);
-        if (gn.z >= 0) o = fmaf(gc.z, ys[gn.z], o);
-        if (gn.w >= 0) o = fmaf(gc.w, ys[gn.w], o);
         return o;
     };
-    const int4 none = make_int4(-1, -1, -1, -1);
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     const int nthr = blockDim.x;
 #pragma unroll
     for (int r = 0; r < C + 1; ++r) {
         const int i = (int)threadIdx.x + r * nthr;
-        if (i <= N && ((pw[r] >> (i & 31)) & 1u)) emit(i, col(i, ax.adjw_plain, none, zero4), r);
+        if (i <= N && ((pw[r] >> (i & 31)) & 1u)) emit(i, col(i, ax.adjw_plain), r);
     }
     for (int i = (int)threadIdx.x + (C + 1) * nthr; i <= N; i += nthr)
-        if ((ax.plain[i >> 5] >> (i & 31)) & 1u) emit(i, col(i, ax.adjw_plain, none, zero4), -1);
+        if ((ax.plain[i >> 5] >> (i & 31)) & 1u) emit(i, col(i, ax.adjw_plain), -1);
     for (int t = threadIdx.x; t < ax.nspec; t += nthr) {
         const SpecialCol sc = ax.spec[t];
-        emit(sc.row, col(sc.row, sc.aw, sc.gn, sc.gc), -1);
+        float o = col(sc.row, sc.aw);
+        const int *gn = ax.g_node + (int64_t)sc.row * ax.gmax;
+        const float *gc = ax.g_c + (int64_t)sc.row * ax.gmax;
+        for (int q = 0; q < ax.gmax; ++q) {
+            const int J = gn[q];
+            if (J >= 0) o = fmaf(gc[q], ys[J], o);
+        }
+        emit(sc.row, o, -1);
     }
 }
 
@@ -858,13 +858,20 @@ __global__ void k_record2(const RecDev *__restrict__ rec0, int nrec0, float w0, 
 
 __global__ void k_set_step(int64_t *d_step, int64_t v) { *d_step = v; }
 
-__global__ void k_residual_inject(const RecDev *__restrict__ rec, int nrec, float *lam, int64_t shot_stride,
-                                  const double *__restrict__ res, int64_t n)
+// Residual injection of the adjoint: each target node sums its receivers' samples in
+// receiver order (FP64) and adds the sum once; targets are distinct, so no atomics.
+__global__ void k_res_gather(const RecTarget *__restrict__ tg, int nt, const int64_t *__restrict__ toff,
+                             float *const *fields, float *single, int64_t shot_stride,
+                             const double *__restrict__ res, int64_t n, float w)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrec) return;
-    const RecDev rd = rec[r];
-    atomicAdd(lam + (int64_t)rd.shot * shot_stride + rd.node, (float)res[rd.trace_off + n]);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const RecTarget g = tg[t];
+    double acc = 0.0;
+    for (int k = g.first; k < g.first + g.count; ++k) acc += res[toff[k] + n];
+    float *f = single ? single : fields[g.comp];
+    const int64_t i = (int64_t)g.shot * shot_stride + g.node;
+    f[i] += w * (float)acc;
 }
 
 __global__ void k_pad_copy(const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, int nz,
@@ -1206,11 +1213,11 @@ hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields
     return hipGetLastError();
 }
 
-hipError_t launch_residual_inject(const RecDev *rec, int nrec, float *lam, int64_t shot_stride,
-                                  const double *res, int64_t n, hipStream_t st)
+hipError_t launch_res_gather(const RecTarget *tg, int nt, const int64_t *toff, float *const *fields, float *single,
+                             int64_t shot_stride, const double *res, int64_t n, float w, hipStream_t st)
 {
-    if (nrec <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_residual_inject, nblk(nrec, 256), 256, 0, st, rec, nrec, lam, shot_stride, res, n);
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_res_gather, nblk(nt, 256), 256, 0, st, tg, nt, toff, fields, single, shot_stride, res, n, w);
     return hipGetLastError();
 }
 

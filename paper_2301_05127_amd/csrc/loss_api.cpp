@@ -96,6 +96,12 @@ struct loss_sim {
     bool rec_has_vel = false, rec_has_stress = false;
     RecDev *d_rec_vel = nullptr, *d_rec_str = nullptr;
     int nrec_vel = 0, nrec_str = 0;
+    // the same receivers grouped by target node for the adjoint's residual injection
+    RecTarget *d_tgt_vel = nullptr, *d_tgt_str = nullptr;
+    int64_t *d_toff_vel = nullptr, *d_toff_str = nullptr;
+    int ntgt_vel = 0, ntgt_str = 0;
+    // box [x0, x1) x [y0, y1) x [z0, z1) covering every force source's footprint
+    int force_box[6] = {0, 0, 0, 0, 0, 0};
     std::vector<int64_t> rec_off;  // per shot trace offset
     double *traces = nullptr;
     int64_t trace_total = 0;
@@ -752,6 +758,17 @@ loss_status upload_sources(loss_sim *s)
             wavpool.insert(wavpool.end(), h.wavelet.begin(), h.wavelet.end());
             sd.push_back(d);
         }
+    for (int k = 0; k < 6; ++k) s->force_box[k] = 0;
+    bool first_force = true;
+    for (const SrcDev &d : sd) {
+        if (!d.force) continue;
+        const int lo[3] = {d.x0, d.y0, d.z0}, hi[3] = {d.x0 + d.bx, d.y0 + d.by, d.z0 + d.bz};
+        for (int a = 0; a < 3; ++a) {
+            s->force_box[2 * a] = first_force ? lo[a] : std::min(s->force_box[2 * a], lo[a]);
+            s->force_box[2 * a + 1] = first_force ? hi[a] : std::max(s->force_box[2 * a + 1], hi[a]);
+        }
+        first_force = false;
+    }
     std::vector<int> begin(s->S + 1, 0);
     for (const SrcDev &d : sd) begin[d.shot + 1]++;
     for (int k = 0; k < s->S; ++k) begin[k + 1] += begin[k];
@@ -819,6 +836,38 @@ loss_status upload_receivers(loss_sim *s)
         if ((r = s->alloc(&s->d_rec_str, str.size()))) return r;
         HIPCHK(hipMemcpy(s->d_rec_str, str.data(), str.size() * sizeof(RecDev), hipMemcpyHostToDevice));
     }
+    // targets of the residual injection: receivers grouped by (shot, field, node), each
+    // group in receiver order
+    auto targets = [&](const std::vector<RecDev> &list, RecTarget **dt, int64_t **dtoff, int *nt) -> loss_status {
+        if (*dt) { s->release(*dt); *dt = nullptr; }
+        if (*dtoff) { s->release(*dtoff); *dtoff = nullptr; }
+        std::vector<int> order(list.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const RecDev &x = list[a], &y = list[b];
+            if (x.shot != y.shot) return x.shot < y.shot;
+            if (x.comp != y.comp) return x.comp < y.comp;
+            return x.node < y.node;
+        });
+        std::vector<RecTarget> tg;
+        std::vector<int64_t> toff;
+        for (int k : order) {
+            const RecDev &d = list[k];
+            if (tg.empty() || tg.back().shot != d.shot || tg.back().comp != d.comp || tg.back().node != d.node)
+                tg.push_back(RecTarget{d.shot, d.comp, d.node, (int)toff.size(), 0});
+            tg.back().count++;
+            toff.push_back(d.trace_off);
+        }
+        *nt = (int)tg.size();
+        if (tg.empty()) return LOSS_OK;
+        loss_status q;
+        if ((q = s->alloc(dt, tg.size())) || (q = s->alloc(dtoff, toff.size()))) return q;
+        HIPCHK(hipMemcpy(*dt, tg.data(), tg.size() * sizeof(RecTarget), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(*dtoff, toff.data(), toff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        return LOSS_OK;
+    };
+    if ((r = targets(vel, &s->d_tgt_vel, &s->d_toff_vel, &s->ntgt_vel))) return r;
+    if ((r = targets(str, &s->d_tgt_str, &s->d_toff_str, &s->ntgt_str))) return r;
     // acoustic: the pressure receivers go to the z stress kernel, keyed by the
     // flattened z column (shot, y, x) of that kernel
     if (s->d.physics == LOSS_ACOUSTIC && !str.empty()) {
@@ -1143,7 +1192,7 @@ loss_status upload_axis(loss_sim *s, int axis)
     std::vector<unsigned> plain((n + 31) / 32, 0u);
     for (int j = 0; j < n; ++j) {
         bool ok = adjw[j].x == plain4.x && adjw[j].y == plain4.y && adjw[j].z == plain4.z;
-        for (int t = 0; t < kMaxGatherTaps; ++t) ok = ok && h.g_node[(size_t)j * kMaxGatherTaps + t] < 0;
+        for (int t = 0; t < h.gmax; ++t) ok = ok && h.g_node[(size_t)j * h.gmax + t] < 0;
         if (ok) plain[j >> 5] |= 1u << (j & 31);
     }
     std::vector<SpecialCol> spec;
@@ -1151,9 +1200,6 @@ loss_status upload_axis(loss_sim *s, int axis)
         if ((plain[j >> 5] >> (j & 31)) & 1u) continue;
         SpecialCol sc{};
         sc.aw = adjw[j];
-        const size_t g = (size_t)j * kMaxGatherTaps;
-        sc.gn = make_int4(h.g_node[g], h.g_node[g + 1], h.g_node[g + 2], h.g_node[g + 3]);
-        sc.gc = make_float4(gc[g], gc[g + 1], gc[g + 2], gc[g + 3]);
         sc.row = j;
         spec.push_back(sc);
     }
@@ -1199,7 +1245,7 @@ loss_status upload_axis(loss_sim *s, int axis)
     d.reach = h.reach;
     d.lum = dlum; d.lum2 = dlum2;
     d.lu = dlu; d.rc = drc; d.luT = dluT; d.lu2 = dlu2; d.lu2c = dlu2c;
-    d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc; d.adjw = dadjw;
+    d.tap_idx = dti; d.tap_c = dtc; d.g_node = dgn; d.g_c = dgc; d.gmax = h.gmax; d.adjw = dadjw;
     d.plain = dplain; d.adjw_plain = plain4;
     d.spec = dspec; d.nspec = (int)spec.size();
     return LOSS_OK;
@@ -1258,11 +1304,13 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
     static const int sh[3][3] = {{LOSS_F_S12, 0, 1}, {LOSS_F_S13, 0, 2}, {LOSS_F_S23, 1, 2}};
     const float *sbar[6] = {A[LOSS_F_S11], A[LOSS_F_S22], A[LOSS_F_S33], A[LOSS_F_S12], A[LOSS_F_S13],
                             A[LOSS_F_S23]};
-    auto inject_res = [&](const RecDev *rec, int nrec, int64_t n, float w) -> loss_status {
-        if (nrec == 0) return LOSS_OK;
+    auto inject_res = [&](bool vel, int64_t n, float w) -> loss_status {
+        const int nt = vel ? s->ntgt_vel : s->ntgt_str;
+        if (nt == 0) return LOSS_OK;
         loss_status q = timed_begin(s);
         if (q) return q;
-        const hipError_t e = launch_el_residual_inject(rec, nrec, s->d_adjtab, ss, s->res_dev, n, w, s->st);
+        const hipError_t e = launch_res_gather(vel ? s->d_tgt_vel : s->d_tgt_str, nt, vel ? s->d_toff_vel : s->d_toff_str,
+                                               s->d_adjtab, nullptr, ss, s->res_dev, n, w, s->st);
         if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
         return timed_end(s, KC_RECEIVER);
     };
@@ -1277,7 +1325,7 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
         if ((r = steps_eager(s, nc, s->divstore, ss))) return r;
         for (int64_t k = nc - 1; k >= 0; --k) {
             const int64_t n = n0 + k;
-            if ((r = inject_res(s->d_rec_vel, s->nrec_vel, n, 0.5f))) return r;
+            if ((r = inject_res(true, n, 0.5f))) return r;
             if (want_b) {
                 // the velocity step of step n drove u with (dt b)(sum_j D_j sigma_ij + f(t_{n+1}) w)
                 const float *ub[3] = {A[LOSS_F_EV1], A[LOSS_F_EV2], A[LOSS_F_EV3]};
@@ -1287,15 +1335,15 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
                 hipError_t e = launch_el_grad_b(gb, ub, dv, s->d.dt, s->nx, s->pitch, ss, S, s->st);
                 if (e == hipSuccess)
                     e = launch_el_grad_force(gb, s->d_src, s->nsrc, s->d_adjtab, s->d_wpool, s->d_wavpool, ss,
-                                             s->pitch, s->plane, n + 1, s->d.dt, s->st);
+                                             s->pitch, s->plane, n + 1, s->d.dt, s->force_box, s->st);
                 if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
                 if ((r = timed_end(s, KC_GRAD))) return r;
             }
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j)
                     if ((r = adj_deriv(s, j, A[LOSS_F_EV1 + i], b, A[sidx[i][j]], 1.f, EPI_AXPY, Y, S))) return r;
-            if ((r = inject_res(s->d_rec_str, s->nrec_str, n, 1.f))) return r;
-            if ((r = inject_res(s->d_rec_vel, s->nrec_vel, n, 0.5f))) return r;
+            if ((r = inject_res(false, n, 1.f))) return r;
+            if ((r = inject_res(true, n, 0.5f))) return r;
             const float *strain[6];
             for (int q = 0; q < 6; ++q) strain[q] = s->divstore + (k * slots + q) * fe;
             if ((r = timed_begin(s))) return r;
@@ -1319,7 +1367,7 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
     hipError_t e = hipSuccess;
     if (want_b)   // the opening half step drove u with (dt/2) b f(t_0) w (the state starts at rest)
         e = launch_el_grad_force(gb, s->d_src, s->nsrc, s->d_adjtab, s->d_wpool, s->d_wavpool, ss, s->pitch,
-                                 s->plane, 0, 0.5 * s->d.dt, s->st);
+                                 s->plane, 0, 0.5 * s->d.dt, s->force_box, s->st);
     if (e == hipSuccess) {
         const int mode = param == LOSS_GRAD_LAME ? 0 : param == LOSS_GRAD_VPVS ? 1 : param == LOSS_GRAD_LAME_RHO ? 2 : 3;
         e = launch_el_grad_unpad(s->grad_pad, s->grad_pad + ss, gb, s->grad_dense, s->nx, s->pitch, s->d_vp, s->d_vs,
@@ -2048,7 +2096,8 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
                 if ((r = pass_t(0, mu1, b, 0, lam))) return r;
                 if ((r = pass_t(2, mu3, b, 1, lam))) return r;
                 if ((r = timed_begin(s))) return r;
-                hipError_t e = launch_residual_inject(s->d_rec_str, s->nrec_str, lam, ss, s->res_dev, n, s->st);
+                hipError_t e = launch_res_gather(s->d_tgt_str, s->ntgt_str, s->d_toff_str, nullptr, lam, ss, s->res_dev,
+                                                 n, 1.f, s->st);
                 if (e == hipSuccess) e = launch_grad_accum(s->grad_pad, lam, s->divstore + k * fe, -dt, (int)S, ss, ss, s->st);
                 if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
                 if ((r = timed_end(s, KC_GRAD))) return r;
@@ -2066,7 +2115,8 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
             const int64_t n = n0 + k;
             if (!lam_x_done && (r = adj_deriv(s, 0, mu1, b, lam, -1.f, EPI_AXPY, Y, (int)S))) return r;
             if ((r = timed_begin(s))) return r;
-            hipError_t e = launch_residual_inject(s->d_rec_str, s->nrec_str, lam, ss, s->res_dev, n, s->st);
+            hipError_t e = launch_res_gather(s->d_tgt_str, s->ntgt_str, s->d_toff_str, nullptr, lam, ss, s->res_dev, n,
+                                             1.f, s->st);
             if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
             if ((r = timed_end(s, KC_RECEIVER))) return r;
             if ((r = adj_deriv(s, 2, mu3, b, lam, -1.f, EPI_AXPY, Y, (int)S))) return r;

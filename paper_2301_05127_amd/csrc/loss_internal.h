@@ -24,7 +24,6 @@
 namespace loss {
 
 constexpr int kMaxHalo = 64;
-constexpr int kMaxGatherTaps = 4;   // junction rows reaching one node (transposed PMBC)
 constexpr int kTabPad = 64;         // identity rows after row N of the per-row factor tables
 // The carry a chunk leaves out of its elimination when it composes only the maps of
 // the chunks within `reach` rows is at most kReachTol times the carry itself.
@@ -47,8 +46,10 @@ struct AxisHost {
     // LU of T (forward) and of T^T (adjoint), no pivoting
     std::vector<double> m, invd;        // T:   y_i = rhs_i - m_i y_{i-1}; w_i = (y_i - sup_i w_{i+1}) invd_i
     std::vector<double> mT, invdT, supT, subT;
-    // transposed PMBC: for node j, up to kMaxGatherTaps (junction node, coefficient)
-    std::vector<int> g_node;            // [N+1][kMaxGatherTaps], -1 = none
+    // transposed PMBC: for node j, up to gmax (junction node, coefficient) pairs, gmax
+    // the most junction rows whose taps reach one node (about 2 halo / M + 1)
+    int gmax = 1;
+    std::vector<int> g_node;            // [N+1][gmax], -1 = none
     std::vector<double> g_c;
     // second-derivative system (per patch, Hermite/natural end rows)
     std::vector<double> m2, invd2, sup2;    // factors for rows as the first/interior row of a patch
@@ -63,9 +64,7 @@ std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_m
 // the transposed PMBC rows reaching it (gather of the adjoint x pass).
 struct SpecialCol {
     float4 aw;             // {c+ of row j-1, c0 of row j, c- of row j+1, 0}
-    float4 gc;             // coefficients of the junction rows in gn
-    int4 gn;               // junction rows reaching the node (-1 = none)
-    int row, pad0, pad1, pad2;
+    int row, pad0, pad1, pad2;   // node j; its junction rows are row j of g_node / g_c
 };
 
 // Device copy of one axis (float32).
@@ -84,8 +83,9 @@ struct AxisDev {
     const float2 *lu2c;    // {m2c, invd2c}
     const int *tap_idx;    // [nslot][ntap]
     const float *tap_c;
-    const int *g_node;     // [N+1][kMaxGatherTaps]
+    const int *g_node;     // [N+1][gmax]
     const float *g_c;
+    int gmax;              // entries per node of g_node / g_c
     const float4 *adjw;    // [N+1] {c+ of row j-1, c0 of row j, c- of row j+1, 0}: column j of G's stencil
     const unsigned *plain; // bit j: column j is {s3, 0, -s3, 0} and no junction row's taps reach node j
     float4 adjw_plain;     // that column
@@ -218,6 +218,14 @@ struct RecDev {
     int64_t node;                     // padded node offset within a shot field
     int64_t trace_off;                // offset of sample 0 in the trace pool
 };
+// One node that receives trace residuals in the adjoint: the receivers at that node of
+// that shot and field are entries first .. first + count - 1 of a trace-offset list, in
+// receiver order (so the injection needs no atomics and sums in a fixed order).
+struct RecTarget {
+    int shot, comp;
+    int64_t node;
+    int first, count;
+};
 
 // adjoint through the absorbing layer (adjoint_layer.hip)
 hipError_t launch_pml_adj_operand(float *w, const float *f, const float *coef, float alpha, float *m,
@@ -240,11 +248,15 @@ hipError_t launch_inject(const SrcDev *src, int nsrc, float *const *fields, cons
                          const float *wpool, const float *wavpool, int64_t shot_stride, int64_t pitch,
                          int64_t plane, const int64_t *d_step, int time_offset, float scale,
                          int want_force, hipStream_t st);
+// dJ/db += scale f(t_n) w(x) ubar(x) of every force source; one thread per node of the box
+// [x0, x1) x [y0, y1) x [z0, z1) covering all force footprints, sources summed in order
 hipError_t launch_el_grad_force(double *gb, const SrcDev *src, int nsrc, float *const *adj, const float *wpool,
                                 const float *wavpool, int64_t shot_stride, int64_t pitch, int64_t plane, int64_t n,
-                                double scale, hipStream_t st);
-hipError_t launch_el_residual_inject(const RecDev *rec, int nrec, float *const *adj, int64_t shot_stride,
-                                     const double *res, int64_t n, float w, hipStream_t st);
+                                double scale, const int *box, hipStream_t st);
+// field[target] += w * (sum of the target's residual samples n), one thread per target:
+// fields = device table of field pointers by field id, or `single` for every target
+hipError_t launch_res_gather(const RecTarget *tg, int nt, const int64_t *toff, float *const *fields, float *single,
+                             int64_t shot_stride, const double *res, int64_t n, float w, hipStream_t st);
 hipError_t launch_record(const RecDev *rec, int nrec, const float *const *fields, int64_t shot_stride,
                          double *traces, const int64_t *d_step, int64_t trace_len, float weight,
                          int accumulate, hipStream_t st);
@@ -267,8 +279,6 @@ hipError_t launch_grad_accum(double *g, const float *lam, const float *div, floa
 hipError_t launch_grad_unpad(const double *gp, double *g, int nx, int rows, int64_t pitch, const float *vp,
                              const float *rho, int param, hipStream_t st);
 hipError_t launch_nonfinite(const float *p, int64_t n, int *flag, hipStream_t st);
-// lambda[shot][node] += residual[trace_off + n] for every receiver
-hipError_t launch_residual_inject(const RecDev *rec, int nrec, float *lam, int64_t shot_stride,
-                                  const double *res, int64_t n, hipStream_t st);
+
 
 }  // namespace loss

@@ -200,19 +200,26 @@ std::string build_axis(AxisHost &ax, int N, double h, int M, int halo, int end_m
         dprev = di;
     }
     // ---- transposed PMBC gather ---------------------------------------------
-    ax.g_node.assign((size_t)n * kMaxGatherTaps, -1);
-    ax.g_c.assign((size_t)n * kMaxGatherTaps, 0.0);
+    // (a halo wider than the patches reaches a node from several junction rows: the
+    // table is as wide as the most rows reaching one node)
     std::vector<int> cnt(n, 0);
+    for (size_t s = 0; s < ax.junction_node.size(); ++s)
+        for (int t = 0; t < ntap; ++t) {
+            const int k = ax.tap_idx[s * ntap + t];
+            if (k >= 0 && ax.tap_c[s * ntap + t] != 0.0) ++cnt[k];
+        }
+    ax.gmax = std::max(1, *std::max_element(cnt.begin(), cnt.end()));
+    ax.g_node.assign((size_t)n * ax.gmax, -1);
+    ax.g_c.assign((size_t)n * ax.gmax, 0.0);
+    std::fill(cnt.begin(), cnt.end(), 0);
     for (size_t s = 0; s < ax.junction_node.size(); ++s) {
         for (int t = 0; t < ntap; ++t) {
             int k = ax.tap_idx[s * ntap + t];
             if (k < 0) continue;
             double c = ax.tap_c[s * ntap + t];
             if (c == 0.0) continue;
-            if (cnt[k] >= kMaxGatherTaps)
-                return "halo reaches more than 4 junction rows from one node (patch too short)";
-            ax.g_node[(size_t)k * kMaxGatherTaps + cnt[k]] = ax.junction_node[s];
-            ax.g_c[(size_t)k * kMaxGatherTaps + cnt[k]] = c;
+            ax.g_node[(size_t)k * ax.gmax + cnt[k]] = ax.junction_node[s];
+            ax.g_c[(size_t)k * ax.gmax + cnt[k]] = c;
             ++cnt[k];
         }
     }

@@ -19,6 +19,9 @@ CASES = [
     (3, (64, 64, 64), (64, 32, 16), 10, 2),
     (2, (50, 0, 40), (50, 50, 40), 4, 0),        # one patch per axis (global spline)
     (2, (37, 0, 21), (3, 3, 3), 2, 0),           # very short patches
+    (2, (96, 0, 80), (4, 4, 4), 12, 0),          # halo 3 patches wide
+    (3, (48, 40, 44), (8, 8, 8), 20, 0),         # the halo 20 of the decay pin, 2.5 patches wide
+    (2, (96, 0, 96), (8, 8, 8), 20, 2),          # periodic, halo wider than the patches
 ]
 
 

@@ -29,25 +29,28 @@ def _workload(nsteps):
                 shots=[{"sources": [src], "receivers": rec, "rec_comp": 0}])
 
 
-def _gpu(w, flags=0, cx=None):
+def _gpu(w, flags=0, cx=None, kmax=None):
     from paper_2301_05127_amd import loss
     sim = loss.Simulation(w["grid"], 0, w["dt"], nshots=1, trace_len=w["nsteps"], flags=flags)
     sim.setup_workload(w)
-    sim.set_pml(PML["width"], PML["R"], PML["kmax"], PML["f0"])
+    sim.set_pml(PML["width"], PML["R"], PML["kmax"] if kmax is None else kmax, PML["f0"])
     if cx:
         sim.set_shape([cx, None, None])
     return sim
 
 
-def test_pml_matches_oracle(orc):
+@pytest.mark.parametrize("kmax", [1.0, 2.0])
+def test_pml_matches_oracle(orc, kmax):
     """500 steps: the pulse crosses the layer.  Errors are measured against the largest
-    field norm of the run (late fields are tiny once the layer has absorbed them)."""
+    field norm of the run (late fields are tiny once the layer has absorbed them).
+    kmax = 2 stretches the coordinate (k from 1 to 2 across the layer), so the tabulated
+    1/k and d/k^2 factors are compared with the oracle's."""
     require_gpu()
     w = _workload(500)
-    announce("pml parity 500 steps")
-    sim = _gpu(w)
+    announce("pml parity 500 steps kmax %g" % kmax)
+    sim = _gpu(w, kmax=kmax)
     sh = w["shots"][0]
-    pml = dict(PML, cmax=float(w["vp"].max()))
+    pml = dict(PML, cmax=float(w["vp"].max()), kmax=kmax)
     of, peak, errs = None, np.zeros(3), []
     for n0 in range(0, 500, 100):
         sim.step(100)
@@ -136,7 +139,8 @@ def test_pml_full_size_few_steps(orc, shape):
     sim.close()
 
 
-def test_pml_gradient_matches_oracle():
+@pytest.mark.parametrize("kmax", [1.0, 2.0])
+def test_pml_gradient_matches_oracle(kmax):
     """The acoustic gradient through the layer: 2 shots on the 128 x 96 grid with the
     16-node layer, 300 steps (the pulse crosses the layer), checkpoints every 70 (a short
     last segment): dJ/dK against the FP64 oracle's layer adjoint, shot by shot."""
@@ -145,8 +149,8 @@ def test_pml_gradient_matches_oracle():
     w = _workload(300)
     src2 = dict(w["shots"][0]["sources"][0], pos=(900.0, 0.0, 300.0))
     w["shots"].append({"sources": [src2], "receivers": w["shots"][0]["receivers"], "rec_comp": 0})
-    announce("pml gradient 2 shots 300 steps")
-    pml = dict(PML, cmax=float(w["vp"].max()))
+    announce("pml gradient 2 shots 300 steps kmax %g" % kmax)
+    pml = dict(PML, cmax=float(w["vp"].max()), kmax=kmax)
     obs, g_ref = [], np.zeros_like(w["vp"])
     import oracle as orc
     for sh in w["shots"]:
@@ -159,7 +163,7 @@ def test_pml_gradient_matches_oracle():
                                           sh["receivers"], d - o)
     sim = loss.Simulation(w["grid"], 0, w["dt"], nshots=2, trace_len=300)
     sim.setup_workload(w)
-    sim.set_pml(PML["width"], PML["R"], PML["kmax"], PML["f0"])
+    sim.set_pml(PML["width"], PML["R"], kmax, PML["f0"])
     sim.forward_ckpt(300, 70)
     tr = [sim.get_traces(s) for s in range(2)]
     g = sim.adjoint(np.concatenate([(tr[s] - obs[s]).ravel() for s in range(2)]), loss.GRAD_K)
