@@ -121,7 +121,9 @@ typedef struct {
  * tridiagonal factor tables in FP64 on the host (Sec. 3.2: truncated rows of the
  * inverse of the global collocation matrix) and stores them as float32.
  * Errors: LOSS_EINVAL for an inconsistent desc (ndim/physics mismatch, M < 1,
- * n < 2, halo < 1 or > 64, periodic with 2*halo+1 > n), LOSS_ENOMEM, LOSS_EHIP. */
+ * n < 2, halo < 1 or > 64, periodic with 2*halo+1 > n), LOSS_EUNSUPPORTED for a
+ * patch length above 1024 or a per-shot field of 2^31 or more elements (the x extent
+ * padded to a multiple of 4), LOSS_ENOMEM, LOSS_EHIP. */
 loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out);
 
 /* Free every resource of the handle (NULL is accepted). */

@@ -42,21 +42,28 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
 {
     const AxisDev &ax = a.ax;
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
+    const int lg = __builtin_ctz((unsigned)G);   // G is a power of two
     const int k = lane & (G - 1);
-    const int grp = lane / G;
-    const int upw = 64 / G;
-    int unit = (blockIdx.x * (blockDim.x >> 6) + wid) * upw + grp;
-    const bool uact = unit < nunits;
-    if (!uact) unit = nunits - 1;
+    const int upw = 64 >> lg;                     // units per wave
     const int N = ax.N, M = ax.M, p = ax.p;
-    const int line = unit / p;
-    const int l = unit - line * p;
-    const int lps = a.nz * a.ny;                 // lines per shot
-    const int shot = line / lps;
-    const int64_t base = (int64_t)line * a.pitch;
-    const int64_t mbase = (int64_t)(line - shot * lps) * a.pitch;
+    const int lps = a.nz * a.ny;                  // lines per shot
+    // the wave's first unit, its line and shot (wave-uniform: scalar divisions)
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int u0 = (blockIdx.x * (blockDim.x >> 6) + wid) * upw;
     if (a.step_inc && blockIdx.x == 0 && threadIdx.x == 0) *a.step_inc += 1;
+    if (u0 >= nunits) return;                     // the whole wave is past the last unit
+    const int line0 = u0 / p;
+    const int shot0 = line0 / lps;
+    const int rl0 = line0 - shot0 * lps;
+    // this lane's unit (lanes past the last unit repeat it): patch l of line line0 + dl
+    const bool uact = (lane >> lg) < nunits - u0;
+    int l = u0 - line0 * p + min(lane >> lg, nunits - 1 - u0), dl = 0;
+    while (l >= p) { l -= p; ++dl; }
+    int rl = rl0 + dl, shot = shot0;              // line within its shot
+    while (rl >= lps) { rl -= lps; ++shot; }
+    const int pitch = (int)a.pitch;
+    const int64_t base = (int64_t)line0 * a.pitch + dl * pitch;   // scalar part + 32-bit lane part
+    const int64_t mbase = rl * pitch;
     const int s = l * M;
     const int e = min(s + M, N);
     const int q = s + k * C;
@@ -73,19 +80,23 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
             for (int g4 = 0; g4 < C / 4; ++g4) pre[g4] = pre_load4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4);
         }
         if (a.src) {
-            const int r = line - shot * lps;
-            rowz = r / a.ny;
-            rowy = r - rowz * a.ny;
+            // (y, z) of the line from those of the wave's first line (scalar division)
+            const int rz0 = rl0 / a.ny;
+            rowz = rz0;
+            rowy = rl0 - rz0 * a.ny + dl;
+            if (shot != shot0) { rowz = 0; rowy = rl; }
+            while (rowy >= a.ny) { rowy -= a.ny; ++rowz; }
             srcs = segment_has_source(a, shot, 0, 0, rowy, rowz, q, min(q + C, N));
         }
     };
     float w[C];
-    const float *__restrict__ icf = a.in_coef ? a.in_coef + mbase : nullptr;
+    const bool has_icf = a.in_coef != nullptr;    // uniform
+    const float *__restrict__ icf = a.in_coef + mbase;
     float we = x_unit<C, SOLVE>(
-        ax, k, G, l, true, [&](int i) { return icf ? in[i] * icf[i] : in[i]; },
+        ax, k, G, l, true, [&](int i) { return has_icf ? in[i] * icf[i] : in[i]; },
         [&](int i) {
             float4 v = ld4(in + i);
-            if (icf) {
+            if (has_icf) {
                 const float4 c = ld4(icf + i);
                 v = make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
             }
@@ -285,8 +296,15 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
     const int stride = (axis == 1) ? pitch : (int)a.plane;
     const int mbase = ((axis == 1) ? o * (int)a.plane : o * pitch) + min(col, a.nx - 1);
     const int64_t sbase = (int64_t)shot * a.shot_stride;   // start of the shot's field
-    const float *__restrict__ in = a.in + sbase;
     if (a.step_inc && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.step_inc += 1;
+    // WIDE: the array pointers move to the lane's column once, so that the node indices
+    // below are row offsets, wave-uniform (scalar), and every access costs one address
+    // add; otherwise the indices carry the column (fo: fields, mo: media)
+    const LineArgs la = WIDE ? lane_args(a, sbase + mbase, mbase, shot) : a;
+    const int64_t fo = WIDE ? 0 : sbase + mbase;
+    const int64_t mo = WIDE ? 0 : mbase;
+    const float *__restrict__ in = la.in;
+    const float *__restrict__ icf = la.in_coef;
     const int N = ax.N, M = ax.M;
     const int s = l * M;
     const int e = min(s + M, N);
@@ -296,8 +314,8 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
     float u[C + 2];
 #pragma unroll
     for (int c = 0; c < C + 2; ++c) {
-        const int off = mbase + clampi(q - 1 + c, 0, N) * stride;
-        u[c] = a.in_coef ? in[off] * a.in_coef[off] : in[off];
+        const int r = clampi(q - 1 + c, 0, N) * stride;
+        u[c] = a.in_coef ? in[fo + r] * icf[mo + r] : in[fo + r];
     }
     const int4 rinfo = (a.rcol && cact) ? a.rcol[fcol] : make_int4(0, 0, 0, -1);
     float fm[C], fi[C], fs[C];
@@ -315,8 +333,8 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
             const int t = min(chunk + h * T, nt - 1);
             tcs[h] = ax.tap_c[max(ss, 0) * nt + t];
             tce[h] = ax.tap_c[max(se, 0) * nt + t];
-            tvs[h] = in[mbase + tap_node(ax, s, t) * stride];
-            tve[h] = in[mbase + tap_node(ax, e, t) * stride];
+            tvs[h] = in[fo + tap_node(ax, s, t) * stride];
+            tve[h] = in[fo + tap_node(ax, e, t) * stride];
         }
     }
     // epilogue operands (small chunks only: they cost 3 registers per node)
@@ -325,8 +343,8 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
     if constexpr (kPre) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int off = mbase + min(q + c, N) * stride;
-            pre[c] = pre_load<EPI>(a, sbase + off, off);
+            const int r = min(q + c, N) * stride;
+            pre[c] = pre_load<EPI>(la, fo + r, mo + r);
         }
     }
     float ps = 0.f, pe = 0.f;
@@ -339,8 +357,8 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
                 if (se >= 0 && ok) pe = fmaf(tce[h], tve[h], pe);
             }
             for (int t = chunk + kTapsPerChunk * T; t < nt; t += T) {   // wide halos
-                if (ss >= 0) ps = fmaf(ax.tap_c[ss * nt + t], in[mbase + tap_node(ax, s, t) * stride], ps);
-                if (se >= 0) pe = fmaf(ax.tap_c[se * nt + t], in[mbase + tap_node(ax, e, t) * stride], pe);
+                if (ss >= 0) ps = fmaf(ax.tap_c[ss * nt + t], in[fo + tap_node(ax, s, t) * stride], ps);
+                if (se >= 0) pe = fmaf(ax.tap_c[se * nt + t], in[fo + tap_node(ax, e, t) * stride], pe);
             }
         }
     }
@@ -417,7 +435,7 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
 
     if (cact) {
         if (a.pml_mem)
-            pml_run<C>(ax, a.pml_tab, a.pml_mem, a.pml_store, q, e, sbase + mbase + (int64_t)q * stride, stride, y);
+            pml_run<C>(ax, a.pml_tab, la.pml_mem, a.pml_store, q, e, fo + (int64_t)q * stride, stride, y);
         const int cy = axis == 1 ? 0 : o, cz = axis == 1 ? o : 0;
         const bool srcs = a.src && segment_has_source(a, shot, axis, col, cy, cz, q, min(q + C, N));
         // receivers of this column among the rows this lane updates: trace sample n
@@ -430,23 +448,23 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
         for (int c = 0; c < C; ++c) {
             const int i = q + c;
             if (i < e) {
-                const int off = mbase + i * stride;
+                const int r = i * stride;
                 const float D = y[c];
                 float v;
                 if constexpr (kPre)
-                    v = epilogue_pre<EPI>(a, sbase + off, off, shot, D, pre[c], col, axis == 1 ? i : cy,
+                    v = epilogue_pre<EPI>(la, fo + r, mo + r, shot, D, pre[c], col, axis == 1 ? i : cy,
                                           axis == 1 ? cz : i, srcs);
                 else
-                    v = epilogue<EPI>(a, sbase + off, off, shot, D, col, axis == 1 ? i : cy, axis == 1 ? cz : i,
+                    v = epilogue<EPI>(la, fo + r, mo + r, shot, D, col, axis == 1 ? i : cy, axis == 1 ? cz : i,
                                       srcs);
                 if (n >= 0 && i >= rinfo.z && i <= rinfo.w) record_row(a, rinfo, i, v, n);
             }
         }
         if (e == N && chunk == kc) {
-            const int off = mbase + N * stride;
+            const int r = N * stride;
             float D = we;
-            if (a.pml_mem && in_pml(ax, N)) D = pml_adjust(a.pml_tab, a.pml_mem, a.pml_store, N, sbase + off, D);
-            const float v = epilogue<EPI>(a, sbase + off, off, shot, D, col, axis == 1 ? N : cy,
+            if (a.pml_mem && in_pml(ax, N)) D = pml_adjust(a.pml_tab, la.pml_mem, a.pml_store, N, fo + r, D);
+            const float v = epilogue<EPI>(la, fo + r, mo + r, shot, D, col, axis == 1 ? N : cy,
                                           axis == 1 ? cz : N, srcs);
             if (rinfo.y > 0 && rinfo.w == N) {
                 const int64_t nn = *a.d_step - 1;
@@ -1021,7 +1039,7 @@ hipError_t dispatch_s(int axis, int epi, const LineArgs &a, hipStream_t st)
     dim3 grid((unsigned)gxp, a.ax.p, 1);
     const int threads = 64 * W;
     const size_t shm = (6 * (size_t)threads + 64) * sizeof(float);
-    if constexpr (C != 8) {
+    {
         if (CW == 64) {
             switch (epi) {
             case EPI_STORE: hipLaunchKernelGGL((k_line_s<C, SOLVE, EPI_STORE, true>), grid, threads, shm, st, a, axis, CW, gx); break;

@@ -8,6 +8,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "loss_internal.h"
 
 namespace loss {
@@ -91,7 +93,9 @@ __device__ __forceinline__ float epilogue(const LineArgs &a, int64_t oidx, int64
         return D;
     } else if constexpr (EPI == EPI_AXPY) {
         float v0 = 0.f;
-        for (int j = 0; j < a.nout; ++j) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {   // static indices: the pointers may live in registers
+            if (j >= a.nout) break;
             const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
             float v = fmaf(a.alpha * c, D, a.out[j][oidx]);
             if (srcs && a.src) v += source_terms(a, j, shot, x, y, z, midx);
@@ -153,7 +157,9 @@ __device__ __forceinline__ float epilogue_pre(const LineArgs &a, int64_t oidx, i
     float v = D;
     if constexpr (EPI == EPI_AXPY) {
         v = fmaf(a.alpha * pr.c, D, pr.o);
-        for (int j = 1; j < a.nout; ++j) {
+#pragma unroll
+        for (int j = 1; j < 3; ++j) {
+            if (j >= a.nout) break;
             const float c = a.coef[j] ? a.coef[j][midx] : 1.f;
             a.out[j][oidx] = fmaf(a.alpha * c, D, a.out[j][oidx]);
         }
@@ -166,6 +172,31 @@ __device__ __forceinline__ float epilogue_pre(const LineArgs &a, int64_t oidx, i
     }
     a.out[0][oidx] = v;
     return v;
+}
+
+// The arguments with every array pointer moved to one lane's column: field arrays by
+// `fe` elements (shot and column), media arrays by `me`, the divergence store to the
+// shot's slice; null pointers stay null.  Node indices handed to the epilogue helpers
+// with these arguments are then row offsets alone, the same for every lane of a wave
+// whose lanes share their rows.
+__device__ __forceinline__ LineArgs lane_args(const LineArgs &a, int64_t fe, int64_t me, int shot)
+{
+    LineArgs r = a;
+    auto mv = [](auto *p, int64_t o) { return p ? p + o : p; };
+    r.in = a.in + fe;
+    r.in_coef = mv(a.in_coef, me);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        r.out[j] = mv(a.out[j], fe);
+        r.coef[j] = mv(a.coef[j], me);
+    }
+    r.aux = mv(a.aux, fe);
+    r.aux2 = mv(a.aux2, fe);
+    r.div = mv(a.div, (int64_t)shot * a.div_shot_stride + me);
+    r.div_shot_stride = 0;
+    r.bcoef = mv(a.bcoef, me);
+    r.pml_mem = mv(a.pml_mem, fe);
+    return r;
 }
 
 // Trace samples of the receivers at row `r` of a strided column ({first, count} in ri).
@@ -407,6 +438,41 @@ __device__ __forceinline__ void pml_run(const AxisDev &ax, const float4 *__restr
 // x axis (contiguous): G lanes per unit, C nodes per lane, 64/G units per wave.
 // ---------------------------------------------------------------------------
 
+// Lane exchanges inside the G lanes of a unit (G a power of two, units aligned to
+// multiples of G).  When G <= 16 a unit lies inside one 16-lane DPP row and a shift by
+// d is one row_shr / row_shl move (lane i of the row receives lane i - d, resp. i + d;
+// sources outside the row give 0); wider units take the LDS permute.  Values that a
+// shift brings in from outside the unit are for the caller to discard.
+template <int D>
+__device__ __forceinline__ float row_shift_up(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xF, 0xF, true));
+}
+template <int D>
+__device__ __forceinline__ float row_shift_down(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + D, 0xF, 0xF, true));
+}
+struct UnitLanes {
+    int G;
+    template <int D>
+    __device__ __forceinline__ float up(float v) const
+    {
+        if constexpr (D < 16) {
+            if (G <= 16) return row_shift_up<D>(v);
+        }
+        return __shfl_up(v, D, G);
+    }
+    template <int D>
+    __device__ __forceinline__ float down(float v) const
+    {
+        if constexpr (D < 16) {
+            if (G <= 16) return row_shift_down<D>(v);
+        }
+        return __shfl_down(v, D, G);
+    }
+};
+
 // Solve of one unit (patch l) of an x line by its G lanes (lane k owns nodes
 // q = s + kC .. q + C - 1).  `val(i)` reads node i of the line and `val4(i)` nodes
 // i..i+3 (i 16-byte aligned, i + 3 <= N; used when `vec_in`).  `issue()` runs once
@@ -421,6 +487,7 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
     const int s = l * M;
     const int e = min(s + M, N);
     const int q = s + k * C;
+    const UnitLanes lanes{G};
 
     // ---- loads -------------------------------------------------------------
     // chunk values u[1..C] = nodes q..q+C-1; u[0], u[C+1] = the neighbouring lanes'
@@ -436,7 +503,8 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
 #pragma unroll
         for (int c = 1; c <= C; ++c) u[c] = val(min(q - 1 + c, N));
     }
-    const float uright = val(min(q + C, N));   // kept by the unit's last lane
+    float uright = 0.f;   // the node past the unit's last chunk, read by its last lane
+    if (k == G - 1) uright = val(min(q + C, N));
     float fm[C], fi[C], fs[C];
     row_factors<C, SOLVE>(ax, q, fm, fi, fs);
     const EndRows er = end_rows<SOLVE>(ax, s, e);
@@ -474,16 +542,26 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
 
     // ---- solve -------------------------------------------------------------
     {
-        const float left = __shfl_up(u[C], 1, G);
-        const float right = __shfl_down(u[1], 1, G);
+        const float left = lanes.up<1>(u[C]);
+        const float right = lanes.down<1>(u[1]);
         u[0] = (k == 0) ? u[1] : left;   // row s never uses node s-1
         u[C + 1] = (k == G - 1) ? uright : right;
     }
     if constexpr (SOLVE != SOLVE_T1) {
-        for (int d = G >> 1; d > 0; d >>= 1) {
-            phs += __shfl_xor(phs, d, G);
-            phe += __shfl_xor(phe, d, G);
-        }
+        // suffix sums over the unit's lanes: lane 0 ends with both junction sums
+        auto suffix = [&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            if (D < G) {
+                const float a = lanes.down<D>(phs), b = lanes.down<D>(phe);
+                if (k + D < G) { phs += a; phe += b; }
+            }
+        };
+        suffix(std::integral_constant<int, 1>{});
+        suffix(std::integral_constant<int, 2>{});
+        suffix(std::integral_constant<int, 4>{});
+        suffix(std::integral_constant<int, 8>{});
+        suffix(std::integral_constant<int, 16>{});
+        suffix(std::integral_constant<int, 32>{});
     }
 
     // forward elimination over the chunk from a zero carry
@@ -505,18 +583,28 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
     const int reach = ax.reach;
     float A = pv, B = yv;
     if (k == 0) { B = fmaf(A, phs, B); A = 0.f; }
-    for (int d = 1; d < G && d * C < reach; d <<= 1) {
-        const float Ap = __shfl_up(A, d, G), Bp = __shfl_up(B, d, G);
-        if (k >= d) { B = fmaf(A, Bp, B); A = A * Ap; }
-    }
-    float yin = __shfl_up(B, 1, G);
+    auto scan_up = [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if (D < G && D * C < reach) {
+            const float Ap = lanes.up<D>(A), Bp = lanes.up<D>(B);
+            if (k >= D) { B = fmaf(A, Bp, B); A = A * Ap; }
+        }
+    };
+    scan_up(std::integral_constant<int, 1>{});
+    scan_up(std::integral_constant<int, 2>{});
+    scan_up(std::integral_constant<int, 4>{});
+    scan_up(std::integral_constant<int, 8>{});
+    scan_up(std::integral_constant<int, 16>{});
+    scan_up(std::integral_constant<int, 32>{});
+    float yin = lanes.up<1>(B);
     if (k == 0) yin = phs;
 #pragma unroll
     for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
 
-    // closing row
+    // closing row (its junction sum comes from lane 0)
     const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
     float we = 0.f;
+    if constexpr (SOLVE != SOLVE_T1) phe = __shfl(phe, 0, G);
     if (k == kc) {
         float ylast = 0.f, ulast = 0.f, ue = 0.f;
 #pragma unroll
@@ -539,11 +627,20 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
         Q[c] = qv;
     }
     float Qm = qv, Wm = wv;
-    for (int d = 1; d < G && d * C < reach; d <<= 1) {
-        const float Qn = __shfl_down(Qm, d, G), Wn = __shfl_down(Wm, d, G);
-        if (k + d < G) { Wm = fmaf(Qm, Wn, Wm); Qm = Qm * Qn; }
-    }
-    float Qx = __shfl_down(Qm, 1, G), Wx = __shfl_down(Wm, 1, G);
+    auto scan_down = [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if (D < G && D * C < reach) {
+            const float Qn = lanes.down<D>(Qm), Wn = lanes.down<D>(Wm);
+            if (k + D < G) { Wm = fmaf(Qm, Wn, Wm); Qm = Qm * Qn; }
+        }
+    };
+    scan_down(std::integral_constant<int, 1>{});
+    scan_down(std::integral_constant<int, 2>{});
+    scan_down(std::integral_constant<int, 4>{});
+    scan_down(std::integral_constant<int, 8>{});
+    scan_down(std::integral_constant<int, 16>{});
+    scan_down(std::integral_constant<int, 32>{});
+    float Qx = lanes.down<1>(Qm), Wx = lanes.down<1>(Wm);
     if (k == G - 1) { Qx = 1.f; Wx = 0.f; }
     // lanes past the closing row hold identity maps, so the closing value enters
     // exactly where the window reaches it (elsewhere its factor is below the tolerance)

@@ -1454,6 +1454,11 @@ loss_status loss_create(const loss_desc *desc, void *hip_stream, loss_sim **out)
     s->plane = s->pitch * s->ny;
     s->shot_stride = s->plane * s->nz;
     s->nodes = (int64_t)s->nx * s->ny * s->nz;
+    // the line kernels index within one shot's field in 32-bit arithmetic
+    if (s->shot_stride >= (int64_t(1) << 31)) {
+        loss_destroy(s);
+        return fail(LOSS_EUNSUPPORTED, "a field of one shot holds 2^31 or more elements (padded)");
+    }
     auto bail = [&](loss_status st) { loss_destroy(s); return st; };
     for (int a = 0; a < 3; ++a) {
         if (a == 1 && d.ndim == 2) continue;
@@ -1898,7 +1903,7 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
         // candidates: x -> nodes per lane; y, z -> (columns per wave, nodes per lane)
         std::vector<std::pair<int, int>> cands;
         if (axis == 0) cands = {{4, 0}, {8, 0}, {16, 0}};
-        else cands = {{64, 16}, {32, 16}, {16, 16}, {32, 8}, {16, 8}};
+        else cands = {{64, 8}, {64, 16}, {32, 16}, {16, 16}, {32, 8}, {16, 8}};
         best = 1e30f;
         std::pair<int, int> bestc = cands[0];
         for (const auto &cd : cands) {

@@ -94,6 +94,21 @@ def test_create_rejects_bad_descriptions(kw, needle):
     assert not h.value
 
 
+def test_create_refuses_fields_past_32bit_indexing():
+    """A per-shot field of 2^31 or more (padded) elements is refused with
+    LOSS_EUNSUPPORTED before any device call (the line kernels index within a shot's
+    field in 32-bit arithmetic)."""
+    import ctypes as C
+    from paper_2301_05127_amd import loss
+    L = loss.lib()
+    h = C.c_void_p()
+    # 1292 x 1291 x 1291 padded nodes = 2.15e9 elements
+    d = _desc(physics=1, ndim=3, n=(1290, 1290, 1290), patch=(64, 64, 64))
+    assert L.loss_create(C.byref(d), None, C.byref(h)) == -5, L.loss_last_error()
+    assert b"2^31" in L.loss_last_error()
+    assert not h.value
+
+
 def test_null_arguments():
     import ctypes as C
     from paper_2301_05127_amd import loss
