@@ -10,10 +10,17 @@ which hold none of the method's arithmetic).  Usage:
   nine fields on the lattice of every 16th node of each axis.
 * ``cfg4`` (513^3 layered medium, explosive shot): every receiver trace over 100 steps
   and all nine fields at step 100 on the lattice of every 32nd node.
+* ``cfg3_pml``: the 257^3 workload with the absorbing layer (Sec. 3.3) on every side,
+  20 nodes wide, R = 1e-6, k_max = 1, alpha from the 15 Hz source frequency: 1000 steps,
+  lattice of every 16th node at steps 400 and 1000.  With natural ends alone, FP32-sized
+  perturbations grow exponentially at the grid corners of a 3-D elastic run (the FP64
+  oracle fed such noise diverges like the GPU), so long runs take the layer, as the
+  paper pairs natural ends with it.
 
 The oracle runs on the inputs the GPU receives: media and wavelets rounded to float32.
 Output: ``tests/golden/<cfg>_oracle.npz`` (float64 arrays ``traces_s<shot>`` [rec][t],
-``fields_s<shot>_n<step>`` [field][z][y][x] on the lattice, ``stride``, ``steps``).
+``fields_s<shot>_n<step>`` [field][z][y][x] on the lattice, ``stride``, ``steps``,
+``shots_done``; the file is rewritten after each shot).
 """
 from __future__ import annotations
 
@@ -31,7 +38,9 @@ import oracle  # noqa: E402
 from paper_2301_05127_amd import inputs  # noqa: E402
 
 PLAN = {"cfg3": dict(steps=1000, snapshots=(400, 1000), stride=16),
-        "cfg4": dict(steps=100, snapshots=(100,), stride=32)}
+        "cfg4": dict(steps=100, snapshots=(100,), stride=32),
+        "cfg3_pml": dict(base="cfg3", steps=1000, snapshots=(400, 1000), stride=16,
+                         pml=dict(width=20, R=1e-6, kmax=1.0, f0=15.0))}
 
 
 def f32_inputs(w):
@@ -45,27 +54,39 @@ def f32_inputs(w):
 
 def make(name):
     plan = PLAN[name]
-    w = f32_inputs(inputs.config(name, nsteps=plan["steps"]))
+    w = f32_inputs(inputs.config(plan.get("base", name), nsteps=plan["steps"]))
     st = plan["stride"]
+    pml = plan.get("pml")
+    if pml is not None:
+        pml = dict(pml, cmax=float(np.max(w["vp"])))
     out = {"stride": np.int64(st), "steps": np.int64(plan["steps"]),
            "snapshots": np.array(plan["snapshots"], np.int64)}
+    if pml is not None:
+        out["pml"] = np.array([pml["width"], pml["R"], pml["kmax"], pml["f0"]], np.float64)
+    path = os.path.join(HERE, "%s_oracle.npz" % name)
     for shot, sh in enumerate(w["shots"]):
         fields, done, traces = None, 0, []
         for snap in plan["snapshots"]:
             t0 = time.time()
-            fields, tr = oracle.run(w["grid"], 1, w["dt"], snap - done, w["vp"], w["rho"], vs=w["vs"],
-                                    sources=sh["sources"], receivers=sh["receivers"],
-                                    rec_comp=sh.get("rec_comp", 0), fields_in=fields, step0=done)
+            if pml is None:
+                fields, tr = oracle.run(w["grid"], 1, w["dt"], snap - done, w["vp"], w["rho"], vs=w["vs"],
+                                        sources=sh["sources"], receivers=sh["receivers"],
+                                        rec_comp=sh.get("rec_comp", 0), fields_in=fields, step0=done)
+            else:
+                fields, tr = oracle.run_pml_elastic(w["grid"], pml, w["dt"], snap - done, w["vp"], w["vs"],
+                                                    w["rho"], sources=sh["sources"], receivers=sh["receivers"],
+                                                    rec_comp=sh.get("rec_comp", 0), fields_in=fields, step0=done)
             traces.append(tr)
             done = snap
-            out["fields_s%d_n%d" % (shot, snap)] = np.ascontiguousarray(fields[:, ::st, ::st, ::st])
+            out["fields_s%d_n%d" % (shot, snap)] = np.ascontiguousarray(fields[:9, ::st, ::st, ::st])
             print("%s shot %d: step %d (%.0f s)" % (name, shot, snap, time.time() - t0), flush=True)
         out["traces_s%d" % shot] = np.concatenate(traces, axis=1)
-    path = os.path.join(HERE, "%s_oracle.npz" % name)
-    np.savez_compressed(path, **out)
-    print("wrote", path, os.path.getsize(path), "bytes", flush=True)
+        out["shots_done"] = np.int64(shot + 1)
+        np.savez_compressed(path + ".tmp.npz", **out)
+        os.replace(path + ".tmp.npz", path)
+        print("wrote", path, os.path.getsize(path), "bytes", flush=True)
 
 
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["cfg3", "cfg4"]:
+    for name in sys.argv[1:] or ["cfg3", "cfg4", "cfg3_pml"]:
         make(name)
