@@ -124,6 +124,8 @@ def _load(path):
         "or_elastic_adjoint": (c_int, [G, c_double, c_int, D, D, D, c_int, S, c_int, I, c_int, D, D, D, D]),
         "or_run_pml_elastic": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, c_int, D, D, D, c_int, S,
                                        c_int, I, c_int, D, D, D]),
+        "or_elastic_adjoint_pml": (c_int, [G, ctypes.POINTER(_Pml), c_double, c_int, D, D, D, c_int, S, c_int, I,
+                                           c_int, D, D, D, D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -373,6 +375,27 @@ def elastic_adjoint(g, dt, nsteps, vp, vs, rho, sources, receivers, rec_comp, re
                                   _dp(gm), _dp(gb))
     if rc != 0:
         raise ValueError("oracle or_elastic_adjoint rejected its arguments (rc=%d)" % rc)
+    return (gl, gm, gb) if with_b else (gl, gm)
+
+
+def elastic_adjoint_pml(g, pml, dt, nsteps, vp, vs, rho, sources, receivers, rec_comp, residual, with_b=False):
+    """Gradients (dJ/dlambda, dJ/dmu[, dJ/db]) of a run with the ADE-PML layer on every
+    axis (pml: dict(width, R, kmax, f0, cmax)) for J = 1/2 sum residual^2 of the traces of
+    field rec_comp (the transpose of run_pml_elastic's sequence, Sec. 3.3)."""
+    shape = field_shape(g)
+    vp, vs, rho = _f64(vp), _f64(vs), _f64(rho)
+    src, keep = _sources(list(sources))
+    rec = np.ascontiguousarray(receivers, dtype=np.int32)
+    res = _f64(residual)
+    gl, gm = np.zeros(shape), np.zeros(shape)
+    gb = np.zeros(shape) if with_b else None
+    p = _Pml(int(pml["width"]), float(pml["R"]), float(pml["kmax"]), float(pml["f0"]), float(pml["cmax"]))
+    gs = _grid(g)
+    rc = lib().or_elastic_adjoint_pml(ctypes.byref(gs), ctypes.byref(p), float(dt), int(nsteps), _dp(vp), _dp(vs),
+                                      _dp(rho), len(keep), src, rec.shape[0], _ip(rec), int(rec_comp), _dp(res),
+                                      _dp(gl), _dp(gm), _dp(gb))
+    if rc != 0:
+        raise ValueError("oracle or_elastic_adjoint_pml rejected its arguments (rc=%d)" % rc)
     return (gl, gm, gb) if with_b else (gl, gm)
 
 

@@ -1363,3 +1363,229 @@ int or_acoustic_adjoint_pml(const or_grid *g, const or_pml *pml, double dt, int 
     for (k = 0; k < 2; ++k) { free(Dm[k]); free(Lh[k].Ep); free(Lf[k].Ep); }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of the elastic 3-D scheme with the absorbing layer       */
+/* ------------------------------------------------------------------------ */
+/* The canonical sequence of or_run_pml_elastic written through the flows' linear forms
+ * (flow_lin: with L = the form of the pass's axis and time span, the pass maps
+ * (D, psi) to psi' = Ep psi + Dp D and the drive Dv D + Pv psi):
+ *   A(dt/2): v_i += -b (Dv D_j sigma_ij + Pv psi_ij) for every j, psi_ij advanced (+ forces);
+ *   B(dt):   e_ij = -(Dv D_j v_i + Pv phi_ij) (stretched increments, dt included),
+ *            phi_ij advanced; sigma_kk += lambda tr(e) + 2 mu e_kk,
+ *            sigma_ij += mu (e_ij + e_ji) (i < j).
+ * Transposes, given the field bars and the memory-variable bars (of psi', phi'):
+ *   A: for each pass, t = -b v_i-bar; D-bar = Dv t + Dp psi-bar, psi-bar <- Pv t + Ep psi-bar,
+ *      sigma_ij-bar += D_j^T D-bar;
+ *   B: e-bar_kk = lambda S + 2 mu sigma_kk-bar (S the sum of the normal bars),
+ *      e-bar_ij = e-bar_ji = mu sigma_ij-bar; t = -e-bar_ij; D-bar = Dv t + Dp phi-bar,
+ *      phi-bar <- Pv t + Ep phi-bar, v_i-bar += D_j^T D-bar.
+ * Gradients as in or_elastic_adjoint with the stretched increments: dJ/dlambda += tr(e) S,
+ * dJ/dmu += 2 sum_k e_kk sigma_kk-bar + sum_{i<j} (e_ij + e_ji) sigma_ij-bar, and
+ * dJ/db += the drive of each velocity half step (-(Dv D + Pv psi) summed over j, plus
+ * (dt/2) f_i W) times v_i-bar. */
+int or_elastic_adjoint_pml(const or_grid *g, const or_pml *pml, double dt, int nsteps,
+                           const double *vp, const double *vs, const double *rho,
+                           int nsrc, const or_source *src,
+                           int nrec, const int *rec_idx, int rec_comp,
+                           const double *res, double *grad_lam, double *grad_mu, double *grad_b)
+{
+    static const int sig_of[3][3] = {{OR_E_S11, OR_E_S12, OR_E_S13},
+                                     {OR_E_S12, OR_E_S22, OR_E_S23},
+                                     {OR_E_S13, OR_E_S23, OR_E_S33}};
+    static const int shear[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    long nn[3], tot, i;
+    int n, r, k, a, ci, cj, half;
+    double *Dm[3];
+    dense_ctx dc[3];
+    flow_lin Lh[3], Lf[3];        /* tau = dt/2 (velocity half steps), dt (stress), per axis */
+    double *F, *Fb, *psi, *phi, *bpsi, *bphi, *lam, *mu, *b, *t0, *t1, *strain, *drive, **W;
+    if (check_grid(g, OR_ELASTIC) || rec_comp < 0 || rec_comp >= 9) return -1;
+    for (a = 0; a < 3; ++a)
+        if (pml->width < 1 || pml->width > g->n[a] / 2) return -1;
+    if (!(pml->R > 0.0 && pml->R < 1.0) || pml->kmax < 1.0 || pml->f0 <= 0.0) return -1;
+    grid_nodes(g, nn);
+    tot = grid_total(g);
+    for (a = 0; a < 3; ++a) {
+        int N = g->n[a];
+        Dm[a] = (double *)malloc(sizeof(double) * (size_t)(N + 1) * (N + 1));
+        or_line_deriv_matrix(N, g->h[a], g->M[a], g->halo, g->end_mode, Dm[a]);
+        dc[a].D = Dm[a]; dc[a].n = N + 1; dc[a].transpose = 0;
+        flow_lin_build(pml, g, a, 0.5 * dt, &Lh[a]);
+        flow_lin_build(pml, g, a, dt, &Lf[a]);
+    }
+    F = (double *)calloc((size_t)tot * 59, sizeof(double));
+    Fb = F + (size_t)9 * tot;
+    psi = Fb + (size_t)9 * tot; phi = psi + (size_t)9 * tot;
+    bpsi = phi + (size_t)9 * tot; bphi = bpsi + (size_t)9 * tot;
+    lam = bphi + (size_t)9 * tot; mu = lam + tot; b = mu + tot; t0 = b + tot; t1 = t0 + tot;
+    /* per step: the stretched e_11, e_22, e_33, e_12 + e_21, e_13 + e_31, e_23 + e_32;
+     * per velocity half step (2n + h): each component's drive, what b multiplies */
+    strain = (double *)malloc(sizeof(double) * (size_t)tot * 6 * nsteps);
+    drive = (double *)calloc((size_t)tot * 3 * 2 * nsteps, sizeof(double));
+    if (!F || !strain || !drive) { free(strain); free(drive); free(F); return -2; }
+    for (i = 0; i < tot; ++i) {
+        b[i] = 1.0 / rho[i];
+        mu[i] = rho[i] * vs[i] * vs[i];
+        lam[i] = rho[i] * vp[i] * vp[i] - 2.0 * mu[i];
+    }
+    W = (double **)malloc(sizeof(double *) * (nsrc > 0 ? nsrc : 1));
+    for (k = 0; k < nsrc; ++k) {
+        W[k] = (double *)malloc(sizeof(double) * tot);
+        or_source_weights(g, src[k].pos, src[k].spread, W[k]);
+    }
+    for (n = 0; n < nsteps; ++n) {
+        for (half = 0; half < 2; ++half) {
+            long fk = half == 0 ? n : n + 1;
+            double *dr = drive + (size_t)(2 * n + half) * 3 * tot;
+            for (ci = 0; ci < 3; ++ci)
+                for (cj = 0; cj < 3; ++cj) {
+                    const flow_lin *L = &Lh[cj];
+                    double *m = psi + (size_t)(3 * ci + cj) * tot;
+                    apply_lines(g, cj, F + (size_t)sig_of[ci][cj] * tot, t0, dense_op, &dc[cj], 0);
+                    for (i = 0; i < tot; ++i) {
+                        const long c[3] = {i % nn[0], i / nn[0] % nn[1], i / (nn[0] * nn[1])};
+                        const long jj = c[cj];
+                        const double m0 = m[i], inc = -(L->Dv[jj] * t0[i] + L->Pv[jj] * m0);
+                        m[i] = L->Ep[jj] * m0 + L->Dp[jj] * t0[i];
+                        F[(size_t)(OR_E_V1 + ci) * tot + i] += b[i] * inc;
+                        dr[(size_t)ci * tot + i] += inc;
+                    }
+                }
+            for (k = 0; k < nsrc; ++k) {
+                int fld = src[k].kind == OR_SRC_FORCE_X ? OR_E_V1
+                        : src[k].kind == OR_SRC_FORCE_Y ? OR_E_V2
+                        : src[k].kind == OR_SRC_FORCE_Z ? OR_E_V3 : -1;
+                double sv = sample(&src[k], fk);
+                if (fld < 0) continue;
+                for (i = 0; i < tot; ++i) {
+                    F[(size_t)fld * tot + i] += 0.5 * dt * b[i] * sv * W[k][i];
+                    dr[(size_t)(fld - OR_E_V1) * tot + i] += 0.5 * dt * sv * W[k][i];
+                }
+            }
+            if (half == 1) break;
+            {
+                double *e = strain + (size_t)n * 6 * tot;
+                double *inc = (double *)malloc(sizeof(double) * (size_t)tot * 9);
+                int q;
+                for (q = 0; q < 9; ++q) {
+                    const int vi = q / 3, j = q % 3;
+                    const flow_lin *L = &Lf[j];
+                    double *m = phi + (size_t)q * tot;
+                    apply_lines(g, j, F + (size_t)(OR_E_V1 + vi) * tot, t0, dense_op, &dc[j], 0);
+                    for (i = 0; i < tot; ++i) {
+                        const long c[3] = {i % nn[0], i / nn[0] % nn[1], i / (nn[0] * nn[1])};
+                        const long jj = c[j];
+                        const double m0 = m[i];
+                        inc[(size_t)q * tot + i] = -(L->Dv[jj] * t0[i] + L->Pv[jj] * m0);
+                        m[i] = L->Ep[jj] * m0 + L->Dp[jj] * t0[i];
+                    }
+                }
+                for (i = 0; i < tot; ++i) {
+                    double tr;
+                    e[i] = inc[i];
+                    e[tot + i] = inc[4 * (size_t)tot + i];
+                    e[2 * (size_t)tot + i] = inc[8 * (size_t)tot + i];
+                    e[3 * (size_t)tot + i] = inc[1 * (size_t)tot + i] + inc[3 * (size_t)tot + i];
+                    e[4 * (size_t)tot + i] = inc[2 * (size_t)tot + i] + inc[6 * (size_t)tot + i];
+                    e[5 * (size_t)tot + i] = inc[5 * (size_t)tot + i] + inc[7 * (size_t)tot + i];
+                    tr = e[i] + e[tot + i] + e[2 * (size_t)tot + i];
+                    for (k = 0; k < 3; ++k)
+                        F[(size_t)(OR_E_S11 + k) * tot + i] += lam[i] * tr + 2.0 * mu[i] * e[(size_t)k * tot + i];
+                    F[(size_t)OR_E_S12 * tot + i] += mu[i] * e[3 * (size_t)tot + i];
+                    F[(size_t)OR_E_S13 * tot + i] += mu[i] * e[4 * (size_t)tot + i];
+                    F[(size_t)OR_E_S23 * tot + i] += mu[i] * e[5 * (size_t)tot + i];
+                }
+                free(inc);
+            }
+            for (k = 0; k < nsrc; ++k) {
+                double sv = sample(&src[k], n);
+                if (src[k].kind != OR_SRC_PRESSURE && src[k].kind != OR_SRC_EXPLOSIVE) continue;
+                for (i = 0; i < tot; ++i)
+                    for (a = 0; a < 3; ++a) F[(size_t)(OR_E_S11 + a) * tot + i] += dt * sv * W[k][i];
+            }
+        }
+    }
+    /* reverse sweep (bars of the memory variables start at zero with the fields') */
+    for (i = 0; i < tot; ++i) {
+        grad_lam[i] = 0.0;
+        grad_mu[i] = 0.0;
+        if (grad_b) grad_b[i] = 0.0;
+    }
+    dc[0].transpose = dc[1].transpose = dc[2].transpose = 1;
+    for (n = nsteps - 1; n >= 0; --n) {
+        const double *e = strain + (size_t)n * 6 * tot;
+        for (r = 0; r < nrec; ++r) {
+            long ix = rec_idx[3 * r], iy = rec_idx[3 * r + 1], iz = rec_idx[3 * r + 2];
+            Fb[(size_t)rec_comp * tot + (iz * nn[1] + iy) * nn[0] + ix] += res[(size_t)r * nsteps + n];
+        }
+        for (half = 0; half < 2; ++half) {
+            if (grad_b) {
+                const double *dr = drive + (size_t)(2 * n + 1 - half) * 3 * tot;
+                for (ci = 0; ci < 3; ++ci)
+                    for (i = 0; i < tot; ++i)
+                        grad_b[i] += dr[(size_t)ci * tot + i] * Fb[(size_t)(OR_E_V1 + ci) * tot + i];
+            }
+            /* transpose of a velocity half step */
+            for (ci = 0; ci < 3; ++ci)
+                for (cj = 0; cj < 3; ++cj) {
+                    const flow_lin *L = &Lh[cj];
+                    double *mb = bpsi + (size_t)(3 * ci + cj) * tot;
+                    for (i = 0; i < tot; ++i) {
+                        const long c[3] = {i % nn[0], i / nn[0] % nn[1], i / (nn[0] * nn[1])};
+                        const long jj = c[cj];
+                        const double t = -b[i] * Fb[(size_t)(OR_E_V1 + ci) * tot + i], m0 = mb[i];
+                        t1[i] = L->Dv[jj] * t + L->Dp[jj] * m0;
+                        mb[i] = L->Pv[jj] * t + L->Ep[jj] * m0;
+                    }
+                    apply_lines(g, cj, t1, t0, dense_op, &dc[cj], 0);
+                    for (i = 0; i < tot; ++i) Fb[(size_t)sig_of[ci][cj] * tot + i] += t0[i];
+                }
+            if (half == 1) break;
+            /* gradient with the stretched increments, then the transpose of the stress
+             * sub-flow (increment bars from the stress bars, then each pass) */
+            for (i = 0; i < tot; ++i) {
+                double S = Fb[(size_t)OR_E_S11 * tot + i] + Fb[(size_t)OR_E_S22 * tot + i] + Fb[(size_t)OR_E_S33 * tot + i];
+                double tr = e[i] + e[tot + i] + e[2 * (size_t)tot + i], m = 0.0;
+                for (k = 0; k < 3; ++k) m += 2.0 * e[(size_t)k * tot + i] * Fb[(size_t)(OR_E_S11 + k) * tot + i];
+                m += e[3 * (size_t)tot + i] * Fb[(size_t)OR_E_S12 * tot + i] + e[4 * (size_t)tot + i] * Fb[(size_t)OR_E_S13 * tot + i]
+                   + e[5 * (size_t)tot + i] * Fb[(size_t)OR_E_S23 * tot + i];
+                grad_lam[i] += tr * S;
+                grad_mu[i] += m;
+            }
+            {
+                int q;
+                for (q = 0; q < 9; ++q) {
+                    const int vi = q / 3, j = q % 3;
+                    const flow_lin *L = &Lf[j];
+                    double *mb = bphi + (size_t)q * tot;
+                    for (i = 0; i < tot; ++i) {
+                        const long c[3] = {i % nn[0], i / nn[0] % nn[1], i / (nn[0] * nn[1])};
+                        const long jj = c[j];
+                        double eb, t, m0 = mb[i];
+                        if (vi == j) {
+                            double S = Fb[(size_t)OR_E_S11 * tot + i] + Fb[(size_t)OR_E_S22 * tot + i]
+                                     + Fb[(size_t)OR_E_S33 * tot + i];
+                            eb = lam[i] * S + 2.0 * mu[i] * Fb[(size_t)(OR_E_S11 + vi) * tot + i];
+                        } else {
+                            eb = mu[i] * Fb[(size_t)sig_of[vi][j] * tot + i];
+                        }
+                        t = -eb;
+                        t1[i] = L->Dv[jj] * t + L->Dp[jj] * m0;
+                        mb[i] = L->Pv[jj] * t + L->Ep[jj] * m0;
+                    }
+                    apply_lines(g, j, t1, t0, dense_op, &dc[j], 0);
+                    for (i = 0; i < tot; ++i) Fb[(size_t)(OR_E_V1 + vi) * tot + i] += t0[i];
+                }
+            }
+        }
+    }
+    (void)shear;
+    for (k = 0; k < nsrc; ++k) free(W[k]);
+    free(W);
+    free(strain);
+    free(drive);
+    free(F);
+    for (a = 0; a < 3; ++a) { free(Dm[a]); free(Lh[a].Ep); free(Lf[a].Ep); }
+    return 0;
+}

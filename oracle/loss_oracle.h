@@ -184,6 +184,15 @@ int or_elastic_adjoint(const or_grid *g, double dt, int nsteps,
  * sequence, memory variables starting at zero), J = 1/2 sum residual^2: the exact
  * transpose of every sub-flow, each linear in its frozen derivative and memory variable.
  * grad_K: nodes.  Returns 0 on success. */
+/* Elastic Lame-parameter (and optionally buoyancy) gradients with the absorbing layer on
+ * every axis: the transpose of or_run_pml_elastic's sequence, every pass through its
+ * flow's linear form (Sec. 3.3).  grad_b may be NULL. */
+int or_elastic_adjoint_pml(const or_grid *g, const or_pml *pml, double dt, int nsteps,
+                           const double *vp, const double *vs, const double *rho,
+                           int nsrc, const or_source *src,
+                           int nrec, const int *rec_idx, int rec_comp,
+                           const double *res, double *grad_lam, double *grad_mu, double *grad_b);
+
 int or_acoustic_adjoint_pml(const or_grid *g, const or_pml *pml, double dt, int nsteps,
                             const double *vp, const double *rho, int nsrc, const or_source *src,
                             int nrec, const int *rec_idx, const double *res, double *grad_K);
