@@ -238,8 +238,9 @@ loss_status loss_deriv_static(loss_sim *sim, int32_t axis, int32_t order, const 
  * the standard adjoint-state one).  loss_forward_ckpt resets, runs nsteps (<= trace_len) steps
  * from rest recording traces and keeping the state every ckpt_every steps in device
  * memory (3 fields per checkpoint acoustic, 9 elastic; with the absorbing layer the
- * acoustic checkpoint also carries its 4 memory variables, and the adjoint allocates 5
- * more fields for their bars and its operand).  loss_adjoint then takes the trace
+ * checkpoint also carries its 4 (acoustic) or 18 (elastic) memory variables, and the
+ * adjoint allocates 5 resp. 19 more fields for their bars and its operand: every pass
+ * is transposed through its layer's exact sub-flow).  loss_adjoint then takes the trace
  * residual of J = 1/2 sum residual^2, laid out like the traces of all shots concatenated (residual[shot][rec][t], t < trace_len,
  * float64; samples t >= nsteps are ignored) and returns dJ/dparam summed over shots
  * (float64).  Acoustic: param = LOSS_GRAD_K (bulk modulus K) or LOSS_GRAD_VP (c with rho
@@ -250,8 +251,8 @@ loss_status loss_deriv_static(loss_sim *sim, int32_t axis, int32_t order, const 
  * fields per step, nine with the density (6 or 9 x ckpt_every fields of device memory).  The adjoint applies the exact transpose
  * of every discrete operator of the time-stepping scheme; forward states are
  * recomputed from the checkpoints segment by segment.  Afterwards the wavefields hold
- * an intermediate state (call loss_reset).  Errors: LOSS_EUNSUPPORTED (elastic with the
- * absorbing layer, patches shorter than 2 intervals), LOSS_EINVAL (param not of the physics),
+ * an intermediate state (call loss_reset).  Errors: LOSS_EUNSUPPORTED (patches shorter
+ * than 2 intervals), LOSS_EINVAL (param not of the physics),
  * LOSS_ESTATE (no loss_forward_ckpt since the last loss_set_media or loss_set_pml: the
  * checkpoints must belong to the media and layer the adjoint runs with). */
 #define LOSS_GRAD_K    0

@@ -3,7 +3,8 @@
 // at a band node (table entry {E, phi1, A, B} of the node along the pass's axis), and
 // out += alpha coef D elsewhere.  Its transpose, given out-bar f (unchanged) and the
 // memory variable's bar m (of psi'): D-bar = B alpha coef f - A m, and m becomes the bar
-// of psi0, phi1 alpha coef f + E m.  The transposed derivative then takes D-bar.
+// of psi0, phi1 alpha coef f + E m.  The transposed derivative then takes D-bar.  A null
+// coef stands for 1 (an operand the caller has already combined).
 #include <hip/hip_runtime.h>
 
 #include "loss_internal.h"
@@ -28,7 +29,7 @@ __global__ void k_pml_adj_operand(float *__restrict__ w, const float *__restrict
     const int64_t p = r * pitch + x;             // node within the shot (media index)
     const int64_t q = shot * per_shot + p;
     const int j = axis == 0 ? x : (axis == 1 ? (int)(r % ny) : (int)(r / ny));
-    const float c = alpha * coef[p] * f[q];
+    const float c = alpha * (coef ? coef[p] : 1.f) * f[q];
     if (j < pml_w || j > N - pml_w) {
         const float4 t = tab[j];
         const float mb = m[q];

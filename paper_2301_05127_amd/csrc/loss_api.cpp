@@ -139,6 +139,7 @@ struct loss_sim {
     float *adj[4] = {nullptr, nullptr, nullptr, nullptr};   // lambda, mu1, mu3, Y scratch
     float *adj_el[11] = {};        // elastic: the 9 field bars (field order), Y scratch, operand
     float *adj_pml[5] = {};        // acoustic with the layer: the 4 memory-variable bars, operand
+    float *adj_pml_el[19] = {};    // elastic with the layer: the 18 memory-variable bars, operand
     int ck_fields = 0;             // fields per checkpoint (the state, and the layer's variables)
     float **d_adjtab = nullptr;    // device copy of adj_el[0..8]
     double *grad_pad = nullptr, *grad_dense = nullptr, *res_dev = nullptr;
@@ -650,9 +651,12 @@ loss_status stress_stage(loss_sim *s, float *div_store, int64_t div_shot_stride)
                                   s->st));
     }
     if (div_store) {
+        // e33 as the pass below will see it: with the layer, the stretched derivative from
+        // the current memory variable, which this evaluation leaves unchanged
         LineArgs a = base_args(s, 2);
         a.in = F[LOSS_F_EV3];
         a.out[0] = div_store + 2 * fe;
+        set_pml(s, a, 2, 9 + 8, 1.f, false);
         if ((r = run_line(s, KC_STRESS_Z, 2, SOLVE_D1, EPI_STORE, a))) return r;
     }
     {
@@ -1293,6 +1297,16 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
                               mem == LOSS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->st));
     for (int k = 0; k < 9; ++k)
         if (launch_fill(s->adj_el[k], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    // with the layer: the bars of its 18 memory variables (0..8 psi_ij of the velocity
+    // passes d_j sigma_ij, 9..17 phi_ij of the stress passes d_j v_i, numbered 3i + j as
+    // in the forward), zero after the last step, and the operand of each pass
+    const bool layer = s->pml_mem != nullptr;
+    if (layer) {
+        for (int k = 0; k < 19; ++k)
+            if (!s->adj_pml_el[k] && (r = s->alloc(&s->adj_pml_el[k], fe))) return r;
+        for (int k = 0; k < 18; ++k)
+            if (launch_fill(s->adj_pml_el[k], fe, 0.f, s->st) != hipSuccess) return fail(LOSS_EHIP, "fill");
+    }
     HIPCHK(hipMemsetAsync(s->grad_pad, 0, sizeof(double) * 3 * ss, s->st));
     double *gb = s->grad_pad + 2 * ss;
     float *const *A = s->adj_el;
@@ -1314,12 +1328,29 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
         if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
         return timed_end(s, KC_RECEIVER);
     };
+    // one transposed pass: target += D_axis^T (coef fbar), through the layer's flow of the
+    // pass's memory variable mv when there is one (its bar updated in place)
+    auto pass_t = [&](int axis, const float *fbar, const float *coef, int mv, float *target) -> loss_status {
+        if (!layer) return adj_deriv(s, axis, fbar, coef, target, 1.f, EPI_AXPY, Y, S);
+        loss_status q = timed_begin(s);
+        if (q) return q;
+        float *Wl = s->adj_pml_el[18];
+        const hipError_t e = launch_pml_adj_operand(Wl, fbar, coef, 1.f, s->adj_pml_el[mv], s->pml_tab[axis], axis,
+                                                    s->pml_w, (int)s->d.n[axis], s->nx, s->ny, s->pitch, ss, S, s->st);
+        if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+        if ((q = timed_end(s, KC_GRAD))) return q;
+        return adj_deriv(s, axis, Wl, nullptr, target, 1.f, EPI_AXPY, Y, S);
+    };
     for (int64_t c = s->ck_nseg - 1; c >= 0; --c) {
         const int64_t n0 = c * s->ck_every, nc = std::min(s->ck_every, s->ck_steps - n0);
-        // restore the fused state at step n0 and recompute the segment, keeping the strains
+        // restore the fused state at step n0 (with the layer's memory variables) and
+        // recompute the segment, keeping the strains
         for (int k = 0; k < s->nf; ++k)
             HIPCHK(hipMemcpyAsync(s->f[k], s->ckpt + (c * s->ck_fields + k) * fe, sizeof(float) * fe,
                                   hipMemcpyDeviceToDevice, s->st));
+        if (layer)
+            HIPCHK(hipMemcpyAsync(s->pml_mem, s->ckpt + (c * s->ck_fields + s->nf) * fe,
+                                  sizeof(float) * s->npml * fe, hipMemcpyDeviceToDevice, s->st));
         HIPCHK(launch_set_step(s->d_step, n0, s->st));
         s->fused = true;
         if ((r = steps_eager(s, nc, s->divstore, ss))) return r;
@@ -1341,7 +1372,7 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
             }
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j)
-                    if ((r = adj_deriv(s, j, A[LOSS_F_EV1 + i], b, A[sidx[i][j]], 1.f, EPI_AXPY, Y, S))) return r;
+                    if ((r = pass_t(j, A[LOSS_F_EV1 + i], b, 3 * i + j, A[sidx[i][j]]))) return r;
             if ((r = inject_res(false, n, 1.f))) return r;
             if ((r = inject_res(true, n, 0.5f))) return r;
             const float *strain[6];
@@ -1355,12 +1386,12 @@ loss_status elastic_adjoint(loss_sim *s, const double *residual, int32_t param, 
                 e = launch_el_normal_operand(Wop, A[LOSS_F_S11], A[LOSS_F_S22], A[LOSS_F_S33], l2m, lam, kk, s->nx,
                                              s->pitch, ss, S, s->st);
                 if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
-                if ((r = adj_deriv(s, kk, Wop, nullptr, A[LOSS_F_EV1 + kk], 1.f, EPI_AXPY, Y, S))) return r;
+                if ((r = pass_t(kk, Wop, nullptr, 9 + 4 * kk, A[LOSS_F_EV1 + kk]))) return r;
             }
             for (int q = 0; q < 3; ++q) {
                 const int sij = sh[q][0], i = sh[q][1], j = sh[q][2];
-                if ((r = adj_deriv(s, j, A[sij], mu, A[LOSS_F_EV1 + i], 1.f, EPI_AXPY, Y, S))) return r;
-                if ((r = adj_deriv(s, i, A[sij], mu, A[LOSS_F_EV1 + j], 1.f, EPI_AXPY, Y, S))) return r;
+                if ((r = pass_t(j, A[sij], mu, 9 + 3 * i + j, A[LOSS_F_EV1 + i]))) return r;
+                if ((r = pass_t(i, A[sij], mu, 9 + 3 * j + i, A[LOSS_F_EV1 + j]))) return r;
             }
         }
     }
@@ -1999,8 +2030,6 @@ loss_status loss_forward_ckpt(loss_sim *s, int64_t nsteps, int64_t ckpt_every)
 {
     if (!s) return fail(LOSS_EINVAL, "null argument");
     if (nsteps < 1 || ckpt_every < 1) return fail(LOSS_EINVAL, "nsteps and ckpt_every must be >= 1");
-    if (s->pml_mem && s->d.physics != LOSS_ACOUSTIC)
-        return fail(LOSS_EUNSUPPORTED, "the elastic adjoint is built without the absorbing layer");
     for (int a = 0; a < 3; ++a)
         if (!(a == 1 && s->d.ndim == 2) && s->d.patch[a] < 2)
             return fail(LOSS_EUNSUPPORTED, "the adjoint needs patches of at least 2 intervals");
@@ -2040,10 +2069,7 @@ loss_status loss_adjoint(loss_sim *s, const double *residual, int32_t param, dou
         return fail(LOSS_ESTATE, "loss_forward_ckpt must run first (and again after loss_set_media or loss_set_pml)");
     if ((s->pml_mem != nullptr) != (s->ck_fields > s->nf))
         return fail(LOSS_ESTATE, "the checkpoints were taken with a different absorbing layer");
-    if (s->d.physics == LOSS_ELASTIC) {
-        if (s->pml_mem) return fail(LOSS_EUNSUPPORTED, "the elastic adjoint is built without the absorbing layer");
-        return elastic_adjoint(s, residual, param, grad, mem);
-    }
+    if (s->d.physics == LOSS_ELASTIC) return elastic_adjoint(s, residual, param, grad, mem);
     if (param != LOSS_GRAD_K && param != LOSS_GRAD_VP) return fail(LOSS_EINVAL, "unknown gradient parameter");
     loss_status r;
     const int64_t fe = field_elems(s), S = s->S, ss = s->shot_stride;

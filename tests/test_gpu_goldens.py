@@ -44,6 +44,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # None skips a check
 CASES = {
     "cfg3": ("cfg3", {400: (None, None, 1e-5)}),
+    "cfg4": ("cfg4", {100: (1e-5, 1e-5, 1e-5)}),
 }
 
 
