@@ -92,17 +92,23 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
     float w[C];
     const bool has_icf = a.in_coef != nullptr;    // uniform
     const float *__restrict__ icf = a.in_coef + mbase;
-    float we = x_unit<C, SOLVE>(
-        ax, k, G, l, true, [&](int i) { return has_icf ? in[i] * icf[i] : in[i]; },
-        [&](int i) {
-            float4 v = ld4(in + i);
-            if (has_icf) {
-                const float4 c = ld4(icf + i);
-                v = make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
-            }
-            return v;
-        },
-        issue, w);
+    auto val = [&](int i) { return has_icf ? in[i] * icf[i] : in[i]; };
+    auto val4 = [&](int i) {
+        float4 v = ld4(in + i);
+        if (has_icf) {
+            const float4 c = ld4(icf + i);
+            v = make_float4(v.x * c.x, v.y * c.y, v.z * c.z, v.w * c.w);
+        }
+        return v;
+    };
+    // whole patches of 16 lanes (one DPP row each) take the unmasked solve; the choice is
+    // per unit, the same in every kernel that solves x units, so that a unit's bits do not
+    // depend on the kernel (a wave of whole units runs that path alone)
+    float we;
+    if (G == 16 && M == 16 * C && (l + 1) * M <= N)
+        we = x_unit<C, SOLVE, true>(ax, k, G, l, true, val, val4, issue, w);
+    else
+        we = x_unit<C, SOLVE, false>(ax, k, G, l, true, val, val4, issue, w);
 
     if (uact) {
         const int kc = (e - 1 - s) / C;
@@ -169,8 +175,11 @@ __global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__
         }
     };
     float w[C];
-    float we = x_unit<C, SOLVE_D1>(
-        ax, k, G, l, true, [&](int i) { return in[i]; }, [&](int i) { return ld4(in + i); }, issue, w);
+    const bool full16 = G == 16 && M == 16 * C && (l + 1) * M <= N;   // as in k_line_x
+    auto gval = [&](int i) { return in[i]; };
+    auto gval4 = [&](int i) { return ld4(in + i); };
+    float we = full16 ? x_unit<C, SOLVE_D1, true>(ax, k, G, l, true, gval, gval4, issue, w)
+                      : x_unit<C, SOLVE_D1, false>(ax, k, G, l, true, gval, gval4, issue, w);
     if (uact) {
         if (a.pml_mem) {
             pml_run<C>(ax, a.pml_tab, a.pml_mem, 1, q, e, base + q, 1, w);
@@ -204,8 +213,11 @@ __global__ void __launch_bounds__(512) k_line_xx(LineArgs a, float *__restrict__
     __syncthreads();
 
     // ---- stress pass: T = d v1 / dx from the line in LDS ------------------------
-    we = x_unit<C, SOLVE_D1>(
-        ax, k, G, l, true, [&](int i) { return line_s[i]; }, [&](int i) { return lds4[i >> 2]; }, [] {}, w);
+    auto lval = [&](int i) { return line_s[i]; };
+    auto lval4 = [&](int i) { return lds4[i >> 2]; };
+    auto none = [] {};
+    we = full16 ? x_unit<C, SOLVE_D1, true>(ax, k, G, l, true, lval, lval4, none, w)
+                : x_unit<C, SOLVE_D1, false>(ax, k, G, l, true, lval, lval4, none, w);
     if (uact) {
         float *__restrict__ T = Tout + base;
         if (pml_t) {

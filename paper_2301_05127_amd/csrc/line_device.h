@@ -453,6 +453,20 @@ __device__ __forceinline__ float row_shift_down(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + D, 0xF, 0xF, true));
 }
+// Row shifts whose lanes with a source outside the 16-lane row receive `fill` (DPP with
+// the destination disabled for those lanes, its initial value kept).
+template <int D>
+__device__ __forceinline__ float row_shift_up_fill(float v, float fill)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x110 + D, 0xF, 0xF, false));
+}
+template <int D>
+__device__ __forceinline__ float row_shift_down_fill(float v, float fill)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x100 + D, 0xF, 0xF, false));
+}
 struct UnitLanes {
     int G;
     template <int D>
@@ -479,21 +493,32 @@ struct UnitLanes {
 // the unit's loads are issued (the caller's epilogue prefetch goes there).  On return
 // w[c] holds the derivative at node q + c for q + c < e; the function returns the
 // derivative at the closing row e (the same value in every lane of the unit).
-template <int C, int SOLVE, typename Val, typename Val4, typename Issue>
+// FULL16: the caller guarantees G = 16 and a whole unit (e - s = M = 16 C, so the
+// closing row follows the last lane's last node); the lane exchanges are then row shifts
+// that bring in the identity map from outside the unit, with no masks, and the closing
+// lane is known.
+template <int C, int SOLVE, bool FULL16 = false, typename Val, typename Val4, typename Issue>
 __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, bool vec_in, Val val, Val4 val4,
                                         Issue issue, float (&w)[C])
 {
+    if constexpr (FULL16) G = 16;
     const int N = ax.N, M = ax.M;
     const int s = l * M;
-    const int e = min(s + M, N);
+    const int e = FULL16 ? s + 16 * C : min(s + M, N);
     const int q = s + k * C;
     const UnitLanes lanes{G};
+    using I = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    using I8 = std::integral_constant<int, 8>;
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
 
     // ---- loads -------------------------------------------------------------
     // chunk values u[1..C] = nodes q..q+C-1; u[0], u[C+1] = the neighbouring lanes'
     // edge nodes
     float u[C + 2];
-    if (vec_in && ((q & 3) == 0) && q + C - 1 <= N) {
+    if (FULL16 || (vec_in && ((q & 3) == 0) && q + C - 1 <= N)) {
 #pragma unroll
         for (int g4 = 0; g4 < C / 4; ++g4) {
             const float4 v = val4(q + 4 * g4);
@@ -548,20 +573,28 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
         u[C + 1] = (k == G - 1) ? uright : right;
     }
     if constexpr (SOLVE != SOLVE_T1) {
-        // suffix sums over the unit's lanes: lane 0 ends with both junction sums
-        auto suffix = [&](auto dc) {
-            constexpr int D = decltype(dc)::value;
-            if (D < G) {
-                const float a = lanes.down<D>(phs), b = lanes.down<D>(phe);
-                if (k + D < G) { phs += a; phe += b; }
-            }
-        };
-        suffix(std::integral_constant<int, 1>{});
-        suffix(std::integral_constant<int, 2>{});
-        suffix(std::integral_constant<int, 4>{});
-        suffix(std::integral_constant<int, 8>{});
-        suffix(std::integral_constant<int, 16>{});
-        suffix(std::integral_constant<int, 32>{});
+        if constexpr (FULL16) {
+            // the start junction's sum to lane 0 (suffix sums), the end junction's to the
+            // closing lane 15 (prefix sums); sources outside the row bring in 0
+            auto step = [&](auto dc) {
+                constexpr int D = decltype(dc)::value;
+                phs += row_shift_down_fill<D>(phs, 0.f);
+                phe += row_shift_up_fill<D>(phe, 0.f);
+            };
+            step(I{}); step(I2{}); step(I4{}); step(I8{});
+        } else {
+            // the same sums and order: suffix sums to lane 0 for the start junction,
+            // prefix sums to the last lane for the end junction
+            auto step = [&](auto dc) {
+                constexpr int D = decltype(dc)::value;
+                if (D < G) {
+                    const float a = lanes.down<D>(phs), b = lanes.up<D>(phe);
+                    if (k + D < G) phs += a;
+                    if (k >= D) phe += b;
+                }
+            };
+            step(I{}); step(I2{}); step(I4{}); step(I8{}); step(I16{}); step(I32{});
+        }
     }
 
     // forward elimination over the chunk from a zero carry
@@ -585,41 +618,51 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
     if (k == 0) { B = fmaf(A, phs, B); A = 0.f; }
     auto scan_up = [&](auto dc) {
         constexpr int D = decltype(dc)::value;
-        if (D < G && D * C < reach) {
-            const float Ap = lanes.up<D>(A), Bp = lanes.up<D>(B);
-            if (k >= D) { B = fmaf(A, Bp, B); A = A * Ap; }
+        if constexpr (FULL16) {
+            // lanes with no lane D back take the identity map (A 1, B 0)
+            if (D < 16 && D * C < reach) {
+                const float Ap = row_shift_up_fill<D < 16 ? D : 1>(A, 1.f);
+                const float Bp = row_shift_up_fill<D < 16 ? D : 1>(B, 0.f);
+                B = fmaf(A, Bp, B);
+                A = A * Ap;
+            }
+        } else {
+            if (D < G && D * C < reach) {
+                const float Ap = lanes.up<D>(A), Bp = lanes.up<D>(B);
+                if (k >= D) { B = fmaf(A, Bp, B); A = A * Ap; }
+            }
         }
     };
-    scan_up(std::integral_constant<int, 1>{});
-    scan_up(std::integral_constant<int, 2>{});
-    scan_up(std::integral_constant<int, 4>{});
-    scan_up(std::integral_constant<int, 8>{});
-    scan_up(std::integral_constant<int, 16>{});
-    scan_up(std::integral_constant<int, 32>{});
+    scan_up(I{}); scan_up(I2{}); scan_up(I4{}); scan_up(I8{}); scan_up(I16{}); scan_up(I32{});
     float yin = lanes.up<1>(B);
     if (k == 0) yin = phs;
 #pragma unroll
     for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
 
-    // closing row (its junction sum comes from lane 0)
-    const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
+    // closing row (its junction sum is the unit's end-junction sum)
     float we = 0.f;
-    if constexpr (SOLVE != SOLVE_T1) phe = __shfl(phe, 0, G);
-    if (k == kc) {
-        float ylast = 0.f, ulast = 0.f, ue = 0.f;
+    if constexpr (FULL16) {
+        if (k == 15) we = last_row<SOLVE>(ax, er, y[C - 1], u[C], u[C + 1], phe);
+        we = __shfl(we, 15, 16);
+    } else {
+        const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
+        if constexpr (SOLVE != SOLVE_T1) phe = __shfl(phe, G - 1, G);
+        if (k == kc) {
+            float ylast = 0.f, ulast = 0.f, ue = 0.f;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
-        we = last_row<SOLVE>(ax, er, ylast, ulast, ue, phe);
+            for (int c = 0; c < C; ++c)
+                if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
+            we = last_row<SOLVE>(ax, er, ylast, ulast, ue, phe);
+        }
+        we = __shfl(we, kc, G);
     }
-    we = __shfl(we, kc, G);
 
     // back substitution
     float Q[C];
     float wv = 0.f, qv = 1.f;
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
-        if (q + c < e) {
+        if (FULL16 || q + c < e) {
             wv = fmaf(-fs[c], wv, y[c]) * fi[c];
             qv = -fs[c] * fi[c] * qv;
         }
@@ -629,19 +672,30 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
     float Qm = qv, Wm = wv;
     auto scan_down = [&](auto dc) {
         constexpr int D = decltype(dc)::value;
-        if (D < G && D * C < reach) {
-            const float Qn = lanes.down<D>(Qm), Wn = lanes.down<D>(Wm);
-            if (k + D < G) { Wm = fmaf(Qm, Wn, Wm); Qm = Qm * Qn; }
+        if constexpr (FULL16) {
+            if (D < 16 && D * C < reach) {
+                const float Qn = row_shift_down_fill<D < 16 ? D : 1>(Qm, 1.f);
+                const float Wn = row_shift_down_fill<D < 16 ? D : 1>(Wm, 0.f);
+                Wm = fmaf(Qm, Wn, Wm);
+                Qm = Qm * Qn;
+            }
+        } else {
+            if (D < G && D * C < reach) {
+                const float Qn = lanes.down<D>(Qm), Wn = lanes.down<D>(Wm);
+                if (k + D < G) { Wm = fmaf(Qm, Wn, Wm); Qm = Qm * Qn; }
+            }
         }
     };
-    scan_down(std::integral_constant<int, 1>{});
-    scan_down(std::integral_constant<int, 2>{});
-    scan_down(std::integral_constant<int, 4>{});
-    scan_down(std::integral_constant<int, 8>{});
-    scan_down(std::integral_constant<int, 16>{});
-    scan_down(std::integral_constant<int, 32>{});
-    float Qx = lanes.down<1>(Qm), Wx = lanes.down<1>(Wm);
-    if (k == G - 1) { Qx = 1.f; Wx = 0.f; }
+    scan_down(I{}); scan_down(I2{}); scan_down(I4{}); scan_down(I8{}); scan_down(I16{}); scan_down(I32{});
+    float Qx, Wx;
+    if constexpr (FULL16) {
+        Qx = row_shift_down_fill<1>(Qm, 1.f);   // the last lane takes the identity map
+        Wx = row_shift_down_fill<1>(Wm, 0.f);
+    } else {
+        Qx = lanes.down<1>(Qm);
+        Wx = lanes.down<1>(Wm);
+        if (k == G - 1) { Qx = 1.f; Wx = 0.f; }
+    }
     // lanes past the closing row hold identity maps, so the closing value enters
     // exactly where the window reaches it (elsewhere its factor is below the tolerance)
     const float wr = fmaf(Qx, we, Wx);
