@@ -12,9 +12,16 @@ on a lattice of every ``stride``-th node at the stored steps:
 * ``cfg4``: 513^3 nodes, layered medium, patches of 64, halo 12, explosive shot; 100
   steps, lattice of every 32nd node at step 100.
 
-Each check is the relative L2 error of the FP32 GPU run against the FP64 oracle: over the
-whole lattice, over the lattice nodes at least one lattice spacing from every grid end,
-and over the traces of the receivers outside any layer, up to the stored step.
+Each check is the L2 error of the FP32 GPU run against the FP64 oracle: over the whole
+lattice and over the lattice nodes at least one lattice spacing from every grid end, both
+relative to the largest lattice norm of the stored steps so far (with the layer the field
+is absorbed: on the 257^3 workload it falls from 9.7e-9 at step 400 to 3.3e-13 at step
+1000, and an error relative to what remains would measure FP32 rounding against a
+residue), and over the traces of the receivers outside any layer, relative to the traces,
+up to the stored step.  At step 1000 of the layer case the GPU is 6e-7 of that norm from
+the oracle inside and 1.1e-5 on the whole lattice: the difference sits on the outermost
+nodes, inside the layer at the natural ends, where the corner growth described below is
+damped but not removed; hence the bound of 2e-5 there.
 
 With natural ends alone, FP32-sized perturbations grow exponentially at the grid corners
 of a 3-D elastic run: on 65^3 nodes (c_P 3000 m/s, h 10 m, dt 1 ms) by about four times
@@ -44,6 +51,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # None skips a check
 CASES = {
     "cfg3": ("cfg3", {400: (None, None, 1e-5)}),
+    "cfg3_pml": ("cfg3", {400: (1e-5, 1e-5, 1e-5), 1000: (2e-5, 1e-5, 1e-5)}),
     "cfg4": ("cfg4", {100: (1e-5, 1e-5, 1e-5)}),
 }
 
@@ -77,6 +85,8 @@ def test_full_length_against_oracle_goldens(name):
         n = w["grid"]["n"]
         keep = np.all([(r[:, a] >= width) & (r[:, a] <= n[a] - width) for a in range(3)], axis=0)
     done, rows = 0, []
+    peak = np.zeros(S)
+    inner_sl = (slice(None),) + (slice(1, -1),) * 3
     for snap in sorted(checks):
         sim.step(snap - done)
         done = snap
@@ -85,11 +95,12 @@ def test_full_length_against_oracle_goldens(name):
             whole = inner = 0.0
             if checks[snap][0] is not None or checks[snap][1] is not None:
                 ref = g["fields_s%d_n%d" % (s, snap)]
+                peak[s] = max(peak[s], np.linalg.norm(ref))
                 got = np.stack([sim.get_field(f, shot=s)[::st, ::st, ::st] for f in range(9)]).astype(np.float64)
-                whole = rel_l2(got, ref)
-                inner = rel_l2(got[:, 1:-1, 1:-1, 1:-1], ref[:, 1:-1, 1:-1, 1:-1])
+                whole = float(np.linalg.norm(got - ref) / peak[s])
+                inner = float(np.linalg.norm(got[inner_sl] - ref[inner_sl]) / peak[s])
             rows.append((snap, s, whole, inner, tr))
-            print("%s step %4d shot %d: lattice %.2e  interior %.2e  traces %.2e (%d receivers)"
+            print("%s step %4d shot %d: lattice %.2e  interior %.2e (of the largest lattice norm)  traces %.2e (%d receivers)"
                   % (name, snap, s, whole, inner, tr, keep.sum()), flush=True)
     sim.close()
     for snap, s, whole, inner, tr in rows:
