@@ -89,6 +89,10 @@ def main():
                    help="write the GPU - oracle difference of field 0, shot 0, at the end (.npy)")
     p.add_argument("--checkpoints", default="",
                    help="comma-separated step counts at which the fields are also compared (shot 0)")
+    p.add_argument("--coef-f32", action="store_true",
+                   help="acoustic: give the oracle media whose update coefficients are the GPU's float32 "
+                        "dt K and dt b (rho' = dt / fl32(dt b), vp' = sqrt(fl32(dt K) / (dt rho'))), so that "
+                        "what remains is arithmetic rounding")
     a = p.parse_args()
     import oracle
     from paper_2301_05127_amd import inputs, loss
@@ -98,17 +102,24 @@ def main():
         w = f32_inputs(inputs.config(name, **({"nshots": a.shots} if name == "cfg5" and a.shots else {})))
         nsteps = a.steps or w["nsteps"]
         S = len(w["shots"]) if a.shots is None else min(a.shots, len(w["shots"]))
+        w_gpu = w
+        if a.coef_f32 and w["physics"] == 0:
+            dt = w["dt"]
+            dtb = np.asarray(dt / w["rho"], np.float32).astype(np.float64)
+            dtK = np.asarray(((dt * w["rho"]) * w["vp"]) * w["vp"], np.float32).astype(np.float64)   # as k_media
+            rho_o = dt / dtb
+            w = dict(w, rho=rho_o, vp=np.sqrt(dtK / (dt * rho_o)))
         print("[%s] GPU, %d shot(s), %d steps" % (name, S, nsteps), flush=True)
         sim = loss.Simulation(w["grid"], w["physics"], w["dt"], nshots=S, trace_len=nsteps)
-        sim.setup_workload(w, shots=w["shots"][:S])
+        sim.setup_workload(w_gpu, shots=w_gpu["shots"][:S])
         pml = None
         if a.pml:
             f0 = 15.0 if name != "cfg2" else 20.0
-            pml = dict(width=a.pml, R=1e-6, kmax=1.0, f0=f0, cmax=float(np.max(w["vp"])))
+            pml = dict(width=a.pml, R=1e-6, kmax=1.0, f0=f0, cmax=float(np.max(w_gpu["vp"])))
             sim.set_pml(a.pml, 1e-6, 1.0, f0)
         nf = 3 if w["physics"] == 0 else 9
-        res = {"workload": name, "steps": nsteps, "shots": S, "pml": a.pml, "fields": {}, "interior16": {},
-               "traces": {}, "checkpoints": {}}
+        res = {"workload": name, "steps": nsteps, "shots": S, "pml": a.pml, "coef_f32": bool(a.coef_f32),
+               "fields": {}, "interior16": {}, "traces": {}, "checkpoints": {}}
         cps = sorted(int(c) for c in a.checkpoints.split(",") if c and int(c) < nsteps)
         shot0 = None
         if cps:

@@ -91,8 +91,12 @@ def test_plane_schedule_matches_oracle_and_line_passes(orc, geom):
         el[s, 9] = rel_l2(tl[s], rt)
     np.set_printoptions(precision=2)
     print("rel-L2 vs the FP64 oracle per field (9 fields, traces), plane then line passes:\n", eo, "\n", el)
-    assert eo.max() < 2e-5, eo
-    assert el.max() < 2e-5, el
+    # the paper's end stencil (end mode 1) makes the operator strongly non-normal: its
+    # transient growth amplifies FP32 differences (1.4e-5 here); the other closures stay
+    # below 7e-6
+    tol = 2e-5 if end == 1 else 1e-5
+    assert eo.max() < tol, eo
+    assert el.max() < tol, el
 
 
 def test_plane_graph_and_eager_bitwise_equal():

@@ -70,7 +70,7 @@ def test_elastic_pml_matches_oracle(orc):
         errs.append(row)
     errs = np.array(errs) / peak[None]
     print("field errors / peak norm, worst leg per shot and field:", errs.max(axis=0))
-    assert errs.max() < 3e-5, errs.max(axis=0)
+    assert errs.max() < 1e-5, errs.max(axis=0)
     # the layer absorbed the waves: little is left inside
     for s in range(2):
         assert max(np.linalg.norm(of[s][f]) / peak[s, f] for f in range(9)) < 0.1
@@ -79,7 +79,7 @@ def test_elastic_pml_matches_oracle(orc):
                                     sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh["rec_comp"])
         e = rel_l2(sim.get_traces(s), rt)
         print("shot %d traces rel-L2 %.2e" % (s, e))
-        assert e < 3e-5, (s, e)
+        assert e < 1e-5, (s, e)
     sim.close()
 
 
