@@ -286,6 +286,16 @@ loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
  * schedule where it applies, 1 line passes).  LOSS_EINVAL for any other value. */
 loss_status loss_set_shape(loss_sim *sim, int32_t axis, int32_t shape);
 
+/* Energy of the wavefield of every shot at the state's time (velocities at the same
+ * integer time as loss_get_field returns them): the kinetic energy 1/2 rho |v|^2 plus the
+ * strain energy 1/2 sigma : C^-1 : sigma of the velocity-stress system (Sec. 2; elastic,
+ * isotropic: s:s / (4 mu) + (tr sigma)^2 / (18 K) with s the stress deviator and
+ * K = lambda + 2 mu / 3; acoustic: sigma^2 / (2 K)), summed over the nodes times the cell
+ * volume (h_x h_y h_z, or h_x h_z in 2-D).  Reduced on the device in FP64 in a fixed order
+ * (repeated calls give the same bits).  energy: host array of nshots doubles.  Blocks until
+ * done.  Errors: LOSS_EINVAL (null argument), LOSS_ESTATE (no media yet), LOSS_EHIP. */
+loss_status loss_energy(loss_sim *sim, double *energy);
+
 /* Wait for all work queued on the sim stream; LOSS_EUNSTABLE if the non-finite sentinel
  * (see loss_step) has fired. */
 loss_status loss_sync(loss_sim *sim);

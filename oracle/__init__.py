@@ -399,6 +399,39 @@ def elastic_adjoint_pml(g, pml, dt, nsteps, vp, vs, rho, sources, receivers, rec
     return (gl, gm, gb) if with_b else (gl, gm)
 
 
+def energy(g, physics, fields, vp, rho, vs=None):
+    """Wavefield energy (the velocity-stress system of Sec. 2): the sum over the nodes of
+    1/2 rho |v|^2 + 1/2 sigma . epsilon, epsilon = C^-1 sigma, times the cell volume.
+    fields: acoustic (sigma, v1, v3), elastic (v1, v2, v3, s11, s22, s33, s12, s13, s23),
+    each of the grid's shape.  The strain is found by solving the isotropic stiffness
+    system in Voigt form (normal rows lambda + 2 mu on the diagonal, lambda off it; shear
+    rows mu acting on the engineering strain 2 eps_ij) at every node; acoustic: sigma / K.
+    Plain FP64 numpy."""
+    f = _f64(fields)
+    rho = _f64(rho)
+    vp = _f64(vp)
+    gg = _grid(g)
+    cell = gg.h[0] * gg.h[2] * (gg.h[1] if gg.ndim == 3 else 1.0)
+    if physics == 0:
+        K = rho * vp ** 2
+        e = 0.5 * rho * (f[1] ** 2 + f[2] ** 2) + 0.5 * f[0] ** 2 / K
+        return float(np.sum(e) * cell)
+    vs = _f64(vs)
+    mu = rho * vs ** 2
+    lam = rho * vp ** 2 - 2.0 * mu
+    n = rho.size
+    C = np.zeros((n, 6, 6))
+    for i in range(3):
+        for j in range(3):
+            C[:, i, j] = lam.ravel() + (2.0 * mu.ravel() if i == j else 0.0)
+        C[:, 3 + i, 3 + i] = mu.ravel()
+    sig = np.stack([f[3 + k].ravel() for k in range(6)], axis=1)        # s11 s22 s33 s12 s13 s23
+    strain = np.linalg.solve(C, sig[:, :, None])[:, :, 0]               # eps11..33, 2 eps12..
+    e = 0.5 * rho.ravel() * (f[0].ravel() ** 2 + f[1].ravel() ** 2 + f[2].ravel() ** 2) \
+        + 0.5 * np.sum(sig * strain, axis=1)
+    return float(np.sum(e) * cell)
+
+
 def rel_l2(x, ref):
     x = np.asarray(x, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)

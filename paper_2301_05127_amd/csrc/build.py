@@ -18,7 +18,8 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libloss.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "libloss")
-SOURCES = ["kernels.hip", "plane_xy.hip", "adjoint_elastic.hip", "adjoint_layer.hip", "tables.cpp", "loss_api.cpp"]
+SOURCES = ["kernels.hip", "plane_xy.hip", "adjoint_elastic.hip", "adjoint_layer.hip", "energy.hip", "tables.cpp",
+           "loss_api.cpp"]
 ARCH = os.environ.get("LOSS_OFFLOAD_ARCH", "gfx950")
 
 

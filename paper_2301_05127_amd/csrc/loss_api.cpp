@@ -145,6 +145,7 @@ struct loss_sim {
     double *grad_pad = nullptr, *grad_dense = nullptr, *res_dev = nullptr;
     float *d_vp = nullptr, *d_rho = nullptr;   // dense copies of the media for the gradient map
     float *d_vs = nullptr;
+    double *energy_buf = nullptr;  // loss_energy: block partials [S][1024], then one value per shot
     double cmax = 0.0;                         // largest velocity of the media
     // absorbing layer: memory variables, each laid out like a field (acoustic: psi_x,
     // psi_z of the velocity sub-flow, phi_x, phi_z of the stress sub-flow; elastic:
@@ -1864,6 +1865,44 @@ loss_status loss_deriv_static(loss_sim *s, int32_t axis, int32_t order, const fl
         e = launch_pad_copy(pout, out + b0 * dense, s->nx, (int)(nb * s->ny * s->nz), s->pitch, 0, s->st);
         if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
     }
+    return LOSS_OK;
+}
+
+loss_status loss_energy(loss_sim *s, double *energy)
+{
+    if (!s || !energy) return fail(LOSS_EINVAL, "null argument");
+    if (!s->d_rho) return fail(LOSS_ESTATE, "loss_set_media must run first");
+    std::vector<float *> v;
+    loss_status r = unfused_velocity(s, v);   // the velocity at the state's integer time
+    if (r) return r;
+    EnergyArgs a{};
+    const bool el = s->d.physics == LOSS_ELASTIC;
+    a.nv = el ? 3 : 2;
+    for (int c = 0; c < a.nv; ++c) a.v[c] = v[c];
+    if (el) {
+        a.ns = 6;
+        for (int c = 0; c < 6; ++c) a.s[c] = s->f[LOSS_F_S11 + c];
+    } else {
+        a.ns = 1;
+        a.s[0] = s->f[LOSS_F_SIGMA];
+    }
+    a.vp = s->d_vp;
+    a.vs = s->d_vs;
+    a.rho = s->d_rho;
+    a.nx = s->nx;
+    a.pitch = s->pitch;
+    a.shot_stride = s->shot_stride;
+    a.nodes = s->nodes;
+    const int nblocks = 1024;
+    if (!s->energy_buf && (r = s->alloc(&s->energy_buf, (size_t)(s->S * nblocks + s->S)))) return r;
+    double cell = s->d.h[0] * s->d.h[2];
+    if (el) cell *= s->d.h[1];
+    const hipError_t e = launch_energy(a, (int)s->S, s->energy_buf, nblocks, cell, s->energy_buf + s->S * nblocks,
+                                       s->st);
+    if (e != hipSuccess) return fail(LOSS_EHIP, hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(energy, s->energy_buf + s->S * nblocks, sizeof(double) * s->S, hipMemcpyDeviceToHost,
+                          s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
     return LOSS_OK;
 }
 

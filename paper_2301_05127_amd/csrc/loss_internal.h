@@ -279,6 +279,18 @@ hipError_t launch_grad_accum(double *g, const float *lam, const float *div, floa
 hipError_t launch_grad_unpad(const double *gp, double *g, int nx, int rows, int64_t pitch, const float *vp,
                              const float *rho, int param, hipStream_t st);
 hipError_t launch_nonfinite(const float *p, int64_t n, int *flag, hipStream_t st);
+// Wavefield energy of each shot (energy.hip): velocity and stress fields (padded layout,
+// shot_stride apart), the dense media vp, vs (elastic only), rho.
+struct EnergyArgs {
+    const float *v[3];
+    const float *s[6];
+    int nv, ns;               // acoustic 2, 1 (sigma); elastic 3, 6 (s11 s22 s33 s12 s13 s23)
+    const float *vp, *vs, *rho;
+    int nx;
+    int64_t pitch, shot_stride, nodes;
+};
+hipError_t launch_energy(const EnergyArgs &a, int S, double *partial, int nblocks, double cell, double *out,
+                         hipStream_t st);
 
 
 }  // namespace loss

@@ -29,7 +29,7 @@ GRAD_K, GRAD_VP, GRAD_LAME, GRAD_VPVS, GRAD_LAME_RHO, GRAD_VPVS_RHO = 0, 1, 2, 3
 EXPORTS = [
     "loss_create", "loss_destroy", "loss_set_media", "loss_add_source", "loss_add_receivers",
     "loss_reset", "loss_step", "loss_get_field", "loss_set_field", "loss_get_traces", "loss_deriv",
-    "loss_forward_ckpt", "loss_adjoint", "loss_sync", "loss_set_timing", "loss_kernel_timing",
+    "loss_forward_ckpt", "loss_adjoint", "loss_sync", "loss_energy", "loss_set_timing", "loss_kernel_timing",
     "loss_current_step", "loss_status_str", "loss_last_error", "loss_autotune",
     "loss_autotune_choice", "loss_set_shape", "loss_set_pml", "loss_deriv_static",
 ]
@@ -79,6 +79,7 @@ def lib():
         "loss_forward_ckpt": (I32, [P, I64, I64]),
         "loss_adjoint": (I32, [P, P, I32, P, I32]),
         "loss_sync": (I32, [P]),
+        "loss_energy": (I32, [P, P]),
         "loss_set_timing": (I32, [P, I32]),
         "loss_kernel_timing": (I32, [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64),
                                      ctypes.POINTER(ctypes.c_char_p)]),
@@ -217,6 +218,12 @@ class Simulation:
 
     def sync(self):
         _check(lib().loss_sync(self._h))
+
+    def energy(self):
+        """Wavefield energy of every shot at the state's time (FP64, reduced on the device)."""
+        out = np.zeros(self.nshots, dtype=np.float64)
+        _check(lib().loss_energy(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     @property
     def current_step(self):
