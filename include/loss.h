@@ -266,9 +266,10 @@ loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, d
                          int32_t mem);
 
 /* Autotune the launch shape of the line kernels: along x the nodes per lane (4, 8 or
- * 16); along y and z the columns per wave (16, 32 or 64 x-columns; the rest of the
- * wave's lanes take further chunks of the same lines) and the nodes per lane (8 or
- * 16); each candidate timed over `trial_steps` steps, the fastest kept.  Elastic grids
+ * 16) and, where every patch fills 16 lanes and the patches of a line come in fours, the
+ * lines a wave solves in turn (1, 4, 8 or automatic); along y and z the columns per
+ * wave (16, 32 or 64 x-columns; the rest of the wave's lanes take further chunks of the
+ * same lines) and the nodes per lane (8 or 16); each candidate timed over `trial_steps` steps, the fastest kept.  Elastic grids
  * that admit the plane schedule (LOSS_FLAG_LINE_PASSES) have it timed against the line
  * passes and the faster one kept.  A shape or schedule changes only how the carries of
  * the scan are grouped and the order in which derivative terms are summed
@@ -276,14 +277,17 @@ loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, d
  * afterwards. */
 loss_status loss_autotune(loss_sim *sim, int32_t trial_steps);
 
-/* The launch shape in use along `axis`: nodes per lane for x; for y and z,
+/* The launch shape in use along `axis`: for x, 100 * lines per wave + nodes per lane
+ * (lines per wave 0 = automatic: 16, 8, 4 or 2 where the kernel applies, as long as
+ * that leaves 8192 waves; 1 = one unit per lane group); for y and z,
  * 100 * columns per wave + nodes per lane (0 = automatic choice); axis 3: the elastic
  * schedule in use (0 plane passes, 1 line passes). */
 loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
 
 /* Set the launch shape along `axis` in the encoding of loss_autotune_choice
- * (x: 4, 8 or 16; y/z: 100 * {8, 16, 32, 64} + {8, 16}; 0 = automatic; axis 3: 0 plane
- * schedule where it applies, 1 line passes).  LOSS_EINVAL for any other value. */
+ * (x: 100 * {0, 1, 2, 4, 8, 16} + {4, 8, 16}; y/z: 100 * {8, 16, 32, 64} + {8, 16};
+ * 0 = automatic; axis 3: 0 plane schedule where it applies, 1 line passes).  LOSS_EINVAL
+ * for any other value. */
 loss_status loss_set_shape(loss_sim *sim, int32_t axis, int32_t shape);
 
 /* Energy of the wavefield of every shot at the state's time (velocities at the same

@@ -133,6 +133,98 @@ __global__ void __launch_bounds__(256) k_line_x(LineArgs a, int G, int nunits)
     }
 }
 
+// x pass over whole units of 16 lanes (M = 16 C, N a multiple of M, p a multiple of the
+// four units of a wave): a wave solves the same four patches on `lpw` consecutive lines
+// (of any shots), so the patch's row factors, end rows, tap coefficients and tap nodes
+// are read once per wave, and the line, its shot and its media row are wave-uniform.
+// The next line's loads are issued before the current line is solved.  The same
+// arithmetic as k_line_x (whose units take the same unmasked solve), so the bits agree.
+template <int C, int SOLVE, int EPI>
+__global__ void __launch_bounds__(256) k_line_xl(LineArgs a, int lpw, int nwaves)
+{
+    const AxisDev &ax = a.ax;
+    const int lane = threadIdx.x & 63;
+    const int k = lane & 15;
+    const int N = ax.N, p = ax.p;
+    const int lps = a.nz * a.ny;
+    const int64_t nlines = (int64_t)a.S * lps;
+    const int w = (int)(blockIdx.x * (blockDim.x >> 6)) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (a.step_inc && blockIdx.x == 0 && threadIdx.x == 0) *a.step_inc += 1;
+    if (w >= nwaves) return;
+    const int bpl = p >> 2;                      // four-unit blocks per line
+    const int g = w / bpl;                       // line group (wave-uniform)
+    const int l = (w - g * bpl) * 4 + (lane >> 4);
+    const int64_t L0 = (int64_t)g * lpw;
+    const int nl = (int)min((int64_t)lpw, nlines - L0);
+    const XFix<C, SOLVE> f = x_fix<C, SOLVE, true>(ax, k, 16, l);
+    const int q = f.q, e = f.e;
+    const int pitch = (int)a.pitch;
+    int shot = (int)(L0 / lps);
+    int rl = (int)(L0 - (int64_t)shot * lps);
+    const bool has_icf = a.in_coef != nullptr;
+
+    // the loads of line L (row rl of its shot): node values and epilogue operands
+    struct LineLoads {
+        XVals<C> v;
+        Pre4 pre[C / 4];
+    };
+    auto load = [&](int64_t L, int r) {
+        const float *__restrict__ in = a.in + L * pitch;
+        const float *__restrict__ icf = a.in_coef + (int64_t)r * pitch;
+        auto val = [&](int i) { return has_icf ? in[i] * icf[i] : in[i]; };
+        auto val4 = [&](int i) {
+            float4 x = ld4(in + i);
+            if (has_icf) {
+                const float4 c = ld4(icf + i);
+                x = make_float4(x.x * c.x, x.y * c.y, x.z * c.z, x.w * c.w);
+            }
+            return x;
+        };
+        LineLoads ll;
+        x_vals_chunk<C, true>(ax, q, k, 16, true, val, val4, ll.v);
+        x_vals_taps<C, SOLVE, true>(ax, f, k, 16, val, ll.v);
+#pragma unroll
+        for (int g4 = 0; g4 < C / 4; ++g4)
+            ll.pre[g4] = pre_load4<EPI>(a, L * pitch + q + 4 * g4, (int64_t)r * pitch + q + 4 * g4);
+        return ll;
+    };
+    LineLoads cur = load(L0, rl);
+    for (int i = 0; i < nl; ++i) {
+        const int64_t L = L0 + i;
+        const int64_t base = L * pitch;
+        const int64_t mbase = (int64_t)rl * pitch;
+        int rn = rl + 1, sn = shot;                  // the next line's row and shot
+        if (rn == lps) { rn = 0; ++sn; }
+        LineLoads nxt;
+        if (i + 1 < nl) nxt = load(L + 1, rn);
+        const float *__restrict__ in = a.in + base;
+        const float *__restrict__ icf = a.in_coef + mbase;
+        auto val = [&](int j) { return has_icf ? in[j] * icf[j] : in[j]; };
+        float wv[C];
+        float we = x_solve<C, SOLVE, true>(ax, f, cur.v, k, 16, val, wv);
+        int rowz = 0, rowy = 0;
+        bool srcs = false;
+        if (a.src) {
+            rowz = rl / a.ny;
+            rowy = rl - rowz * a.ny;
+            srcs = segment_has_source(a, shot, 0, 0, rowy, rowz, q, min(q + C, N));
+        }
+        if (a.pml_mem) {
+            pml_run<C>(ax, a.pml_tab, a.pml_mem, a.pml_store, q, e, base + q, 1, wv);
+            if (e == N && k == 15 && in_pml(ax, N)) we = pml_adjust(a.pml_tab, a.pml_mem, a.pml_store, N, base + N, we);
+        }
+#pragma unroll
+        for (int g4 = 0; g4 < C / 4; ++g4)
+            epilogue4<EPI>(a, base + q + 4 * g4, mbase + q + 4 * g4, shot,
+                           make_float4(wv[4 * g4], wv[4 * g4 + 1], wv[4 * g4 + 2], wv[4 * g4 + 3]), cur.pre[g4],
+                           q + 4 * g4, rowy, rowz, srcs);
+        if (e == N && k == 15) epilogue<EPI>(a, base + N, mbase + N, shot, we, N, rowy, rowz, srcs);
+        if (i + 1 < nl) cur = nxt;
+        rl = rn;
+        shot = sn;
+    }
+}
+
 // Velocity pass along x of one step fused with the stress pass along x of the next
 // (acoustic, no body forces): v1 += alpha * coef0 * d(in)/dx, then Tout = d v1/dx of
 // the updated v1.  One block holds every patch of one line (p*G lanes), so the
@@ -1016,6 +1108,33 @@ hipError_t dispatch_x(int epi, const LineArgs &a, hipStream_t st)
     const int64_t nunits = lines * a.ax.p;
     if (nunits >= (1ll << 31)) return hipErrorInvalidValue;
     const int threads = 256;
+    // whole units of 16 lanes, four per wave on every line: the multi-line kernel, with
+    // the caller's lines per wave, else (automatic) the most of 16, 8, 4, 2 that still
+    // gives 8192 waves (32 per CU)
+    const int bpl = a.ax.p / 4;
+    if (a.xl != 1 && G == 16 && M == 16 * C && a.ax.N % M == 0 && a.ax.p % 4 == 0) {
+        int xl = a.xl;
+        if (xl == 0) {
+            xl = 16;
+            while (xl > 1 && (lines + xl - 1) / xl * bpl < 8192) xl >>= 1;
+        }
+        if (xl > 1) {
+            const int64_t nwaves = (lines + xl - 1) / xl * bpl;
+            if (nwaves >= (1ll << 31)) return hipErrorInvalidValue;
+            const unsigned bl = nblk(nwaves, threads / 64);
+            const int nw = (int)nwaves;
+            switch (epi) {
+            case EPI_STORE: hipLaunchKernelGGL((k_line_xl<C, SOLVE, EPI_STORE>), bl, threads, 0, st, a, xl, nw); break;
+            case EPI_AXPY: hipLaunchKernelGGL((k_line_xl<C, SOLVE, EPI_AXPY>), bl, threads, 0, st, a, xl, nw); break;
+            case EPI_AXPY_AUX:
+                hipLaunchKernelGGL((k_line_xl<C, SOLVE, EPI_AXPY_AUX>), bl, threads, 0, st, a, xl, nw);
+                break;
+            case EPI_BASE: hipLaunchKernelGGL((k_line_xl<C, SOLVE, EPI_BASE>), bl, threads, 0, st, a, xl, nw); break;
+            default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
+    }
     const int64_t units_per_block = (threads / 64) * (64 / G);
     const unsigned blocks = nblk(nunits, (int)units_per_block);
     const int nu = (int)nunits;

@@ -704,5 +704,281 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
     return we;
 }
 
+// The solve of x_unit in three parts, for kernels that solve the same patches on many
+// lines: XFix holds what depends only on the patch and the lane (row factors, end rows,
+// PMBC tap coefficients and tap nodes), XVals the node values of one line (the lane's
+// chunk and the node past the unit, x_vals_chunk; the tap values, x_vals_taps), and
+// x_solve is x_unit's elimination from there on, operation for operation (the fields of
+// the two forms are compared bit for bit), with `val` serving taps past the first two of
+// a lane.
+template <int C, int SOLVE>
+struct XFix {
+    int s, e, q, ss, se;
+    float fm[C], fi[C], fs[C];
+    EndRows er;
+    float tcs[2], tce[2];   // coefficients of taps k and k + G of rows s and e
+    int ns[2], ne[2];       // their nodes
+};
+
+template <int C>
+struct XVals {
+    float u[C + 2];         // u[1..C] = nodes q..q+C-1 (u[0], u[C+1] filled by the solve)
+    float uright;           // the node past the unit's last chunk (its last lane)
+    float tvs[2], tve[2];   // values at the tap nodes
+};
+
+template <int C, int SOLVE, bool FULL16 = false>
+__device__ __forceinline__ XFix<C, SOLVE> x_fix(const AxisDev &ax, int k, int G, int l)
+{
+    if constexpr (FULL16) G = 16;
+    XFix<C, SOLVE> f;
+    const int N = ax.N, M = ax.M;
+    f.s = l * M;
+    f.e = FULL16 ? f.s + 16 * C : min(f.s + M, N);
+    f.q = f.s + k * C;
+    row_factors<C, SOLVE>(ax, f.q, f.fm, f.fi, f.fs);
+    f.er = end_rows<SOLVE>(ax, f.s, f.e);
+    // PMBC taps of rows s and e, shared by the G lanes of the unit: taps k and k+G
+    // of this lane (the products are selected in the solve)
+    const int nt = ax.ntap;
+    f.ss = slot_first(ax, l);
+    f.se = slot_last(ax, l, f.e);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        f.tcs[h] = f.tce[h] = 0.f;
+        f.ns[h] = f.ne[h] = 0;
+    }
+    if constexpr (SOLVE != SOLVE_T1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 0 || G < nt) {
+                const int t = min(k + h * G, nt - 1);
+                f.tcs[h] = ax.tap_c[max(f.ss, 0) * nt + t];
+                f.tce[h] = ax.tap_c[max(f.se, 0) * nt + t];
+                f.ns[h] = tap_node(ax, f.s, t);
+                f.ne[h] = tap_node(ax, f.e, t);
+            }
+        }
+    }
+    return f;
+}
+
+// the lane's chunk u[1..C] and, on the unit's last lane, the node past the unit
+template <int C, bool FULL16 = false, typename Val, typename Val4>
+__device__ __forceinline__ void x_vals_chunk(const AxisDev &ax, int q, int k, int G, bool vec_in, Val val, Val4 val4,
+                                             XVals<C> &v)
+{
+    if constexpr (FULL16) G = 16;
+    const int N = ax.N;
+    if (FULL16 || (vec_in && ((q & 3) == 0) && q + C - 1 <= N)) {
+#pragma unroll
+        for (int g4 = 0; g4 < C / 4; ++g4) {
+            const float4 x = val4(q + 4 * g4);
+            v.u[1 + 4 * g4] = x.x; v.u[2 + 4 * g4] = x.y; v.u[3 + 4 * g4] = x.z; v.u[4 + 4 * g4] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int c = 1; c <= C; ++c) v.u[c] = val(min(q - 1 + c, N));
+    }
+    v.u[0] = v.u[C + 1] = 0.f;
+    v.uright = 0.f;
+    if (k == G - 1) v.uright = val(min(q + C, N));
+}
+
+// the values at the lane's tap nodes
+template <int C, int SOLVE, bool FULL16 = false, typename Val>
+__device__ __forceinline__ void x_vals_taps(const AxisDev &ax, const XFix<C, SOLVE> &f, int k, int G, Val val,
+                                            XVals<C> &v)
+{
+    if constexpr (FULL16) G = 16;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) v.tvs[h] = v.tve[h] = 0.f;
+    if constexpr (SOLVE != SOLVE_T1) {
+        const int nt = ax.ntap;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 0 || G < nt) {
+                v.tvs[h] = val(f.ns[h]);
+                v.tve[h] = val(f.ne[h]);
+            }
+        }
+    }
+}
+
+// `val` serves the taps past the first two of each lane (halos wider than 2G - 1 nodes)
+template <int C, int SOLVE, bool FULL16 = false, typename Val>
+__device__ __forceinline__ float x_solve(const AxisDev &ax, const XFix<C, SOLVE> &f, XVals<C> &v, int k, int G,
+                                         Val val, float (&w)[C])
+{
+    if constexpr (FULL16) G = 16;
+    const int s = f.s, e = f.e, q = f.q;
+    float(&u)[C + 2] = v.u;
+    const UnitLanes lanes{G};
+    using I = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    using I8 = std::integral_constant<int, 8>;
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
+    float fm[C], fi[C], fs[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) { fm[c] = f.fm[c]; fi[c] = f.fi[c]; fs[c] = f.fs[c]; }
+    const EndRows &er = f.er;
+    const int ss = f.ss, se = f.se;
+
+    float phs = 0.f, phe = 0.f;
+    if constexpr (SOLVE != SOLVE_T1) {
+        const int nt = ax.ntap;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool ok = k + h * G < nt;
+            if (ss >= 0 && ok) phs = fmaf(f.tcs[h], v.tvs[h], phs);
+            if (se >= 0 && ok) phe = fmaf(f.tce[h], v.tve[h], phe);
+        }
+        for (int t = k + 2 * G; t < nt; t += G) {   // halos wider than two taps per lane
+            if (ss >= 0) phs = fmaf(ax.tap_c[ss * nt + t], val(tap_node(ax, s, t)), phs);
+            if (se >= 0) phe = fmaf(ax.tap_c[se * nt + t], val(tap_node(ax, e, t)), phe);
+        }
+    }
+
+    // ---- solve -------------------------------------------------------------
+    {
+        const float left = lanes.up<1>(u[C]);
+        const float right = lanes.down<1>(u[1]);
+        u[0] = (k == 0) ? u[1] : left;   // row s never uses node s-1
+        u[C + 1] = (k == G - 1) ? v.uright : right;
+    }
+    if constexpr (SOLVE != SOLVE_T1) {
+        if constexpr (FULL16) {
+            // the start junction's sum to lane 0 (suffix sums), the end junction's to the
+            // closing lane 15 (prefix sums); sources outside the row bring in 0
+            auto step = [&](auto dc) {
+                constexpr int D = decltype(dc)::value;
+                phs += row_shift_down_fill<D>(phs, 0.f);
+                phe += row_shift_up_fill<D>(phe, 0.f);
+            };
+            step(I{}); step(I2{}); step(I4{}); step(I8{});
+        } else {
+            // the same sums and order: suffix sums to lane 0 for the start junction,
+            // prefix sums to the last lane for the end junction
+            auto step = [&](auto dc) {
+                constexpr int D = decltype(dc)::value;
+                if (D < G) {
+                    const float a = lanes.down<D>(phs), b = lanes.up<D>(phe);
+                    if (k + D < G) phs += a;
+                    if (k >= D) phe += b;
+                }
+            };
+            step(I{}); step(I2{}); step(I4{}); step(I8{}); step(I16{}); step(I32{});
+        }
+    }
+
+    // forward elimination over the chunk from a zero carry
+    float y[C], P[C];   // eliminated rhs, carry factor
+    float yv = 0.f, pv = 1.f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float r = interior_rhs<SOLVE>(ax, u[c], u[c + 1], u[c + 2]);
+        if constexpr (SOLVE != SOLVE_T1) {
+            if (c == 0 && k == 0) r = first_row<SOLVE>(ax, er, u[1], u[2], fm[0], fi[0], fs[0]);
+        }
+        yv = fmaf(-fm[c], yv, r);
+        pv = -fm[c] * pv;
+        y[c] = yv;
+        P[c] = pv;
+    }
+    // compose the forward carries of the lanes within reach (inclusive scan of
+    // affine maps); the first lane's carry is the junction slope
+    const int reach = ax.reach;
+    float A = pv, B = yv;
+    if (k == 0) { B = fmaf(A, phs, B); A = 0.f; }
+    auto scan_up = [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if constexpr (FULL16) {
+            // lanes with no lane D back take the identity map (A 1, B 0)
+            if (D < 16 && D * C < reach) {
+                const float Ap = row_shift_up_fill<D < 16 ? D : 1>(A, 1.f);
+                const float Bp = row_shift_up_fill<D < 16 ? D : 1>(B, 0.f);
+                B = fmaf(A, Bp, B);
+                A = A * Ap;
+            }
+        } else {
+            if (D < G && D * C < reach) {
+                const float Ap = lanes.up<D>(A), Bp = lanes.up<D>(B);
+                if (k >= D) { B = fmaf(A, Bp, B); A = A * Ap; }
+            }
+        }
+    };
+    scan_up(I{}); scan_up(I2{}); scan_up(I4{}); scan_up(I8{}); scan_up(I16{}); scan_up(I32{});
+    float yin = lanes.up<1>(B);
+    if (k == 0) yin = phs;
+#pragma unroll
+    for (int c = 0; c < C; ++c) y[c] = fmaf(P[c], yin, y[c]);
+
+    // closing row (its junction sum is the unit's end-junction sum)
+    float we = 0.f;
+    if constexpr (FULL16) {
+        if (k == 15) we = last_row<SOLVE>(ax, er, y[C - 1], u[C], u[C + 1], phe);
+        we = __shfl(we, 15, 16);
+    } else {
+        const int kc = (e - 1 - s) / C, cc = (e - 1 - s) - kc * C;
+        if constexpr (SOLVE != SOLVE_T1) phe = __shfl(phe, G - 1, G);
+        if (k == kc) {
+            float ylast = 0.f, ulast = 0.f, ue = 0.f;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (c == cc) { ylast = y[c]; ulast = u[c + 1]; ue = u[c + 2]; }
+            we = last_row<SOLVE>(ax, er, ylast, ulast, ue, phe);
+        }
+        we = __shfl(we, kc, G);
+    }
+
+    // back substitution
+    float Q[C];
+    float wv = 0.f, qv = 1.f;
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        if (FULL16 || q + c < e) {
+            wv = fmaf(-fs[c], wv, y[c]) * fi[c];
+            qv = -fs[c] * fi[c] * qv;
+        }
+        w[c] = wv;
+        Q[c] = qv;
+    }
+    float Qm = qv, Wm = wv;
+    auto scan_down = [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if constexpr (FULL16) {
+            if (D < 16 && D * C < reach) {
+                const float Qn = row_shift_down_fill<D < 16 ? D : 1>(Qm, 1.f);
+                const float Wn = row_shift_down_fill<D < 16 ? D : 1>(Wm, 0.f);
+                Wm = fmaf(Qm, Wn, Wm);
+                Qm = Qm * Qn;
+            }
+        } else {
+            if (D < G && D * C < reach) {
+                const float Qn = lanes.down<D>(Qm), Wn = lanes.down<D>(Wm);
+                if (k + D < G) { Wm = fmaf(Qm, Wn, Wm); Qm = Qm * Qn; }
+            }
+        }
+    };
+    scan_down(I{}); scan_down(I2{}); scan_down(I4{}); scan_down(I8{}); scan_down(I16{}); scan_down(I32{});
+    float Qx, Wx;
+    if constexpr (FULL16) {
+        Qx = row_shift_down_fill<1>(Qm, 1.f);   // the last lane takes the identity map
+        Wx = row_shift_down_fill<1>(Wm, 0.f);
+    } else {
+        Qx = lanes.down<1>(Qm);
+        Wx = lanes.down<1>(Wm);
+        if (k == G - 1) { Qx = 1.f; Wx = 0.f; }
+    }
+    // lanes past the closing row hold identity maps, so the closing value enters
+    // exactly where the window reaches it (elsewhere its factor is below the tolerance)
+    const float wr = fmaf(Qx, we, Wx);
+#pragma unroll
+    for (int c = 0; c < C; ++c) w[c] = fmaf(Q[c], wr, w[c]);
+    return we;
+}
+
 }  // namespace
 }  // namespace loss

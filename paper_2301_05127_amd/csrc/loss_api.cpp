@@ -84,6 +84,7 @@ struct loss_sim {
     int *d_src_begin = nullptr;    // [S+1]
     int cw[3] = {0, 0, 0};         // strided-kernel columns per wave per axis (0 = automatic)
     int cx = 0;                    // x-kernel nodes per lane (0 = automatic)
+    int xl = 0;                    // x-kernel lines per wave over whole units (1: one; 0 = automatic)
     int cs[3] = {0, 0, 0};         // strided-kernel nodes per lane per axis (0 = automatic)
     int nsrc = 0;
     bool pending_inc = false;      // next line kernel advances the step counter
@@ -190,6 +191,7 @@ LineArgs base_args(const loss_sim *s, int axis)
     a.nout = 1;
     a.cw = s->cw[axis];
     a.cx = s->cx;
+    a.xl = s->xl;
     a.cs = s->cs[axis];
     return a;
 }
@@ -1970,21 +1972,22 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     };
     // launch shapes of the line kernels along `axis`, the fastest kept; returns its time
     auto tune_axis = [&](int axis, float &best) -> loss_status {
-        // candidates: x -> nodes per lane; y, z -> (columns per wave, nodes per lane)
+        // candidates: x -> (nodes per lane, lines per wave); y, z -> (columns per wave,
+        // nodes per lane)
         std::vector<std::pair<int, int>> cands;
-        if (axis == 0) cands = {{4, 0}, {8, 0}, {16, 0}};
+        if (axis == 0) cands = {{4, 0}, {4, 1}, {8, 0}, {16, 0}, {4, 4}, {4, 8}};
         else cands = {{64, 8}, {64, 16}, {32, 16}, {16, 16}, {32, 8}, {16, 8}};
         best = 1e30f;
         std::pair<int, int> bestc = cands[0];
         for (const auto &cd : cands) {
-            if (axis == 0) s->cx = cd.first;
+            if (axis == 0) { s->cx = cd.first; s->xl = cd.second; }
             else { s->cw[axis] = cd.first; s->cs[axis] = cd.second; }
             float ms = 0.f;
             loss_status q = trial(ms);
             if (q) return q;
             if (ms < best) { best = ms; bestc = cd; }
         }
-        if (axis == 0) s->cx = bestc.first;
+        if (axis == 0) { s->cx = bestc.first; s->xl = bestc.second; }
         else { s->cw[axis] = bestc.first; s->cs[axis] = bestc.second; }
         return LOSS_OK;
     };
@@ -2041,8 +2044,11 @@ loss_status loss_set_shape(loss_sim *s, int32_t axis, int32_t shape)
     }
     if (!s || axis < 0 || axis > 2 || (axis == 1 && s->d.ndim == 2)) return fail(LOSS_EINVAL, "bad axis");
     if (axis == 0) {
-        if (shape != 0 && shape != 4 && shape != 8 && shape != 16) return fail(LOSS_EINVAL, "bad x shape");
-        s->cx = shape;
+        const int cx = shape % 100, xl = shape / 100;
+        if (shape != 0 && !((cx == 4 || cx == 8 || cx == 16) && (xl == 0 || xl == 1 || xl == 2 || xl == 4 || xl == 8 || xl == 16)))
+            return fail(LOSS_EINVAL, "bad x shape");
+        s->cx = cx;
+        s->xl = xl;
     } else {
         const int cw = shape / 100, cs = shape % 100;
         if (shape != 0 && !((cw == 8 || cw == 16 || cw == 32 || cw == 64) && (cs == 8 || cs == 16)))
@@ -2061,7 +2067,7 @@ loss_status loss_autotune_choice(loss_sim *s, int32_t axis, int32_t *cw)
         *cw = plane_ok(s) ? 0 : 1;
         return LOSS_OK;
     }
-    *cw = axis == 0 ? s->cx : s->cw[axis] * 100 + s->cs[axis];
+    *cw = axis == 0 ? s->xl * 100 + s->cx : s->cw[axis] * 100 + s->cs[axis];
     return LOSS_OK;
 }
 

@@ -141,6 +141,8 @@ struct LineArgs {
     int out_field[3];
     int cw;                // strided kernels: columns per wave (16, 32, 64; 0 = automatic)
     int cx;                // x kernel: nodes per lane (4, 8, 16; 0 = automatic)
+    int xl;                // x kernel: lines per wave over whole 16-lane units (2-16; 1: one unit per lane
+                           // group; 0 = automatic)
     int cs;                // y/z kernels: nodes per lane (8 or 16; 0 = automatic)
     // receivers of out[0] recorded by the strided kernel as its update lands (trace
     // sample *d_step - 1): per flattened column {first, count, min row, max row} into

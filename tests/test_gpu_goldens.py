@@ -1,16 +1,20 @@
-"""Full-length GPU parity of the elastic workloads against stored FP64 oracle runs.
+"""Full-length GPU parity of the elastic workloads and the large acoustic workload against
+stored FP64 oracle runs.
 
 The goldens (``tests/golden/<name>_oracle.npz``) were written by
 ``tests/golden/make_goldens.py``, which calls only the oracle on the float32
 inputs the GPU receives.  They hold every receiver trace of each shot and all nine fields
-on a lattice of every ``stride``-th node at the stored steps:
+(three in 2-D) on a lattice of every ``stride``-th node at the stored steps:
 
 * ``cfg3``: 257^3 nodes, patches of 64, halo 10, natural ends, explosive and
   vertical-force shots in one batch; 1000 steps, lattice of every 16th node at steps 400
   and 1000;
 * ``cfg3_pml``: the same with the absorbing layer (Sec. 3.3) 20 nodes wide on every side;
 * ``cfg4``: 513^3 nodes, layered medium, patches of 64, halo 12, explosive shot; 100
-  steps, lattice of every 32nd node at step 100.
+  steps, lattice of every 32nd node at step 100;
+* ``cfg2_pml``: 2049^2 acoustic nodes, Gaussian random velocity, patches of 256, halo 12,
+  a 50-node absorbing layer; 2000 steps, lattice of every 32nd node at steps 500, 1000 and
+  2000 (no traces stored).
 
 Each check is the L2 error of the FP32 GPU run against the FP64 oracle: over the whole
 lattice and over the lattice nodes at least one lattice spacing from every grid end, both
@@ -53,6 +57,7 @@ CASES = {
     "cfg3": ("cfg3", {400: (None, None, 1e-5)}),
     "cfg3_pml": ("cfg3", {400: (1e-5, 1e-5, 1e-5), 1000: (2e-5, 1e-5, 1e-5)}),
     "cfg4": ("cfg4", {100: (1e-5, 1e-5, 1e-5)}),
+    "cfg2_pml": ("cfg2", {500: (1e-5, 1e-5, None), 1000: (1e-5, 1e-5, None), 2000: (1e-5, 1e-5, None)}),
 }
 
 
