@@ -548,22 +548,29 @@ __global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, 
             n = *a.d_step - 1;
             if (n >= a.trace_len) n = -1;
         }
+        // waves with no source and no receiver among their rows (nearly all of them) take
+        // the epilogue without the per-node source and receiver tests
+        auto rows_out = [&](auto plain_c) {
+            constexpr bool P = decltype(plain_c)::value;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int i = q + c;
-            if (i < e) {
-                const int r = i * stride;
-                const float D = y[c];
-                float v;
-                if constexpr (kPre)
-                    v = epilogue_pre<EPI>(la, fo + r, mo + r, shot, D, pre[c], col, axis == 1 ? i : cy,
-                                          axis == 1 ? cz : i, srcs);
-                else
-                    v = epilogue<EPI>(la, fo + r, mo + r, shot, D, col, axis == 1 ? i : cy, axis == 1 ? cz : i,
-                                      srcs);
-                if (n >= 0 && i >= rinfo.z && i <= rinfo.w) record_row(a, rinfo, i, v, n);
+            for (int c = 0; c < C; ++c) {
+                const int i = q + c;
+                if (i < e) {
+                    const int r = i * stride;
+                    const float D = y[c];
+                    float v;
+                    if constexpr (kPre)
+                        v = epilogue_pre<EPI>(la, fo + r, mo + r, shot, D, pre[c], col, axis == 1 ? i : cy,
+                                              axis == 1 ? cz : i, P ? false : srcs);
+                    else
+                        v = epilogue<EPI>(la, fo + r, mo + r, shot, D, col, axis == 1 ? i : cy,
+                                          axis == 1 ? cz : i, P ? false : srcs);
+                    if (!P && n >= 0 && i >= rinfo.z && i <= rinfo.w) record_row(a, rinfo, i, v, n);
+                }
             }
-        }
+        };
+        if (!__any(srcs || n >= 0)) rows_out(std::true_type{});
+        else rows_out(std::false_type{});
         if (e == N && chunk == kc) {
             const int r = N * stride;
             float D = we;
