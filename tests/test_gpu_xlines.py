@@ -111,3 +111,35 @@ def test_multiline_x_acoustic_and_deriv_bitwise():
     for r in res[1:]:
         for a, b in zip(r[0] + r[1] + r[2], res[0][0] + res[0][1] + res[0][2]):
             assert np.array_equal(a, b)
+
+
+def test_shape_encoding_round_trip():
+    """x shapes 100 * lines per wave + nodes per lane (lines 0 automatic, 1, 2, 4, 8, 16),
+    y/z shapes 100 * columns per wave + nodes per lane: accepted values are reported back
+    by loss_autotune_choice, the others refused with LOSS_EINVAL."""
+    require_gpu()
+    import ctypes
+    from paper_2301_05127_amd import loss
+    w = _elastic(4)
+    announce("launch shape encoding")
+    sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=1)
+    sim.set_media(w["vp"], w["rho"], w["vs"])
+
+    def choice(axis):
+        v = ctypes.c_int32()
+        assert loss.lib().loss_autotune_choice(sim._h, axis, ctypes.byref(v)) == 0
+        return v.value
+
+    for xs in (4, 8, 16, 104, 204, 404, 804, 1604, 408, 1616):
+        sim.set_shape([xs, None, None])
+        assert choice(0) == xs, xs
+    for ys in (6408, 3216, 1608, 808):
+        sim.set_shape([None, ys, ys])
+        assert choice(1) == ys and choice(2) == ys, ys
+    einval = -1   # LOSS_EINVAL
+    for bad in (2, 5, 304, 1704, 3204, 10004):
+        assert loss.lib().loss_set_shape(sim._h, 0, bad) == einval, bad
+    for bad in (6404, 6432, 4808, 16408):
+        assert loss.lib().loss_set_shape(sim._h, 1, bad) == einval, bad
+    sim.step(2)   # every accepted shape launches; the last ones set are in use
+    sim.close()
