@@ -269,7 +269,9 @@ loss_status loss_adjoint(loss_sim *sim, const double *residual, int32_t param, d
  * 16) and, where every patch fills 16 lanes and the patches of a line come in fours, the
  * lines a wave solves in turn (1, 4, 8 or automatic); along y and z the columns per
  * wave (16, 32 or 64 x-columns; the rest of the wave's lanes take further chunks of the
- * same lines) and the nodes per lane (8 or 16); each candidate timed over `trial_steps` steps, the fastest kept.  Elastic grids
+ * same lines) and the nodes per lane (8 or 16), and for elastic grids the shape of the y
+ * store passes apart (the axis's own, 64 or 32 columns with 8 nodes per lane); each
+ * candidate timed over `trial_steps` steps, the fastest kept.  Elastic grids
  * that admit the plane schedule (LOSS_FLAG_LINE_PASSES) have it timed against the line
  * passes and the faster one kept.  A shape or schedule changes only how the carries of
  * the scan are grouped and the order in which derivative terms are summed
@@ -281,13 +283,15 @@ loss_status loss_autotune(loss_sim *sim, int32_t trial_steps);
  * (lines per wave 0 = automatic: 16, 8, 4 or 2 where the kernel applies, as long as
  * that leaves 8192 waves; 1 = one unit per lane group); for y and z,
  * 100 * columns per wave + nodes per lane (0 = automatic choice); axis 3: the elastic
- * schedule in use (0 plane passes, 1 line passes). */
+ * schedule in use (0 plane passes, 1 line passes); axes 4 and 5: the shape of the y and
+ * z store passes (passes that only store a derivative), 0 when they take the axis's. */
 loss_status loss_autotune_choice(loss_sim *sim, int32_t axis, int32_t *cw);
 
 /* Set the launch shape along `axis` in the encoding of loss_autotune_choice
  * (x: 100 * {0, 1, 2, 4, 8, 16} + {4, 8, 16}; y/z: 100 * {8, 16, 32, 64} + {8, 16};
- * 0 = automatic; axis 3: 0 plane schedule where it applies, 1 line passes).  LOSS_EINVAL
- * for any other value. */
+ * 0 = automatic; axis 3: 0 plane schedule where it applies, 1 line passes; axes 4, 5:
+ * the y / z store passes, 100 * {8, 16, 32, 64} + {8, 16}, 0 = the axis's shape).
+ * LOSS_EINVAL for any other value. */
 loss_status loss_set_shape(loss_sim *sim, int32_t axis, int32_t shape);
 
 /* Energy of the wavefield of every shot at the state's time (velocities at the same

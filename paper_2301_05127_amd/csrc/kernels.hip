@@ -345,7 +345,8 @@ constexpr int kTapsPerChunk = 2;   // taps per chunk loaded ahead of the solve
 // decomposition is done once per wave.
 // Dynamic LDS: 6 * blockDim.x + 64 floats.
 template <int C, int SOLVE, int EPI, bool WIDE>
-__global__ void __launch_bounds__(1024) k_line_s(LineArgs a, int axis, int CW_, int gx_real)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(EPI == EPI_STORE && WIDE && C == 8 ? 8 : 1)))
+k_line_s(LineArgs a, int axis, int CW_, int gx_real)
 {
     extern __shared__ float lds[];
     const int nthr = blockDim.x;

@@ -85,6 +85,8 @@ struct loss_sim {
     int cw[3] = {0, 0, 0};         // strided-kernel columns per wave per axis (0 = automatic)
     int cx = 0;                    // x-kernel nodes per lane (0 = automatic)
     int xl = 0;                    // x-kernel lines per wave over whole units (1: one; 0 = automatic)
+    int cws[3] = {0, 0, 0};        // y/z store passes: columns per wave (0: the axis's shape)
+    int css[3] = {0, 0, 0};        // y/z store passes: nodes per lane
     int cs[3] = {0, 0, 0};         // strided-kernel nodes per lane per axis (0 = automatic)
     int nsrc = 0;
     bool pending_inc = false;      // next line kernel advances the step counter
@@ -252,6 +254,10 @@ loss_status run_line(loss_sim *s, int kc, int axis, int solve, int epi, const Li
     if (s->pending_inc) {
         a.step_inc = s->d_step;
         s->pending_inc = false;
+    }
+    if (epi == EPI_STORE && axis > 0 && s->cws[axis]) {   // the store passes' own shape
+        a.cw = s->cws[axis];
+        a.cs = s->css[axis];
     }
     loss_status r = timed_begin(s);
     if (r) return r;
@@ -1996,9 +2002,31 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
     // plane schedule (its line kernels run along z only); the faster schedule is kept
     const int sched0 = s->elastic_schedule;
     s->elastic_schedule = 1;
+    // elastic: the y axis is timed with its store passes held at 64 columns, then the
+    // store passes' own shape is chosen
+    if (s->d.physics == LOSS_ELASTIC) {
+        s->cws[1] = 64;
+        s->css[1] = 8;
+    }
     for (int axis = 0; axis < 3; ++axis) {
         if (axis == 1 && s->d.ndim == 2) continue;
         if ((r = tune_axis(axis, t_line))) return r;
+    }
+    // elastic: the y store passes (two of the eighteen per step) may take their own shape
+    if (s->d.physics == LOSS_ELASTIC) {
+        const std::pair<int, int> sc[] = {{0, 0}, {64, 8}, {32, 8}};
+        float best = 1e30f;
+        std::pair<int, int> bestc = sc[0];
+        for (const auto &cd : sc) {
+            s->cws[1] = cd.first;
+            s->css[1] = cd.second;
+            float ms = 0.f;
+            if ((r = trial(ms))) return r;
+            if (ms < best) { best = ms; bestc = cd; }
+        }
+        s->cws[1] = bestc.first;
+        s->css[1] = bestc.second;
+        t_line = std::min(t_line, best);
     }
     s->elastic_schedule = sched0;
     if (s->d.physics == LOSS_ELASTIC) {
@@ -2036,6 +2064,16 @@ loss_status loss_autotune(loss_sim *s, int32_t trial_steps)
 
 loss_status loss_set_shape(loss_sim *s, int32_t axis, int32_t shape)
 {
+    if (s && (axis == 4 || axis == 5)) {   // the y / z store passes
+        const int cw = shape / 100, cs = shape % 100;
+        if (shape != 0 && !((cw == 8 || cw == 16 || cw == 32 || cw == 64) && (cs == 8 || cs == 16)))
+            return fail(LOSS_EINVAL, "bad store shape");
+        if (axis == 4 && s->d.ndim == 2) return fail(LOSS_EINVAL, "bad axis");
+        s->cws[axis - 3] = cw;
+        s->css[axis - 3] = cs;
+        drop_graph(s);
+        return LOSS_OK;
+    }
     if (s && axis == 3) {
         if (shape != 0 && shape != 1) return fail(LOSS_EINVAL, "schedule must be 0 (plane) or 1 (line passes)");
         s->elastic_schedule = shape;
@@ -2062,9 +2100,13 @@ loss_status loss_set_shape(loss_sim *s, int32_t axis, int32_t shape)
 
 loss_status loss_autotune_choice(loss_sim *s, int32_t axis, int32_t *cw)
 {
-    if (!s || !cw || axis < 0 || axis > 3) return fail(LOSS_EINVAL, "bad argument");
+    if (!s || !cw || axis < 0 || axis > 5) return fail(LOSS_EINVAL, "bad argument");
     if (axis == 3) {
         *cw = plane_ok(s) ? 0 : 1;
+        return LOSS_OK;
+    }
+    if (axis > 3) {
+        *cw = s->cws[axis - 3] * 100 + s->css[axis - 3];
         return LOSS_OK;
     }
     *cw = axis == 0 ? s->xl * 100 + s->cx : s->cw[axis] * 100 + s->cs[axis];

@@ -333,10 +333,11 @@ class Simulation:
     def autotune(self, trial_steps=5):
         """Pick the fastest launch shape of the line kernels (and, elastic, the faster of
         the plane and line-pass schedules); returns the choice per axis (loss_set_shape
-        encoding), then the elastic schedule (0 plane, 1 line passes) when elastic."""
+        encoding), then, when elastic, the schedule (0 plane, 1 line passes) and the
+        shapes of the y and z store passes (0: the axis's)."""
         _check(lib().loss_autotune(self._h, int(trial_steps)))
         out = []
-        for axis in range(4 if self.physics == ELASTIC else 3):
+        for axis in range(6 if self.physics == ELASTIC else 3):
             v = ctypes.c_int32()
             _check(lib().loss_autotune_choice(self._h, axis, ctypes.byref(v)))
             out.append(v.value)
@@ -344,7 +345,8 @@ class Simulation:
 
     def set_shape(self, shapes):
         """Set the launch shape per axis (see loss_set_shape; a fourth entry is the elastic
-        schedule, 0 plane passes, 1 line passes); None entries are skipped."""
+        schedule, 0 plane passes, 1 line passes, a fifth and sixth the shapes of the y and
+        z store passes); None entries are skipped."""
         for axis, v in enumerate(shapes):
             if v is None or (axis == 1 and self.grid["ndim"] == 2):
                 continue

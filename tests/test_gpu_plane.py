@@ -120,7 +120,8 @@ def test_autotune_reports_elastic_schedule():
     sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=2, trace_len=10)
     sim.setup_workload(w)
     choice = sim.autotune(2)
-    assert len(choice) == 4 and choice[3] in (0, 1), choice
+    assert len(choice) == 6 and choice[3] in (0, 1), choice
+    assert choice[4] in (0, 6408, 3208) and choice[5] == 0, choice
     sim.step(10)
     sim.sync()
     assert sim.current_step == 10

@@ -141,5 +141,36 @@ def test_shape_encoding_round_trip():
         assert loss.lib().loss_set_shape(sim._h, 0, bad) == einval, bad
     for bad in (6404, 6432, 4808, 16408):
         assert loss.lib().loss_set_shape(sim._h, 1, bad) == einval, bad
+    for st in (6408, 3208, 1616, 0):
+        sim.set_shape([None, None, None, None, st, st])
+        assert choice(4) == st and choice(5) == st, st
+    for bad in (6404, 4808, 16408):
+        assert loss.lib().loss_set_shape(sim._h, 4, bad) == einval, bad
+    sim.set_shape([None, None, None, None, 6408, 3208])
     sim.step(2)   # every accepted shape launches; the last ones set are in use
     sim.close()
+
+
+def test_store_pass_shapes_match_oracle(orc):
+    """The y and z store passes in their own launch shape (64 columns while the other
+    passes of the axis take 32, and the reverse) against the FP64 oracle."""
+    require_gpu()
+    from paper_2301_05127_amd import loss
+    w = _elastic(30)
+    announce("store-pass shapes, elastic 257x33x17 against the oracle")
+    refs = []
+    for s in range(2):
+        sh = w["shots"][s]
+        refs.append(orc.run(w["grid"], 1, w["dt"], w["nsteps"], w["vp"], w["rho"], vs=w["vs"],
+                            sources=sh["sources"], receivers=sh["receivers"], rec_comp=sh["rec_comp"]))
+    for shape in ([404, 3208, 3208, 1, 6408, 6408], [404, 6408, 6408, 1, 3208, 3208]):
+        sim = loss.Simulation(w["grid"], 1, w["dt"], nshots=2, trace_len=w["nsteps"])
+        sim.setup_workload(w)
+        sim.set_shape(shape)
+        sim.step(w["nsteps"])
+        for s in range(2):
+            rf, rt = refs[s]
+            errs = [rel_l2(sim.get_field(c, shot=s), rf[c]) for c in range(9)]
+            et = rel_l2(sim.get_traces(s), rt)
+            assert max(errs) < 1e-5 and et < 1e-5, (shape, s, errs, et)
+        sim.close()
