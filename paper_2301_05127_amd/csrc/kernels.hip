@@ -442,8 +442,10 @@ k_line_s(LineArgs a, int axis, int CW_, int gx_real)
             tve[h] = in[fo + tap_node(ax, e, t) * stride];
         }
     }
-    // epilogue operands (small chunks only: they cost 3 registers per node)
-    constexpr bool kPre = C <= 8 && EPI != EPI_NORMAL3;
+    // epilogue operands (small chunks only: they cost 3 registers per node); the 64-column
+    // axpy with aux loads them after the solve, which keeps it at 72 VGPRs and three
+    // workgroups per CU instead of 101 and two, the faster of the two on 513^3
+    constexpr bool kPre = C <= 8 && EPI != EPI_NORMAL3 && !(WIDE && EPI == EPI_AXPY_AUX);
     Pre pre[kPre ? C : 1];
     if constexpr (kPre) {
 #pragma unroll
