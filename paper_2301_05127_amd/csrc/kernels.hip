@@ -342,10 +342,13 @@ constexpr int kTapsPerChunk = 2;   // taps per chunk loaded ahead of the solve
 // along the axis.  Chunk maps and PMBC partial sums meet in LDS: two barriers.
 // WIDE (CW = 64, one chunk per wave): the chunk index and so the factor rows are
 // wave-uniform (scalar loads, no vector registers for the factors), and the column
-// decomposition is done once per wave.
+// decomposition is done once per wave.  Register bounds (measured on 513^3): the
+// 64-column store fits 8 waves per SIMD (63 VGPRs, four workgroups per CU) and the normal
+// stresses 7 (70 VGPRs), both without spills; tighter bounds on the other epilogues spill.
 // Dynamic LDS: 6 * blockDim.x + 64 floats.
 template <int C, int SOLVE, int EPI, bool WIDE>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(EPI == EPI_STORE && WIDE && C == 8 ? 8 : 1)))
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(EPI == EPI_STORE && WIDE && C == 8 ? 8 : (EPI == EPI_NORMAL3 && WIDE && C == 8 ? 7 : 1))))
 k_line_s(LineArgs a, int axis, int CW_, int gx_real)
 {
     extern __shared__ float lds[];
