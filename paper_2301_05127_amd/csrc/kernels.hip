@@ -343,12 +343,15 @@ constexpr int kTapsPerChunk = 2;   // taps per chunk loaded ahead of the solve
 // WIDE (CW = 64, one chunk per wave): the chunk index and so the factor rows are
 // wave-uniform (scalar loads, no vector registers for the factors), and the column
 // decomposition is done once per wave.  Register bounds (measured on 513^3): the
-// 64-column store fits 8 waves per SIMD (63 VGPRs, four workgroups per CU) and the normal
-// stresses 7 (70 VGPRs), both without spills; tighter bounds on the other epilogues spill.
+// 64-column store and axpy with aux fit 8 waves per SIMD (63-64 VGPRs, four workgroups
+// per CU; the axpy spills one register) and the normal stresses 7 (70 VGPRs); tighter
+// bounds on the other epilogues spill more and run slower.
 // Dynamic LDS: 6 * blockDim.x + 64 floats.
 template <int C, int SOLVE, int EPI, bool WIDE>
 __global__ void __launch_bounds__(1024)
-__attribute__((amdgpu_waves_per_eu(EPI == EPI_STORE && WIDE && C == 8 ? 8 : (EPI == EPI_NORMAL3 && WIDE && C == 8 ? 7 : 1))))
+__attribute__((amdgpu_waves_per_eu((EPI == EPI_STORE || EPI == EPI_AXPY_AUX) && WIDE && C == 8
+                                       ? 8
+                                       : (EPI == EPI_NORMAL3 && WIDE && C == 8 ? 7 : 1))))
 k_line_s(LineArgs a, int axis, int CW_, int gx_real)
 {
     extern __shared__ float lds[];
@@ -446,8 +449,8 @@ k_line_s(LineArgs a, int axis, int CW_, int gx_real)
         }
     }
     // epilogue operands (small chunks only: they cost 3 registers per node); the 64-column
-    // axpy with aux loads them after the solve, which keeps it at 72 VGPRs and three
-    // workgroups per CU instead of 101 and two, the faster of the two on 513^3
+    // axpy with aux loads them after the solve, which lets it run four workgroups per CU
+    // (64 VGPRs) instead of two (101), the faster on 513^3
     constexpr bool kPre = C <= 8 && EPI != EPI_NORMAL3 && !(WIDE && EPI == EPI_AXPY_AUX);
     Pre pre[kPre ? C : 1];
     if constexpr (kPre) {
