@@ -710,7 +710,9 @@ __device__ __forceinline__ float x_unit(const AxisDev &ax, int k, int G, int l, 
 // chunk and the node past the unit, x_vals_chunk; the tap values, x_vals_taps), and
 // x_solve is x_unit's elimination from there on, operation for operation (the fields of
 // the two forms are compared bit for bit), with `val` serving taps past the first two of
-// a lane.
+// a lane.  x_unit keeps its single-function form: written as these three parts it
+// compiled the fused x kernel with 32-lane units (8 nodes per lane, patches of 256) a
+// fifth slower.
 template <int C, int SOLVE>
 struct XFix {
     int s, e, q, ss, se;
